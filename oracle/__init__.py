@@ -1,0 +1,172 @@
+"""CPU oracle for the block Krylov + operator action path.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only users.  The product path never imports this
+package.  It shares no code with the GPU library; both sides only share the
+seeded input generators.
+
+Everything here is plain FP64:
+
+* :func:`assemble` -- the cell-centred finite-volume heat operator as CSR
+  (paper Sec. II-A, Eq. (1) and its boundary models; divergence-form reading
+  so that A is SPD, matching the "sparse symmetric matrices" of Sec. V-A).
+* :func:`cg_many` -- unpreconditioned CG from x0 = 0, one right-hand side at a
+  time (the direct solution method of Sec. II-D; CG baseline of Sec. V-A).
+  The method's block solve reaches X = A^-1 B, which is what this computes.
+* :func:`gemm` -- T = X C by plain loops (Sec. III-B, Eq. (5), raw weights).
+* :func:`apply_many` -- F = A T by CSR products (Sec. III-C, Eq. (6)).
+* :mod:`oracle.conv_ref` -- FP64 convolution encoder-decoder forward and
+  backward for the learned initial guess.
+
+Parity pins live in ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (portable flags: the library may run on
+    another host)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        i64, i32, dbl, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+        lib.orc_nnz_bound.restype = i64
+        lib.orc_nnz_bound.argtypes = [i32, i32, i32]
+        lib.orc_assemble_csr.restype = i64
+        lib.orc_assemble_csr.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, vp, vp, vp, vp, vp]
+        lib.orc_spmv.restype = None
+        lib.orc_spmv.argtypes = [i64, vp, vp, vp, vp, vp]
+        lib.orc_cg.restype = i32
+        lib.orc_cg.argtypes = [i64, vp, vp, vp, vp, vp, dbl, i32, vp, vp]
+        lib.orc_cg_many.restype = None
+        lib.orc_cg_many.argtypes = [i64, vp, vp, vp, i32, vp, i64, vp, i64, dbl, i32, vp, vp, i32]
+        lib.orc_gemm.restype = None
+        lib.orc_gemm.argtypes = [i64, i32, i64, vp, i64, vp, i64, vp, i64, i32]
+        lib.orc_apply_many.restype = None
+        lib.orc_apply_many.argtypes = [i64, vp, vp, vp, i64, vp, i64, vp, i64, i32]
+        lib.orc_max_threads.restype = i32
+        lib.orc_max_threads.argtypes = []
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclass
+class CSR:
+    n: int
+    rowptr: np.ndarray  # int64 (n+1)
+    col: np.ndarray  # int32 (nnz)
+    val: np.ndarray  # float64 (nnz)
+
+    def to_dense(self) -> np.ndarray:
+        """Dense copy (tiny grids only)."""
+        D = np.zeros((self.n, self.n))
+        for r in range(self.n):
+            for p in range(self.rowptr[r], self.rowptr[r + 1]):
+                D[r, self.col[p]] += self.val[p]
+        return D
+
+
+def assemble(nx, ny, nz, lx, ly, lz, k, bc, h) -> CSR:
+    lib = _load()
+    n = nx * ny * nz
+    k = np.ascontiguousarray(k, dtype=np.float64).reshape(-1)
+    assert k.size == n
+    bc_a = np.ascontiguousarray(bc, dtype=np.int32)
+    h_a = np.ascontiguousarray(h, dtype=np.float64)
+    cap = lib.orc_nnz_bound(nx, ny, nz)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(cap, dtype=np.int32)
+    val = np.zeros(cap, dtype=np.float64)
+    nnz = lib.orc_assemble_csr(nx, ny, nz, lx, ly, lz, _p(k), _p(bc_a), _p(h_a), _p(rowptr), _p(col), _p(val))
+    if nnz < 0:
+        raise ValueError("bad grid")
+    return CSR(n, rowptr, col[:nnz].copy(), val[:nnz].copy())
+
+
+def assemble_chip(chip) -> CSR:
+    return assemble(chip.nx, chip.ny, chip.nz, chip.lx, chip.ly, chip.lz, chip.k, chip.bc, chip.h)
+
+
+def spmv(A: CSR, x: np.ndarray) -> np.ndarray:
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(A.n)
+    lib.orc_spmv(A.n, _p(A.rowptr), _p(A.col), _p(A.val), _p(x), _p(y))
+    return y
+
+
+def cg(A: CSR, b: np.ndarray, tol: float, maxit: int = 100000):
+    """One CG solve from x0 = 0.  Returns (x, iterations, true relative residual)."""
+    lib = _load()
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.empty(A.n)
+    rr = np.zeros(1)
+    scratch = np.empty(3 * A.n)
+    it = lib.orc_cg(A.n, _p(A.rowptr), _p(A.col), _p(A.val), _p(b), _p(x), tol, maxit, _p(rr), _p(scratch))
+    return x, int(it), float(rr[0])
+
+
+def cg_many(A: CSR, B: np.ndarray, tol: float, maxit: int = 100000, nthreads: int = 0):
+    """Independent CG per row of B (shape (s, N)).  Returns (X, iters, relres)."""
+    lib = _load()
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    s = B.shape[0]
+    X = np.empty_like(B)
+    iters = np.zeros(s, dtype=np.int32)
+    relres = np.zeros(s)
+    lib.orc_cg_many(A.n, _p(A.rowptr), _p(A.col), _p(A.val), s, _p(B), A.n, _p(X), A.n, tol, maxit,
+                    _p(iters), _p(relres), nthreads)
+    return X, iters, relres
+
+
+def gemm(X: np.ndarray, C: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """T = X C with X (s, N) and C (M, s) in the column-major convention;
+    returns T as (M, N)."""
+    lib = _load()
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    s, n = X.shape
+    m = C.shape[0]
+    assert C.shape[1] == s
+    T = np.empty((m, n))
+    lib.orc_gemm(n, s, m, _p(X), n, _p(C), s, _p(T), n, nthreads)
+    return T
+
+
+def apply_many(A: CSR, T: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """F = A T for T of shape (M, N); returns (M, N)."""
+    lib = _load()
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    m = T.shape[0]
+    F = np.empty_like(T)
+    lib.orc_apply_many(A.n, _p(A.rowptr), _p(A.col), _p(A.val), m, _p(T), A.n, _p(F), A.n, nthreads)
+    return F
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
