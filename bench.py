@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Throughput of the block Krylov + operator action path on one MI355X.
+
+One step = the whole hot path over one synthetic chip, with inputs resident
+in HBM: block solve of A X = B for s power maps (FP32 block iteration with
+FP64 Gram / factorisations / refinement to relative residual 1e-8), the
+combination T = X C into M fields (FP64), and the operator action F = A T
+(FP64).  value = M pairs / step time.
+
+Default workload: 128 x 128 x 8 stacked chip, 7-point stencil, s = 32,
+M = 5000 (the configuration the pairs/s metric is quoted on).
+
+Prints one JSON line.  Extra keys: ``roofline`` (dominant kernel, measured
+with HIP events around its launches on the launch stream), ``stencil``
+(the operator-action kernel's own roofline), ``stages`` (per-stage ms),
+``cpu_baseline`` (the CPU oracle on a bounded sample, host cores).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=1, help="workload index (0..3)")
+    ap.add_argument("--m", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-fields", type=int, default=200)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(the per-chip and per-field work shards without communication, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2510_23221_amd import capi, synth
+
+    dev = torch.device("cuda:0")
+    w = synth.workload(args.config, m=args.m)
+    chip = w.chips[0]
+    s, m, n = w.s, w.m, chip.n
+    mixed = w.scheme.startswith("mixed")
+    compute = capi.F32 if mixed else capi.F64
+    t_dtype = torch.bfloat16 if w.scheme == "mixed_bf16" else torch.float64
+    comb_compute = capi.BF16 if w.scheme == "mixed_bf16" else capi.F64
+    apply_compute = capi.F32 if w.scheme == "mixed_bf16" else capi.F64
+
+    G = capi.HeatOperator.from_chip(chip, dev)
+    B = torch.as_tensor(w.B[0], device=dev)
+    C = torch.as_tensor(w.C[0], device=dev)
+    X = torch.empty_like(B)
+    T = torch.empty((m, n), dtype=t_dtype, device=dev)
+    F = torch.empty((m, n), dtype=t_dtype, device=dev)
+    wbytes = capi.workspace_bytes(G, s, compute)
+    work = torch.empty(wbytes + 256, dtype=torch.uint8, device=dev)
+    wview = work[(-work.data_ptr()) % 256:]
+    stream = torch.cuda.current_stream()
+
+    infos = []
+
+    def step():
+        _, info = capi.block_krylov_solve(G, B, w.tol, compute=compute, X=X, work=wview)
+        capi.combine(X, C, out_dtype=t_dtype, compute=comb_compute, T=T)
+        capi.apply_operator(G, T, out_dtype=t_dtype, compute=apply_compute, F=F)
+        infos.append(info)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    capi.timing_reset()
+    capi.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    capi.timing_enable(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    fam = {f: capi.timing_query(f) for f in capi.FAMILY}
+
+    # ---- algorithmic bytes per launch of each kernel family
+    wv = 4 if mixed else 8
+    wt = 2 if t_dtype == torch.bfloat16 else 8
+    wc = 4 if apply_compute == capi.F32 else 8
+    it_total = sum(i["iters"] for i in infos[-args.steps:])
+    ref_total = sum(i["refinements"] for i in infos[-args.steps:])
+    per_launch_bytes = {
+        "apply": n * m * 2 * wt + n * 4 * wc,
+        "combine": n * m * wt + n * s * 8 + s * m * 8,
+    }
+    # inner solve product: s columns in the block storage type; the FP64
+    # residual launches (refinements + 1 per solve) move 3 passes of FP64
+    n_spmm = fam["spmm"][0]
+    spmm_bytes = n * s * 2 * wv + n * 4 * (4 if mixed else 8)
+    per_launch_bytes["spmm"] = spmm_bytes
+    per_launch_bytes["gram"] = n * s * wv * 1.5
+    per_launch_bytes["update"] = n * s * wv * 5
+    timed = {k: v for k, v in fam.items() if v[0] > 0}
+    dom = max(timed, key=lambda k: timed[k][1])
+
+    def roof(kind):
+        launches, tot = fam[kind]
+        if launches == 0 or kind not in per_launch_bytes:
+            return None
+        avg_ms = tot / launches
+        gbs = per_launch_bytes[kind] / (avg_ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kind,
+                "launches": launches, "avg_us": round(avg_ms * 1e3, 2),
+                "bytes_per_launch": int(per_launch_bytes[kind])}
+
+    roofline = roof(dom) if dom in per_launch_bytes else None
+    value = m / (ms_per_step * 1e-3)
+    res = {
+        "metric": "data pairs/s at rel residual <=1e-8 (BlocKOA: block solve + combine + operator action)",
+        "value": round(value, 1),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": list(chip.dims), "s": s, "M": m, "tol": w.tol,
+                   "scheme": w.scheme, "T_F_dtype": str(t_dtype).replace("torch.", "")},
+        "roofline": roofline,
+        "dominant_kernel": dom,
+        "stencil": roof("apply"),
+        "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in fam.items()},
+        "kernel_launches_per_step": {k: v[0] / args.steps for k, v in fam.items()},
+        "solve": {"iters_per_step": it_total / args.steps, "refinements_per_step": ref_total / args.steps,
+                  "max_rel_res": max(i["max_rel_res"] for i in infos[-args.steps:])},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_fields)
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(w, sample_fields):
+    """The CPU oracle as it stands on the host: per-column CG for the s basis
+    solves (all of them), then combination + operator action on a sample of
+    the M fields, extrapolated linearly in M (both are linear in M)."""
+    import numpy as np
+
+    import oracle
+
+    chip = w.chips[0]
+    A = oracle.assemble_chip(chip)
+    cores = oracle.max_threads()
+    t0 = time.perf_counter()
+    X, iters, rr = oracle.cg_many(A, w.B[0], w.tol)
+    t_solve = time.perf_counter() - t0
+    mm = min(sample_fields, w.m)
+    t0 = time.perf_counter()
+    T = oracle.gemm(X, w.C[0][:mm])
+    oracle.apply_many(A, T)
+    t_fields = (time.perf_counter() - t0) / mm
+    total = t_solve + t_fields * w.m
+    return {"value": round(w.m / total, 2), "unit": "pairs/s", "cores": cores, "kind": "oracle",
+            "sample": f"all {w.s} basis CG solves to rel res {w.tol:g} ({t_solve:.1f} s, mean {float(np.mean(iters)):.0f} "
+                      f"iterations) + combination and operator action on {mm} of {w.m} fields, extrapolated to M",
+            "seconds_measured": round(t_solve + t_fields * mm, 2)}
+
+
+if __name__ == "__main__":
+    main()

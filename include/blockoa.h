@@ -1,0 +1,219 @@
+/*
+ * blockoa.h -- C ABI of the MI355X (gfx950) block Krylov + operator action
+ * data path for steady IC thermal simulation.
+ *
+ * The path follows the three steps of the paper's method (Sec. III):
+ *   1. basis solutions: one shared-operator block solve A X = B for s power
+ *      maps at once (Sec. III-A, Eq. (4));
+ *   2. temperature fields T = X C, random combinations of the basis
+ *      solutions (Sec. III-B, Eq. (5));
+ *   3. operator action F = A T, recovering each field's heat source without
+ *      a solve (Sec. III-C, Eq. (6)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Arrays are DEVICE pointers unless marked "host".  Matrices are column
+ *   major with an explicit leading dimension (element (i, j) at
+ *   ptr[i + j * ld]); each column of an N x s or N x M block is one field
+ *   over the grid, flattened x-fastest, then y, then z (layer 0 bottom).
+ * - The caller owns every buffer (operator coefficients, workspace, inputs,
+ *   outputs).  The library never allocates device memory.  Handles own host
+ *   metadata only.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   Kernels run on that stream.
+ * - Every argument is validated before any launch.  Bad arguments return
+ *   BKO_EINVAL and launch nothing.  No call aborts the process and no C++
+ *   exception crosses the ABI.  The message of the last failure on the
+ *   calling thread is returned by bko_last_error().
+ * - bko_combine and bko_apply_operator are stream-asynchronous: a BKO_OK
+ *   return means the launch was accepted.  bko_assemble_heat_operator and
+ *   bko_block_krylov_solve synchronise the stream before returning.
+ *
+ * Dtype legend: BKO_F64 = IEEE double, BKO_F32 = IEEE single, BKO_BF16 =
+ * bfloat16 stored as 16-bit words (round-to-nearest-even on conversion).
+ */
+#ifndef BLOCKOA_H
+#define BLOCKOA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BKO_OK = 0,
+    BKO_EINVAL = 1,      /* bad argument; nothing launched                     */
+    BKO_ENOTSPD = 2,     /* operator not positive definite (e.g. k <= 0)       */
+    BKO_ENOCONV = 3,     /* solve hit max_iter; X holds the last iterate       */
+    BKO_EBREAKDOWN = 4,  /* every search direction deflated before tol        */
+    BKO_EHIP = 5,        /* HIP runtime error (launch / copy / sync)           */
+    BKO_ENOMEM = 6,      /* caller buffer smaller than the queried size        */
+    BKO_ENOTIMPL = 7
+} bko_status;
+
+typedef enum { BKO_F64 = 0, BKO_F32 = 1, BKO_BF16 = 2 } bko_dtype;
+
+/* Boundary face models of Sec. II-A with homogeneous data: the unknown is the
+ * temperature rise above the fixed (Dirichlet) or ambient (Robin) temperature. */
+typedef enum {
+    BKO_BC_DIRICHLET0 = 0, /* u = u0                                          */
+    BKO_BC_ADIABATIC = 1,  /* zero normal flux                                */
+    BKO_BC_ROBIN = 2       /* k du/dn + h (u - u_inf) = 0, h > 0              */
+} bko_bc_kind;
+
+typedef struct bko_operator *bko_op;
+
+typedef struct {
+    int iters;          /* inner block iterations, summed over refinements   */
+    int refinements;    /* outer FP64 true-residual corrections (>= 1)        */
+    int deflated;       /* search directions dropped as linearly dependent   */
+    int status;         /* bko_status of the solve                           */
+    double max_rel_res; /* max_j ||b_j - A x_j||_2 / ||b_j||_2, FP64, at exit */
+} bko_solve_info;
+
+/* ------------------------------------------------------------------ build */
+
+/* Library version string, e.g. "blockoa 0.1 gfx950". Static storage. */
+const char *bko_version(void);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char *bko_last_error(void);
+
+/* ------------------------------------------------------- heat operator (A) */
+
+/*
+ * Bytes the caller must provide as coefficient storage for an nx x ny x nz
+ * grid (Sec. II-B: the discretised operator A of Eq. (2)).  Storage holds
+ * the diagonal and the three forward-face couplings per cell in FP64 and an
+ * FP32 copy, each array 256-byte aligned.
+ */
+bko_status bko_operator_bytes(int nx, int ny, int nz, size_t *bytes);
+
+/*
+ * Discretise -div(k grad u) = q (Sec. II-A, Eq. (1), read in divergence form
+ * so that A is symmetric positive definite) by cell-centred finite volumes
+ * on an nx x ny x nz grid over lx x ly x lz (metres or any consistent unit):
+ *   interior face a|b along spacing d :  w = 2 k_a k_b / ((k_a + k_b) d^2)
+ *   Dirichlet-0 boundary face          :  w = 2 k_a / d^2
+ *   adiabatic boundary face            :  w = 0
+ *   Robin(h) boundary face             :  w = 1 / (d (d / (2 k_a) + 1 / h))
+ *   (A x)_a = sum_b w_ab (x_a - x_b) + sum_boundary w x_a.
+ * With nz == 1 and both z faces adiabatic the operator is the 5-point one.
+ *
+ *   k_cell_dev  device, N = nx*ny*nz doubles, conductivity per cell (> 0).
+ *   bc          host, 6 face kinds ordered -x, +x, -y, +y, -z, +z.
+ *   h           host, 6 film coefficients (read for BKO_BC_ROBIN faces, > 0).
+ *   coeff_dev   device buffer of at least bko_operator_bytes() bytes,
+ *               256-byte aligned; owned by the caller and must outlive *out.
+ *   out         receives a handle (host metadata + coeff_dev).
+ * Errors: BKO_EINVAL for bad sizes / kinds / h <= 0 on a Robin face / every
+ * face adiabatic (A singular); BKO_ENOTSPD if any k is <= 0 or not finite
+ * (checked on the device; the stream is synchronised).
+ */
+bko_status bko_assemble_heat_operator(int nx, int ny, int nz, double lx, double ly, double lz,
+                                      const double *k_cell_dev, const int bc[6], const double h[6],
+                                      void *coeff_dev, size_t coeff_bytes, void *stream,
+                                      bko_op *out);
+
+/* Grid of an operator: writes nx, ny, nz (any pointer may be NULL). */
+bko_status bko_operator_dims(bko_op A, int *nx, int *ny, int *nz);
+
+/* Free the handle (host memory only; the coefficient buffer stays the caller's). */
+bko_status bko_destroy_operator(bko_op A);
+
+/* ------------------------------------------------------ basis solutions (X) */
+
+/*
+ * Workspace bytes for bko_block_krylov_solve with s right-hand sides and the
+ * given inner compute dtype (BKO_F64 or BKO_F32).
+ */
+bko_status bko_block_krylov_workspace_bytes(bko_op A, int s, bko_dtype compute, size_t *bytes);
+
+/*
+ * Solve A X = B for s right-hand sides sharing A with one block Krylov
+ * (block conjugate gradient) iteration (Sec. III-A, Eq. (4)).
+ *
+ * The block iteration keeps an orthonormal residual basis and SPD-solved
+ * step matrices (a retooled block CG), and drops linearly dependent search
+ * directions instead of breaking down.  Around it runs an FP64 correction
+ * loop: R = B - A X is formed in FP64, the block iteration solves A D = R,
+ * X += D, until max_j ||r_j|| / ||b_j|| <= tol (the per-column relative
+ * residual norm used by the paper's tables, Sec. V).
+ *
+ *   compute = BKO_F64 : block iteration entirely in FP64.
+ *   compute = BKO_F32 : block vectors and stencil products in FP32; the s x s
+ *                       Gram matrices, their factorisations and the true
+ *                       residual stay FP64 (mixed precision with FP64
+ *                       iterative refinement).
+ *   B (n x s, ldb >= n) FP64 device, X (n x s, ldx >= n) FP64 device output.
+ *   X0 (ldx0 >= n) optional FP64 initial guess (e.g. a learned start); NULL
+ *   means X0 = 0.  X0 may alias X (ldx0 == ldx).
+ *   tol > 0, max_iter >= 1 caps the total inner iterations.
+ *   work / work_bytes: caller workspace (bko_block_krylov_workspace_bytes),
+ *   256-byte aligned, contents need not be initialised.
+ *   info (host, may be NULL) receives iteration counts and the final FP64
+ *   relative residual.
+ * Returns BKO_OK on convergence, BKO_ENOCONV if max_iter was reached (X
+ * holds the last iterate and info its residual), BKO_EBREAKDOWN if every
+ * direction deflated above tol.  Synchronises the stream.
+ */
+bko_status bko_block_krylov_solve(bko_op A, int s, const double *B, int ldb, double *X, int ldx,
+                                  const double *X0, int ldx0, bko_dtype compute, double tol,
+                                  int max_iter, void *work, size_t work_bytes,
+                                  bko_solve_info *info, void *stream);
+
+/* ------------------------------------------------- combination (T = X C) */
+
+/*
+ * T = X C: M temperature fields as combinations of s basis solutions
+ * (Sec. III-B, Eq. (5), with raw weights; normalising the weights is the
+ * caller's choice of C).  X is n x s (ldx >= n), C is s x m (ldc >= s),
+ * T is n x m (ldt >= n).  Inputs of any dtype are converted in-register to
+ * the compute dtype: BKO_F64 (FP64 matrix cores), BKO_F32 (FP32 matrix
+ * cores, FP32 accumulate) or BKO_BF16 (inputs rounded to BF16, FP32
+ * accumulate).  T is written in t_t.  Asynchronous.
+ */
+bko_status bko_combine(int n, int s, int m, const void *X, int ldx, bko_dtype x_t,
+                       const void *C, int ldc, bko_dtype c_t, void *T, int ldt, bko_dtype t_t,
+                       bko_dtype compute, void *stream);
+
+/* ----------------------------------------------- operator action (F = A T) */
+
+/*
+ * F = A T for m fields (Sec. III-C, Eq. (6)): one matrix-free stencil
+ * product per field, no solve.  T is n x m (ldt >= n) in t_t, F is n x m
+ * (ldf >= n) in f_t.  compute = BKO_F64 uses the FP64 coefficients and
+ * FP64 accumulation; BKO_F32 (or BKO_BF16) uses the FP32 coefficients and
+ * FP32 accumulation.  T and F must not overlap.  Asynchronous.
+ */
+bko_status bko_apply_operator(bko_op A, int m, const void *T, int ldt, bko_dtype t_t, void *F,
+                              int ldf, bko_dtype f_t, bko_dtype compute, void *stream);
+
+/*
+ * Fused residual form used by the correction loop: R = B - A X in FP64
+ * (B, X, R n x m, FP64).  R may alias B.  Asynchronous.
+ */
+bko_status bko_residual(bko_op A, int m, const double *B, int ldb, const double *X, int ldx,
+                        double *R, int ldr, void *stream);
+
+/* ---------------------------------------------------- kernel timing hooks */
+
+/*
+ * Optional per-kernel timing: when enabled, the library records a HIP event
+ * pair around every launch of the named kernel family on the launch stream
+ * and accumulates the elapsed time when queried (which synchronises).
+ * Families: 0 = operator action, 1 = combine, 2 = gram, 3 = block
+ * update, 4 = small dense solve, 5 = block-solve stencil product, 6 = FP64
+ * residual.  Used to report per-kernel bandwidth.
+ */
+bko_status bko_timing_enable(int enable);
+bko_status bko_timing_query(int family, int *launches, double *total_ms);
+bko_status bko_timing_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLOCKOA_H */

@@ -1,0 +1,287 @@
+"""Thin Python binding of the C ABI in ``include/blockoa.h``.
+
+Argument marshalling only: every step of the path runs in the gfx950 kernels
+of ``libblockoa.so``; torch provides device memory and the current stream.
+There is no CPU fallback -- if the library is missing this module raises.
+
+Array convention: a block of ``k`` fields over ``N`` cells is a torch tensor
+of shape ``(k, N)`` whose rows are contiguous, i.e. a column-major ``N x k``
+matrix with leading dimension ``tensor.stride(0)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libblockoa.so")
+
+OK, EINVAL, ENOTSPD, ENOCONV, EBREAKDOWN, EHIP, ENOMEM, ENOTIMPL = range(8)
+F64, F32, BF16 = 0, 1, 2
+BC_DIRICHLET0, BC_ADIABATIC, BC_ROBIN = 0, 1, 2
+STATUS_NAMES = {0: "BKO_OK", 1: "BKO_EINVAL", 2: "BKO_ENOTSPD", 3: "BKO_ENOCONV",
+                4: "BKO_EBREAKDOWN", 5: "BKO_EHIP", 6: "BKO_ENOMEM", 7: "BKO_ENOTIMPL"}
+TORCH_DTYPE = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}
+DTYPE_CODE = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+DTYPE_NAME = {"f64": F64, "f32": F32, "bf16": BF16}
+
+#: every symbol include/blockoa.h declares
+EXPORTED = ("bko_version", "bko_last_error", "bko_operator_bytes", "bko_assemble_heat_operator",
+            "bko_operator_dims", "bko_destroy_operator", "bko_block_krylov_workspace_bytes",
+            "bko_block_krylov_solve", "bko_combine", "bko_apply_operator", "bko_residual",
+            "bko_timing_enable", "bko_timing_query", "bko_timing_reset")
+
+
+class BlockoaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("refinements", ctypes.c_int), ("deflated", ctypes.c_int),
+                ("status", ctypes.c_int), ("max_rel_res", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libblockoa.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2510_23221_amd.build` "
+                          "(there is no fallback path)")
+    lib = ctypes.CDLL(path)
+    vp, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "bko_version": (ctypes.c_char_p, []),
+        "bko_last_error": (ctypes.c_char_p, []),
+        "bko_operator_bytes": (i32, [i32, i32, i32, ctypes.POINTER(sz)]),
+        "bko_assemble_heat_operator": (i32, [i32, i32, i32, dbl, dbl, dbl, vp, vp, vp, vp, sz, vp,
+                                             ctypes.POINTER(vp)]),
+        "bko_operator_dims": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "bko_destroy_operator": (i32, [vp]),
+        "bko_block_krylov_workspace_bytes": (i32, [vp, i32, i32, ctypes.POINTER(sz)]),
+        "bko_block_krylov_solve": (i32, [vp, i32, vp, i32, vp, i32, vp, i32, i32, dbl, i32, vp, sz,
+                                         ctypes.POINTER(SolveInfo), vp]),
+        "bko_combine": (i32, [i32, i32, i32, vp, i32, i32, vp, i32, i32, vp, i32, i32, i32, vp]),
+        "bko_apply_operator": (i32, [vp, i32, vp, i32, i32, vp, i32, i32, i32, vp]),
+        "bko_residual": (i32, [vp, i32, vp, i32, vp, i32, vp, i32, vp]),
+        "bko_timing_enable": (i32, [i32]),
+        "bko_timing_query": (i32, [i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
+        "bko_timing_reset": (i32, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise BlockoaError(status, load_library().bko_last_error().decode())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _block(t: torch.Tensor, name: str):
+    """(k, N) tensor -> (pointer, ld, dtype code).  Rows must be contiguous."""
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a (k, N) tensor with contiguous rows")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    ld = t.stride(0) if t.shape[0] > 1 else max(t.stride(0), t.shape[1])
+    return _ptr(t), ld, DTYPE_CODE[t.dtype]
+
+
+def version() -> str:
+    return load_library().bko_version().decode()
+
+
+def operator_bytes(nx: int, ny: int, nz: int) -> int:
+    out = ctypes.c_size_t()
+    _check(load_library().bko_operator_bytes(nx, ny, nz, ctypes.byref(out)))
+    return out.value
+
+
+class HeatOperator:
+    """Discretised steady heat operator A of one chip (device-resident).
+
+    Owns the device buffers (conductivity and coefficient storage) through
+    torch; the C handle holds host metadata only."""
+
+    def __init__(self, nx: int, ny: int, nz: int, lx: float, ly: float, lz: float,
+                 k: torch.Tensor, bc: Sequence[int], h: Sequence[float], stream=None):
+        lib = load_library()
+        self.dims = (nx, ny, nz)
+        self.n = nx * ny * nz
+        self.k = k.to(dtype=torch.float64).contiguous()
+        if not self.k.is_cuda:
+            raise ValueError("k must live on the GPU")
+        nbytes = operator_bytes(nx, ny, nz)
+        self.coeff = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.k.device)
+        off = (-self.coeff.data_ptr()) % 256
+        self._coeff_ptr = self.coeff.data_ptr() + off
+        bc_a = (ctypes.c_int * 6)(*[int(b) for b in bc])
+        h_a = (ctypes.c_double * 6)(*[float(x) for x in h])
+        handle = ctypes.c_void_p()
+        _check(lib.bko_assemble_heat_operator(nx, ny, nz, lx, ly, lz, _ptr(self.k), bc_a, h_a,
+                                              ctypes.c_void_p(self._coeff_ptr), nbytes, _stream(stream),
+                                              ctypes.byref(handle)))
+        self.handle = handle
+
+    @classmethod
+    def from_chip(cls, chip, device="cuda", stream=None) -> "HeatOperator":
+        k = torch.as_tensor(chip.k, dtype=torch.float64, device=device)
+        return cls(chip.nx, chip.ny, chip.nz, chip.lx, chip.ly, chip.lz, k, chip.bc, chip.h, stream)
+
+    def coefficients(self):
+        """(diag, wx, wy, wz) FP64 views of the coefficient storage (for tests)."""
+        n = self.n
+        out = []
+        base = self._coeff_ptr - self.coeff.data_ptr()
+        off = 0
+        for _ in range(4):
+            t = self.coeff[base + off: base + off + 8 * n].view(torch.float64)
+            out.append(t)
+            off = (off + 8 * n + 255) // 256 * 256
+        return tuple(out)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load_library().bko_destroy_operator(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace_bytes(A: HeatOperator, s: int, compute: int = F64) -> int:
+    out = ctypes.c_size_t()
+    _check(load_library().bko_block_krylov_workspace_bytes(A.handle, s, compute, ctypes.byref(out)))
+    return out.value
+
+
+def _aligned_workspace(nbytes: int, device) -> tuple:
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf.data_ptr() + off
+
+
+def block_krylov_solve(A: HeatOperator, B: torch.Tensor, tol: float, compute: int = F64,
+                       max_iter: int = 100000, X0: Optional[torch.Tensor] = None,
+                       X: Optional[torch.Tensor] = None, work=None, stream=None, check: bool = True):
+    """Solve A X = B (B: (s, N) FP64 on the GPU).  Returns (X, info dict).
+
+    ``check=False`` returns non-converged results instead of raising."""
+    s = B.shape[0]
+    bp, ldb, bt = _block(B, "B")
+    if bt != F64:
+        raise ValueError("B must be float64")
+    if X is None:
+        X = torch.empty_like(B)
+    xp, ldx, _ = _block(X, "X")
+    x0p, ldx0 = (ctypes.c_void_p(0), 0)
+    if X0 is not None:
+        x0p, ldx0, x0t = _block(X0, "X0")
+        if x0t != F64:
+            raise ValueError("X0 must be float64")
+    nbytes = workspace_bytes(A, s, compute)
+    if work is None:
+        buf, wptr = _aligned_workspace(nbytes, B.device)
+    else:
+        buf, wptr = work, work.data_ptr()
+    info = SolveInfo()
+    st = load_library().bko_block_krylov_solve(A.handle, s, bp, ldb, xp, ldx, x0p, ldx0, compute, tol,
+                                               max_iter, ctypes.c_void_p(wptr), nbytes, ctypes.byref(info),
+                                               _stream(stream))
+    if check and st != OK:
+        _check(st)
+    d = info.as_dict()
+    d["status_name"] = STATUS_NAMES.get(st, str(st))
+    return X, d
+
+
+def combine(X: torch.Tensor, C: torch.Tensor, out_dtype=torch.float64, compute: int = F64,
+            T: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """T = X C with X (s, N) and C (M, s); returns T (M, N)."""
+    s, n = X.shape
+    m = C.shape[0]
+    if C.shape[1] != s:
+        raise ValueError("C must be (M, s)")
+    if T is None:
+        T = torch.empty((m, n), dtype=out_dtype, device=X.device)
+    xp, ldx, xt = _block(X, "X")
+    if C.stride(1) != 1:
+        raise ValueError("C must have contiguous rows")
+    cp, ldc, ct = _ptr(C), C.stride(0) if m > 1 else s, DTYPE_CODE[C.dtype]
+    tp, ldt, tt = _block(T, "T")
+    _check(load_library().bko_combine(n, s, m, xp, ldx, xt, cp, ldc, ct, tp, ldt, tt, compute, _stream(stream)))
+    return T
+
+
+def apply_operator(A: HeatOperator, T: torch.Tensor, out_dtype=torch.float64, compute: int = F64,
+                   F: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """F = A T (T: (M, N)); returns F (M, N)."""
+    m = T.shape[0]
+    if F is None:
+        F = torch.empty((m, A.n), dtype=out_dtype, device=T.device)
+    tp, ldt, tt = _block(T, "T")
+    fp, ldf, ft = _block(F, "F")
+    _check(load_library().bko_apply_operator(A.handle, m, tp, ldt, tt, fp, ldf, ft, compute, _stream(stream)))
+    return F
+
+
+def residual(A: HeatOperator, B: torch.Tensor, X: torch.Tensor, R: Optional[torch.Tensor] = None,
+             stream=None) -> torch.Tensor:
+    """R = B - A X in FP64."""
+    if R is None:
+        R = torch.empty_like(B)
+    bp, ldb, _ = _block(B, "B")
+    xp, ldx, _ = _block(X, "X")
+    rp, ldr, _ = _block(R, "R")
+    _check(load_library().bko_residual(A.handle, B.shape[0], bp, ldb, xp, ldx, rp, ldr, _stream(stream)))
+    return R
+
+
+# ------------------------------------------------------------------ timing hooks
+
+FAMILY = {"apply": 0, "combine": 1, "gram": 2, "update": 3, "small": 4, "spmm": 5, "resid": 6}
+
+
+def timing_enable(on: bool = True):
+    _check(load_library().bko_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    _check(load_library().bko_timing_reset())
+
+
+def timing_query(family: str):
+    n = ctypes.c_int()
+    ms = ctypes.c_double()
+    _check(load_library().bko_timing_query(FAMILY[family], ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value

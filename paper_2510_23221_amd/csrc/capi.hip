@@ -1,0 +1,449 @@
+// C ABI entry points: argument validation, operator handles, assembly of the
+// cell-centred heat operator, timing hooks.  Every entry point catches
+// everything so no C++ exception crosses the ABI.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace bko {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+bko_status hip_fail(hipError_t e, const char *what)
+{
+    set_error("HIP error %d (%s) in %s", static_cast<int>(e), hipGetErrorString(e), what);
+    return BKO_EHIP;
+}
+
+CoeffLayout coeff_layout(int64_t n)
+{
+    CoeffLayout L{};
+    size_t off = 0;
+    for (int a = 0; a < 4; ++a) {
+        L.off[a] = off;
+        off = align_up(off + sizeof(double) * static_cast<size_t>(n), 256);
+    }
+    for (int a = 4; a < 8; ++a) {
+        L.off[a] = off;
+        off = align_up(off + sizeof(float) * static_cast<size_t>(n), 256);
+    }
+    L.status_off = off;
+    L.bytes = off + 256;
+    return L;
+}
+
+// ------------------------------------------------------------ timing hooks
+
+namespace {
+struct TimingState {
+    std::mutex mu;
+    bool enabled = false;
+    std::vector<hipEvent_t> pool;
+    struct Pair { int family; hipEvent_t a, b; };
+    std::vector<Pair> pending;
+    int launches[kNumFamilies] = {};
+    double total_ms[kNumFamilies] = {};
+};
+TimingState &timing()
+{
+    static TimingState *t = new TimingState();  // never destroyed: events may outlive statics
+    return *t;
+}
+hipEvent_t take_event(TimingState &t)
+{
+    if (!t.pool.empty()) {
+        hipEvent_t e = t.pool.back();
+        t.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+bko_status drain(TimingState &t)
+{
+    for (auto &p : t.pending) {
+        float ms = 0.f;
+        BKO_HIP(hipEventSynchronize(p.b));
+        BKO_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+        t.launches[p.family] += 1;
+        t.total_ms[p.family] += ms;
+        t.pool.push_back(p.a);
+        t.pool.push_back(p.b);
+    }
+    t.pending.clear();
+    return BKO_OK;
+}
+}  // namespace
+
+TimedLaunch::TimedLaunch(int fam, hipStream_t s) : family(fam), stream(s), ev0(nullptr)
+{
+    TimingState &t = timing();
+    if (!t.enabled) return;
+    std::lock_guard<std::mutex> g(t.mu);
+    hipEvent_t e = take_event(t);
+    if (e && hipEventRecord(e, s) == hipSuccess) ev0 = e;
+}
+
+TimedLaunch::~TimedLaunch()
+{
+    if (!ev0) return;
+    TimingState &t = timing();
+    std::lock_guard<std::mutex> g(t.mu);
+    hipEvent_t e = take_event(t);
+    if (e && hipEventRecord(e, stream) == hipSuccess) {
+        t.pending.push_back({family, static_cast<hipEvent_t>(ev0), e});
+        if (t.pending.size() > 4096) drain(t);
+    }
+}
+
+// ------------------------------------------------------------ assembly
+
+__device__ inline double face_interior(double ka, double kb, double d2)
+{
+    // symmetric in (ka, kb) bit for bit: order the operands
+    const double lo = fmin(ka, kb), hi = fmax(ka, kb);
+    return 2.0 * lo * hi / ((lo + hi) * d2);
+}
+
+__device__ inline double face_boundary(int kind, double ka, double d, double h)
+{
+    if (kind == BKO_BC_DIRICHLET0) return 2.0 * ka / (d * d);
+    if (kind == BKO_BC_ROBIN) return 1.0 / (d * (d / (2.0 * ka) + 1.0 / h));
+    return 0.0;
+}
+
+struct FaceSpec {
+    int bc[6];
+    double h[6];
+    double d[3];
+};
+
+__global__ __launch_bounds__(256) void assemble_kernel(int nx, int ny, int nz, FaceSpec fs,
+                                                       const double *__restrict__ k, double *diag64,
+                                                       double *wx64, double *wy64, double *wz64,
+                                                       float *diag32, float *wx32, float *wy32,
+                                                       float *wz32, int *bad)
+{
+    const int64_t n = static_cast<int64_t>(nx) * ny * nz;
+    const int64_t a = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const int64_t plane = static_cast<int64_t>(nx) * ny;
+    const int i = static_cast<int>(a % nx);
+    const int j = static_cast<int>((a / nx) % ny);
+    const int l = static_cast<int>(a / plane);
+    const double ka = k[a];
+    if (!(ka > 0.0) || !isfinite(ka)) atomicAdd(bad, 1);
+    const int idx[3] = {i, j, l};
+    const int dims[3] = {nx, ny, nz};
+    const int64_t stride[3] = {1, nx, plane};
+    double plus[3];
+    double diag = 0.0;
+    for (int ax = 0; ax < 3; ++ax) {
+        const double d = fs.d[ax];
+        const double d2 = d * d;
+        if (idx[ax] > 0) diag += face_interior(ka, k[a - stride[ax]], d2);
+        else diag += face_boundary(fs.bc[2 * ax], ka, d, fs.h[2 * ax]);
+        if (idx[ax] < dims[ax] - 1) {
+            plus[ax] = face_interior(ka, k[a + stride[ax]], d2);
+            diag += plus[ax];
+        } else {
+            plus[ax] = 0.0;
+            diag += face_boundary(fs.bc[2 * ax + 1], ka, d, fs.h[2 * ax + 1]);
+        }
+    }
+    diag64[a] = diag;
+    wx64[a] = plus[0];
+    wy64[a] = plus[1];
+    wz64[a] = plus[2];
+    diag32[a] = static_cast<float>(diag);
+    wx32[a] = static_cast<float>(plus[0]);
+    wy32[a] = static_cast<float>(plus[1]);
+    wz32[a] = static_cast<float>(plus[2]);
+}
+
+__global__ void zero_kernel(uint32_t *p, size_t words)
+{
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    for (size_t w = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words; w += stride) p[w] = 0u;
+}
+
+bko_status launch_zero(void *p, size_t bytes, hipStream_t stream)
+{
+    if (bytes == 0) return BKO_OK;
+    if ((bytes % 4) != 0 || (reinterpret_cast<uintptr_t>(p) % 4) != 0) {
+        set_error("launch_zero: %zu bytes at %p not word aligned", bytes, p);
+        return BKO_EINVAL;
+    }
+    const size_t words = bytes / 4;
+    const size_t blocks = std::min<size_t>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(zero_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
+                       static_cast<uint32_t *>(p), words);
+    BKO_HIP(hipGetLastError());
+    return BKO_OK;
+}
+
+}  // namespace bko
+
+using namespace bko;
+
+// ------------------------------------------------------------------ C ABI
+
+#define BKO_GUARD_BEGIN try {
+#define BKO_GUARD_END                                                     \
+    }                                                                     \
+    catch (const std::bad_alloc &) {                                      \
+        set_error("host allocation failed");                              \
+        return BKO_ENOMEM;                                                \
+    }                                                                     \
+    catch (...) {                                                         \
+        set_error("unexpected C++ exception");                            \
+        return BKO_EINVAL;                                                \
+    }
+
+extern "C" {
+
+const char *bko_version(void) { return "blockoa 0.1 gfx950"; }
+
+const char *bko_last_error(void) { return g_err; }
+
+bko_status bko_operator_bytes(int nx, int ny, int nz, size_t *bytes)
+{
+    BKO_CHECK(nx >= 1 && ny >= 1 && nz >= 1, "grid %dx%dx%d must be positive", nx, ny, nz);
+    BKO_CHECK(bytes != nullptr, "bytes is NULL");
+    const int64_t n = static_cast<int64_t>(nx) * ny * nz;
+    BKO_CHECK(n <= (int64_t(1) << 31) - 1, "grid of %lld cells exceeds 2^31-1", (long long)n);
+    *bytes = coeff_layout(n).bytes;
+    return BKO_OK;
+}
+
+bko_status bko_assemble_heat_operator(int nx, int ny, int nz, double lx, double ly, double lz,
+                                      const double *k_cell_dev, const int bc[6], const double h[6],
+                                      void *coeff_dev, size_t coeff_bytes, void *stream,
+                                      bko_op *out)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(out != nullptr, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    bko_status st = bko_operator_bytes(nx, ny, nz, &need);
+    if (st != BKO_OK) return st;
+    BKO_CHECK(std::isfinite(lx) && std::isfinite(ly) && std::isfinite(lz) && lx > 0 && ly > 0 && lz > 0,
+              "extents must be positive and finite");
+    BKO_CHECK(k_cell_dev != nullptr && coeff_dev != nullptr && bc != nullptr && h != nullptr,
+              "NULL pointer argument");
+    BKO_CHECK(coeff_bytes >= need, "coefficient buffer has %zu bytes, need %zu", coeff_bytes, need);
+    BKO_CHECK(reinterpret_cast<uintptr_t>(coeff_dev) % 256 == 0, "coefficient buffer must be 256-byte aligned");
+    bool any_sink = false;
+    FaceSpec fs{};
+    for (int f = 0; f < 6; ++f) {
+        BKO_CHECK(bc[f] == BKO_BC_DIRICHLET0 || bc[f] == BKO_BC_ADIABATIC || bc[f] == BKO_BC_ROBIN,
+                  "face %d has unknown kind %d", f, bc[f]);
+        if (bc[f] == BKO_BC_ROBIN)
+            BKO_CHECK(h[f] > 0.0 && std::isfinite(h[f]), "Robin face %d needs h > 0 (got %g)", f, h[f]);
+        any_sink = any_sink || bc[f] != BKO_BC_ADIABATIC;
+        fs.bc[f] = bc[f];
+        fs.h[f] = bc[f] == BKO_BC_ROBIN ? h[f] : 1.0;
+    }
+    BKO_CHECK(any_sink, "every face is adiabatic: the operator is singular");
+    fs.d[0] = lx / nx;
+    fs.d[1] = ly / ny;
+    fs.d[2] = lz / nz;
+    const int64_t n = static_cast<int64_t>(nx) * ny * nz;
+    const CoeffLayout L = coeff_layout(n);
+    char *base = static_cast<char *>(coeff_dev);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int *bad = reinterpret_cast<int *>(base + L.status_off);
+    st = launch_zero(bad, 256, s);
+    if (st != BKO_OK) return st;
+    const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
+    hipLaunchKernelGGL(assemble_kernel, dim3(blocks), dim3(256), 0, s, nx, ny, nz, fs, k_cell_dev,
+                       reinterpret_cast<double *>(base + L.off[0]), reinterpret_cast<double *>(base + L.off[1]),
+                       reinterpret_cast<double *>(base + L.off[2]), reinterpret_cast<double *>(base + L.off[3]),
+                       reinterpret_cast<float *>(base + L.off[4]), reinterpret_cast<float *>(base + L.off[5]),
+                       reinterpret_cast<float *>(base + L.off[6]), reinterpret_cast<float *>(base + L.off[7]), bad);
+    BKO_HIP(hipGetLastError());
+    int nbad = 0;
+    BKO_HIP(hipMemcpyAsync(&nbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    BKO_HIP(hipStreamSynchronize(s));
+    if (nbad != 0) {
+        set_error("%d cells have conductivity <= 0 or not finite", nbad);
+        return BKO_ENOTSPD;
+    }
+    Operator *op = new Operator();
+    op->nx = nx;
+    op->ny = ny;
+    op->nz = nz;
+    op->lx = lx;
+    op->ly = ly;
+    op->lz = lz;
+    op->n = n;
+    op->coeff = coeff_dev;
+    op->diag64 = reinterpret_cast<const double *>(base + L.off[0]);
+    op->wx64 = reinterpret_cast<const double *>(base + L.off[1]);
+    op->wy64 = reinterpret_cast<const double *>(base + L.off[2]);
+    op->wz64 = reinterpret_cast<const double *>(base + L.off[3]);
+    op->diag32 = reinterpret_cast<const float *>(base + L.off[4]);
+    op->wx32 = reinterpret_cast<const float *>(base + L.off[5]);
+    op->wy32 = reinterpret_cast<const float *>(base + L.off[6]);
+    op->wz32 = reinterpret_cast<const float *>(base + L.off[7]);
+    *out = reinterpret_cast<bko_op>(op);
+    return BKO_OK;
+    BKO_GUARD_END
+}
+
+bko_status bko_operator_dims(bko_op A, int *nx, int *ny, int *nz)
+{
+    BKO_CHECK(A != nullptr, "operator handle is NULL");
+    const Operator *op = reinterpret_cast<const Operator *>(A);
+    if (nx) *nx = op->nx;
+    if (ny) *ny = op->ny;
+    if (nz) *nz = op->nz;
+    return BKO_OK;
+}
+
+bko_status bko_destroy_operator(bko_op A)
+{
+    delete reinterpret_cast<Operator *>(A);
+    return BKO_OK;
+}
+
+static bool valid_dtype(int t) { return t == BKO_F64 || t == BKO_F32 || t == BKO_BF16; }
+
+bko_status bko_apply_operator(bko_op A, int m, const void *T, int ldt, bko_dtype t_t, void *F, int ldf,
+                              bko_dtype f_t, bko_dtype compute, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(A != nullptr, "operator handle is NULL");
+    const Operator &op = *reinterpret_cast<const Operator *>(A);
+    BKO_CHECK(m >= 0, "m = %d < 0", m);
+    BKO_CHECK(valid_dtype(t_t) && valid_dtype(f_t) && valid_dtype(compute), "bad dtype");
+    if (m == 0) return BKO_OK;
+    BKO_CHECK(T != nullptr && F != nullptr, "NULL array");
+    BKO_CHECK(ldt >= op.n && ldf >= op.n, "leading dimensions (%d, %d) must be >= n = %lld", ldt, ldf,
+              (long long)op.n);
+    const char *t0 = static_cast<const char *>(T);
+    const char *t1 = t0 + dtype_size(t_t) * (static_cast<size_t>(ldt) * (m - 1) + op.n);
+    const char *f0 = static_cast<const char *>(F);
+    const char *f1 = f0 + dtype_size(f_t) * (static_cast<size_t>(ldf) * (m - 1) + op.n);
+    BKO_CHECK(t1 <= f0 || f1 <= t0, "T and F overlap");
+    TimedLaunch tl(kApply, static_cast<hipStream_t>(stream));
+    return launch_stencil(op, m, T, ldt, t_t, F, ldf, f_t, compute, nullptr, 0,
+                          static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+bko_status bko_residual(bko_op A, int m, const double *B, int ldb, const double *X, int ldx, double *R,
+                        int ldr, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(A != nullptr, "operator handle is NULL");
+    const Operator &op = *reinterpret_cast<const Operator *>(A);
+    BKO_CHECK(m >= 0, "m = %d < 0", m);
+    if (m == 0) return BKO_OK;
+    BKO_CHECK(B && X && R, "NULL array");
+    BKO_CHECK(ldb >= op.n && ldx >= op.n && ldr >= op.n, "leading dimensions must be >= n");
+    BKO_CHECK(!(R == B && ldr != ldb), "R aliases B with a different leading dimension");
+    TimedLaunch tl(kResid, static_cast<hipStream_t>(stream));
+    return launch_stencil(op, m, X, ldx, BKO_F64, R, ldr, BKO_F64, BKO_F64, B, ldb,
+                          static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+bko_status bko_combine(int n, int s, int m, const void *X, int ldx, bko_dtype x_t, const void *C, int ldc,
+                       bko_dtype c_t, void *T, int ldt, bko_dtype t_t, bko_dtype compute, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(n >= 0 && s >= 1 && m >= 0, "bad sizes n=%d s=%d m=%d", n, s, m);
+    BKO_CHECK(s <= 64, "s = %d exceeds the supported maximum of 64", s);
+    BKO_CHECK(valid_dtype(x_t) && valid_dtype(c_t) && valid_dtype(t_t) && valid_dtype(compute), "bad dtype");
+    if (n == 0 || m == 0) return BKO_OK;
+    BKO_CHECK(X && C && T, "NULL array");
+    BKO_CHECK(ldx >= n && ldc >= s && ldt >= n, "bad leading dimension");
+    TimedLaunch tl(kCombine, static_cast<hipStream_t>(stream));
+    return launch_combine(n, s, m, X, ldx, x_t, C, ldc, c_t, T, ldt, t_t, compute,
+                          static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+bko_status bko_block_krylov_workspace_bytes(bko_op A, int s, bko_dtype compute, size_t *bytes)
+{
+    BKO_CHECK(A != nullptr && bytes != nullptr, "NULL argument");
+    BKO_CHECK(s >= 1 && s <= 64, "s = %d outside [1, 64]", s);
+    BKO_CHECK(compute == BKO_F64 || compute == BKO_F32, "compute must be BKO_F64 or BKO_F32");
+    *bytes = solve_workspace_bytes(reinterpret_cast<const Operator *>(A)->n, s, compute);
+    return BKO_OK;
+}
+
+bko_status bko_block_krylov_solve(bko_op A, int s, const double *B, int ldb, double *X, int ldx,
+                                  const double *X0, int ldx0, bko_dtype compute, double tol, int max_iter,
+                                  void *work, size_t work_bytes, bko_solve_info *info, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(A != nullptr, "operator handle is NULL");
+    const Operator &op = *reinterpret_cast<const Operator *>(A);
+    BKO_CHECK(s >= 1 && s <= 64, "s = %d outside [1, 64]", s);
+    BKO_CHECK(compute == BKO_F64 || compute == BKO_F32, "compute must be BKO_F64 or BKO_F32");
+    BKO_CHECK(B && X && work, "NULL array");
+    BKO_CHECK(ldb >= op.n && ldx >= op.n, "leading dimensions must be >= n");
+    BKO_CHECK(X0 == nullptr || ldx0 >= op.n, "ldx0 must be >= n");
+    BKO_CHECK(tol > 0.0 && std::isfinite(tol), "tol must be positive");
+    BKO_CHECK(max_iter >= 1, "max_iter must be >= 1");
+    BKO_CHECK(reinterpret_cast<uintptr_t>(work) % 256 == 0, "workspace must be 256-byte aligned");
+    const size_t need = solve_workspace_bytes(op.n, s, compute);
+    if (work_bytes < need) {
+        set_error("workspace has %zu bytes, need %zu", work_bytes, need);
+        return BKO_ENOMEM;
+    }
+    if (X0 == X) BKO_CHECK(ldx0 == ldx, "X0 aliases X with a different leading dimension");
+    return block_solve(op, s, B, ldb, X, ldx, X0, ldx0, compute, tol, max_iter, work, work_bytes, info,
+                       static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+bko_status bko_timing_enable(int enable)
+{
+    TimingState &t = timing();
+    std::lock_guard<std::mutex> g(t.mu);
+    t.enabled = enable != 0;
+    return BKO_OK;
+}
+
+bko_status bko_timing_query(int family, int *launches, double *total_ms)
+{
+    BKO_CHECK(family >= 0 && family < kNumFamilies, "unknown timing family %d", family);
+    TimingState &t = timing();
+    std::lock_guard<std::mutex> g(t.mu);
+    bko_status st = drain(t);
+    if (st != BKO_OK) return st;
+    if (launches) *launches = t.launches[family];
+    if (total_ms) *total_ms = t.total_ms[family];
+    return BKO_OK;
+}
+
+bko_status bko_timing_reset(void)
+{
+    TimingState &t = timing();
+    std::lock_guard<std::mutex> g(t.mu);
+    bko_status st = drain(t);
+    for (int f = 0; f < kNumFamilies; ++f) {
+        t.launches[f] = 0;
+        t.total_ms[f] = 0.0;
+    }
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,269 @@
+// Combination of basis solutions into temperature fields, T = X C
+// (Sec. III-B, Eq. (5)): an n x s by s x m product with a short inner
+// dimension (s <= 64), so the kernel is bound by the store of T.
+//
+// Each workgroup owns a 64-cell tile of X, kept in registers as matrix-core
+// operands for the whole launch, and walks a range of fields 64 at a time:
+// stage the 64-field slice of C in LDS, run the 16x16 matrix-core products
+// (one 16-cell row block per wave, four 16-field blocks), stage the 64 x 64
+// output tile in LDS and write it back with 16-byte coalesced stores.
+//
+// Modes: FP64 (v_mfma_f64_16x16x4f64), FP32 (v_mfma_f32_16x16x4f32, FP32
+// accumulate) and BF16 (inputs rounded to BF16, v_mfma_f32_16x16x32_bf16,
+// FP32 accumulate).  Matrix-core operand layout for the 16x16 shapes: lane
+// L supplies A[L % 16][k] and B[k][L % 16] for the k slot(s) of lane group
+// L / 16; its four results are D[mfma_row(L / 16, r)][L % 16] (see
+// common.hpp: the FP64 shape interleaves the rows).
+#include <algorithm>
+#include <type_traits>
+
+#include "kernels.hpp"
+
+namespace bko {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int kTM = 64;       // cells per workgroup tile
+constexpr int kTN = 64;       // fields per inner step
+constexpr int kThreads = 256; // four waves
+
+enum Mode { kF64 = 0, kF32 = 1, kBF16 = 2 };
+
+template <int M> struct ModeTraits;
+template <> struct ModeTraits<kF64> {
+    using Acc = double;
+    using Stage = double;  // C slice element in LDS
+    static constexpr int kK = 4;
+};
+template <> struct ModeTraits<kF32> {
+    using Acc = float;
+    using Stage = float;
+    static constexpr int kK = 4;
+};
+template <> struct ModeTraits<kBF16> {
+    using Acc = float;
+    using Stage = uint16_t;
+    static constexpr int kK = 32;
+};
+
+__device__ inline __bf16 bits_to_bf(uint16_t b) { return __builtin_bit_cast(__bf16, b); }
+
+template <int kMode, class Tx, class Tc, class Tt>
+__global__ __launch_bounds__(kThreads) void combine_kernel(int64_t n, int s, int64_t m,
+                                                           const Tx *__restrict__ X, int64_t ldx,
+                                                           const Tc *__restrict__ C, int64_t ldc,
+                                                           Tt *__restrict__ T, int64_t ldt,
+                                                           int64_t fields_per_wg, uint32_t ntiles, int vec_ok)
+{
+    using TR = ModeTraits<kMode>;
+    using Acc = typename TR::Acc;
+    using Stage = typename TR::Stage;
+    constexpr int kK = TR::kK;
+    constexpr int kMaxSteps = 64 / kK;  // s <= 64
+
+    const int ksteps = (s + kK - 1) / kK;
+    const int s_pad = ksteps * kK;
+    // LDS: the C slice [kTN][cstride], then (aliasing it once the matrix-core
+    // products are done) the output tile [kTN][ostride]
+    const int cstride = kMode == kBF16 ? s_pad + 8 : s_pad + 1;
+    constexpr int ostride = kTM + (sizeof(Acc) == 8 ? 2 : 4);
+    extern __shared__ __align__(16) unsigned char smem[];
+    Stage *Cs = reinterpret_cast<Stage *>(smem);
+    Acc *Os = reinterpret_cast<Acc *>(smem);
+
+    const uint32_t tile = blockIdx.x % ntiles;
+    const uint32_t split = blockIdx.x / ntiles;
+    const int64_t cell0 = static_cast<int64_t>(tile) * kTM;
+    const int64_t f_begin = static_cast<int64_t>(split) * fields_per_wg;
+    const int64_t f_end = min(m, f_begin + fields_per_wg);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int li = lane & 15;  // row (cell) / column (field) within a 16-block
+    const int lg = lane >> 4;  // k group
+
+    // ---- A operands: the wave's 16 cells of X over all k, kept in registers
+    const int64_t my_cell = cell0 + wave * 16 + li;
+    const bool cell_ok = my_cell < n;
+    double a64[kMode == kF64 ? kMaxSteps : 1];
+    float a32[kMode == kF32 ? kMaxSteps : 1];
+    bf8 abf[kMode == kBF16 ? kMaxSteps : 1];
+#pragma unroll
+    for (int t = 0; t < kMaxSteps; ++t) {
+        if (t < ksteps) {
+            if constexpr (kMode == kBF16) {
+                bf8 v;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int k = t * kK + lg * 8 + e;
+                    const float x = (cell_ok && k < s) ? load_as<float>(X + static_cast<int64_t>(k) * ldx + my_cell) : 0.f;
+                    v[e] = bits_to_bf(f32_to_bf16(x));
+                }
+                abf[t] = v;
+            } else {
+                const int k = t * kK + lg;
+                const Acc x = (cell_ok && k < s) ? load_as<Acc>(X + static_cast<int64_t>(k) * ldx + my_cell) : Acc(0);
+                if constexpr (kMode == kF64) a64[t] = x;
+                else a32[t] = x;
+            }
+        }
+    }
+
+    constexpr int kVec = 16 / sizeof(Tt);
+    for (int64_t fb = f_begin; fb < f_end; fb += kTN) {
+        __syncthreads();  // previous tile's LDS reads are done
+        // ---- stage C[0:s_pad, fb:fb+64] as Cs[f][k]
+        for (int idx = tid; idx < kTN * s_pad; idx += kThreads) {
+            const int f = idx / s_pad;
+            const int k = idx - f * s_pad;
+            const int64_t field = fb + f;
+            Stage v;
+            if constexpr (kMode == kBF16) {
+                const float c = (k < s && field < m) ? load_as<float>(C + field * ldc + k) : 0.f;
+                v = f32_to_bf16(c);
+            } else {
+                v = (k < s && field < m) ? load_as<Acc>(C + field * ldc + k) : Acc(0);
+            }
+            Cs[f * cstride + k] = v;
+        }
+        __syncthreads();
+        // ---- four 16x16 blocks per wave, accumulators kept in registers
+        using AccV = typename std::conditional<kMode == kF64, d4, f4>::type;
+        AccV acc[kTN / 16];
+#pragma unroll
+        for (int jb = 0; jb < kTN / 16; ++jb) {
+            const Stage *cb = Cs + (jb * 16 + li) * cstride;
+            acc[jb] = AccV{0, 0, 0, 0};
+            if constexpr (kMode == kF64) {
+#pragma unroll
+                for (int t = 0; t < kMaxSteps; ++t)
+                    if (t < ksteps) acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a64[t], cb[t * kK + lg], acc[jb], 0, 0, 0);
+            } else if constexpr (kMode == kF32) {
+#pragma unroll
+                for (int t = 0; t < kMaxSteps; ++t)
+                    if (t < ksteps) acc[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a32[t], cb[t * kK + lg], acc[jb], 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int t = 0; t < kMaxSteps; ++t) {
+                    if (t < ksteps) {
+                        bf8 b;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) b[e] = bits_to_bf(cb[t * kK + lg * 8 + e]);
+                        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(abf[t], b, acc[jb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        __syncthreads();  // every wave is done with the C slice: reuse it for the output tile
+#pragma unroll
+        for (int jb = 0; jb < kTN / 16; ++jb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                Os[(jb * 16 + li) * ostride + wave * 16 + mfma_row<kMode == kF64>(lg, r)] = acc[jb][r];
+        __syncthreads();
+        // ---- write the 64 x 64 tile: fields are columns of T
+        constexpr int kVecPerField = kTM / kVec;
+        for (int idx = tid; idx < kTN * kVecPerField; idx += kThreads) {
+            const int f = idx / kVecPerField;
+            const int cv = idx - f * kVecPerField;
+            const int64_t field = fb + f;
+            if (field >= m) continue;
+            const int64_t cell = cell0 + cv * kVec;
+            Tt *dst = T + field * ldt + cell;
+            const Acc *src = Os + f * ostride + cv * kVec;
+            if (vec_ok && cell + kVec <= n) {
+                union {
+                    Tt e[kVec];
+                    uint4 v;
+                } u;
+#pragma unroll
+                for (int e = 0; e < kVec; ++e) u.e[e] = store_from<Tt, Acc>(src[e]);
+                *reinterpret_cast<uint4 *>(dst) = u.v;
+            } else {
+                for (int e = 0; e < kVec && cell + e < n; ++e) dst[e] = store_from<Tt, Acc>(src[e]);
+            }
+        }
+    }
+}
+
+template <int kMode, class Tx, class Tc, class Tt>
+bko_status run(int64_t n, int s, int64_t m, const void *X, int64_t ldx, const void *C, int64_t ldc, void *T,
+               int64_t ldt, hipStream_t stream)
+{
+    using TR = ModeTraits<kMode>;
+    const uint32_t ntiles = static_cast<uint32_t>((n + kTM - 1) / kTM);
+    const int64_t ftiles = (m + kTN - 1) / kTN;
+    // split the fields so that the grid has a few thousand workgroups
+    int64_t splits = std::max<int64_t>(1, std::min<int64_t>(ftiles, (8192 + ntiles - 1) / ntiles));
+    const int64_t fields_per_wg = ((ftiles + splits - 1) / splits) * kTN;
+    splits = (m + fields_per_wg - 1) / fields_per_wg;
+    const uint64_t nb = static_cast<uint64_t>(ntiles) * splits;
+    if (nb > 0x7fffffffu) {
+        set_error("combine grid too large");
+        return BKO_EINVAL;
+    }
+    const int ksteps = (s + TR::kK - 1) / TR::kK;
+    const int s_pad = ksteps * TR::kK;
+    const int cstride = kMode == kBF16 ? s_pad + 8 : s_pad + 1;
+    const int ostride = kTM + (sizeof(typename TR::Acc) == 8 ? 2 : 4);
+    const size_t cbytes = sizeof(typename TR::Stage) * kTN * cstride;
+    const size_t smem = std::max(cbytes, sizeof(typename TR::Acc) * kTN * ostride);
+    const int vec_ok = (reinterpret_cast<uintptr_t>(T) % 16 == 0) && ((ldt * sizeof(Tt)) % 16 == 0);
+    hipLaunchKernelGGL((combine_kernel<kMode, Tx, Tc, Tt>), dim3(static_cast<uint32_t>(nb)), dim3(kThreads), smem,
+                       stream, n, s, m, static_cast<const Tx *>(X), ldx, static_cast<const Tc *>(C), ldc,
+                       static_cast<Tt *>(T), ldt, fields_per_wg, ntiles, vec_ok);
+    BKO_HIP(hipGetLastError());
+    return BKO_OK;
+}
+
+template <int kMode, class Tx, class Tc>
+bko_status by_out(int64_t n, int s, int64_t m, const void *X, int64_t ldx, const void *C, int64_t ldc, void *T,
+                  int64_t ldt, bko_dtype t_t, hipStream_t stream)
+{
+    switch (t_t) {
+    case BKO_F64: return run<kMode, Tx, Tc, double>(n, s, m, X, ldx, C, ldc, T, ldt, stream);
+    case BKO_F32: return run<kMode, Tx, Tc, float>(n, s, m, X, ldx, C, ldc, T, ldt, stream);
+    default: return run<kMode, Tx, Tc, bf16>(n, s, m, X, ldx, C, ldc, T, ldt, stream);
+    }
+}
+
+template <int kMode, class Tx>
+bko_status by_c(int64_t n, int s, int64_t m, const void *X, int64_t ldx, const void *C, int64_t ldc, bko_dtype c_t,
+                void *T, int64_t ldt, bko_dtype t_t, hipStream_t stream)
+{
+    switch (c_t) {
+    case BKO_F64: return by_out<kMode, Tx, double>(n, s, m, X, ldx, C, ldc, T, ldt, t_t, stream);
+    case BKO_F32: return by_out<kMode, Tx, float>(n, s, m, X, ldx, C, ldc, T, ldt, t_t, stream);
+    default: return by_out<kMode, Tx, bf16>(n, s, m, X, ldx, C, ldc, T, ldt, t_t, stream);
+    }
+}
+
+template <int kMode>
+bko_status by_x(int64_t n, int s, int64_t m, const void *X, int64_t ldx, bko_dtype x_t, const void *C, int64_t ldc,
+                bko_dtype c_t, void *T, int64_t ldt, bko_dtype t_t, hipStream_t stream)
+{
+    switch (x_t) {
+    case BKO_F64: return by_c<kMode, double>(n, s, m, X, ldx, C, ldc, c_t, T, ldt, t_t, stream);
+    case BKO_F32: return by_c<kMode, float>(n, s, m, X, ldx, C, ldc, c_t, T, ldt, t_t, stream);
+    default: return by_c<kMode, bf16>(n, s, m, X, ldx, C, ldc, c_t, T, ldt, t_t, stream);
+    }
+}
+
+}  // namespace
+
+bko_status launch_combine(int64_t n, int s, int64_t m, const void *X, int64_t ldx, bko_dtype x_t, const void *C,
+                          int64_t ldc, bko_dtype c_t, void *T, int64_t ldt, bko_dtype t_t, bko_dtype compute,
+                          hipStream_t stream)
+{
+    switch (compute) {
+    case BKO_F64: return by_x<kF64>(n, s, m, X, ldx, x_t, C, ldc, c_t, T, ldt, t_t, stream);
+    case BKO_F32: return by_x<kF32>(n, s, m, X, ldx, x_t, C, ldc, c_t, T, ldt, t_t, stream);
+    default: return by_x<kBF16>(n, s, m, X, ldx, x_t, C, ldc, c_t, T, ldt, t_t, stream);
+    }
+}
+
+}  // namespace bko

@@ -1,0 +1,170 @@
+// Shared device/host helpers of the gfx950 library: storage types, BF16
+// conversion, launch bookkeeping and error plumbing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/blockoa.h"
+
+namespace bko {
+
+// ------------------------------------------------------------------ types
+
+// BF16 is carried as raw 16-bit words; conversions are explicit.
+struct bf16 {
+    uint16_t bits;
+};
+
+__device__ inline float bf16_to_f32(uint16_t b)
+{
+    return __uint_as_float(static_cast<uint32_t>(b) << 16);
+}
+
+// Round to nearest, ties to even; NaN stays a quiet NaN.
+__device__ inline uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return static_cast<uint16_t>((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+
+template <class T> struct Conv;
+template <> struct Conv<double> {
+    __device__ static inline double to_f64(double v) { return v; }
+    __device__ static inline float to_f32(double v) { return static_cast<float>(v); }
+    __device__ static inline double from_f64(double v) { return v; }
+    __device__ static inline double from_f32(float v) { return static_cast<double>(v); }
+};
+template <> struct Conv<float> {
+    __device__ static inline double to_f64(float v) { return static_cast<double>(v); }
+    __device__ static inline float to_f32(float v) { return v; }
+    __device__ static inline float from_f64(double v) { return static_cast<float>(v); }
+    __device__ static inline float from_f32(float v) { return v; }
+};
+template <> struct Conv<bf16> {
+    __device__ static inline double to_f64(bf16 v) { return static_cast<double>(bf16_to_f32(v.bits)); }
+    __device__ static inline float to_f32(bf16 v) { return bf16_to_f32(v.bits); }
+    __device__ static inline bf16 from_f64(double v) { return bf16{f32_to_bf16(static_cast<float>(v))}; }
+    __device__ static inline bf16 from_f32(float v) { return bf16{f32_to_bf16(v)}; }
+};
+
+// Accumulator-typed load / store helpers.
+template <class Acc, class T> __device__ inline Acc load_as(const T *p);
+template <> __device__ inline double load_as<double, double>(const double *p) { return *p; }
+template <> __device__ inline double load_as<double, float>(const float *p) { return static_cast<double>(*p); }
+template <> __device__ inline double load_as<double, bf16>(const bf16 *p) { return Conv<bf16>::to_f64(*p); }
+template <> __device__ inline float load_as<float, double>(const double *p) { return static_cast<float>(*p); }
+template <> __device__ inline float load_as<float, float>(const float *p) { return *p; }
+template <> __device__ inline float load_as<float, bf16>(const bf16 *p) { return Conv<bf16>::to_f32(*p); }
+
+template <class T, class Acc> __device__ inline T store_from(Acc v);
+template <> __device__ inline double store_from<double, double>(double v) { return v; }
+template <> __device__ inline float store_from<float, double>(double v) { return static_cast<float>(v); }
+template <> __device__ inline bf16 store_from<bf16, double>(double v) { return Conv<bf16>::from_f64(v); }
+template <> __device__ inline double store_from<double, float>(float v) { return static_cast<double>(v); }
+template <> __device__ inline float store_from<float, float>(float v) { return v; }
+template <> __device__ inline bf16 store_from<bf16, float>(float v) { return Conv<bf16>::from_f32(v); }
+
+// Row of the 16x16 output block held in result register r of a lane in lane
+// group g = lane / 16 (the column is lane % 16).  Measured on gfx950:
+// v_mfma_f64_16x16x4f64 interleaves the rows (g + 4 r); the FP32 and BF16
+// 16x16 shapes hold four consecutive rows (4 g + r).
+template <bool kF64>
+__device__ inline int mfma_row(int g, int r)
+{
+    return kF64 ? g + 4 * r : 4 * g + r;
+}
+
+inline size_t dtype_size(bko_dtype t)
+{
+    return t == BKO_F64 ? 8 : (t == BKO_F32 ? 4 : 2);
+}
+
+__host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------- XCD mapping
+
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
+// with a private L2.  remap_block() turns the hardware order into a logical
+// order in which every XCD walks a contiguous range of tiles, so stencil
+// neighbours and re-read operands stay in one L2.
+constexpr int kNumXcd = 8;
+
+__device__ inline uint32_t remap_block(uint32_t bid, uint32_t nblocks)
+{
+    const uint32_t per = nblocks / kNumXcd;
+    const uint32_t rem = nblocks % kNumXcd;
+    const uint32_t xcd = bid % kNumXcd;
+    const uint32_t slot = bid / kNumXcd;
+    // XCDs [0, rem) own per + 1 logical blocks, the rest own per.
+    const uint32_t start = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
+    return start + slot;
+}
+
+// -------------------------------------------------------- error plumbing
+
+void set_error(const char *fmt, ...);
+bko_status hip_fail(hipError_t e, const char *what);
+
+#define BKO_HIP(call)                                                   \
+    do {                                                                \
+        hipError_t e_ = (call);                                         \
+        if (e_ != hipSuccess) return ::bko::hip_fail(e_, #call);        \
+    } while (0)
+
+#define BKO_CHECK(cond, ...)                                            \
+    do {                                                                \
+        if (!(cond)) {                                                  \
+            ::bko::set_error(__VA_ARGS__);                              \
+            return BKO_EINVAL;                                          \
+        }                                                               \
+    } while (0)
+
+// ------------------------------------------------------------ operator
+
+struct Operator {
+    int nx, ny, nz;
+    double lx, ly, lz;
+    int64_t n;
+    void *coeff;          // caller-owned device buffer
+    // FP64 coefficient arrays (device pointers into coeff)
+    const double *diag64, *wx64, *wy64, *wz64;
+    const float *diag32, *wx32, *wy32, *wz32;
+};
+
+// Byte layout of the coefficient buffer.
+struct CoeffLayout {
+    size_t off[8];
+    size_t status_off;
+    size_t bytes;
+};
+CoeffLayout coeff_layout(int64_t n);
+
+// ------------------------------------------------------------ timing hooks
+
+enum TimingFamily {
+    kApply = 0,    // operator action over M fields
+    kCombine = 1,  // T = X C
+    kGram = 2,     // s x s Gram partials
+    kUpdate = 3,   // block updates
+    kSmall = 4,    // one-workgroup FP64 factorisations
+    kSpmm = 5,     // stencil product inside the block iteration
+    kResid = 6,    // FP64 residual B - A X
+    kNumFamilies = 7
+};
+
+struct TimedLaunch {
+    TimedLaunch(int family, hipStream_t s);
+    ~TimedLaunch();
+    int family;
+    hipStream_t stream;
+    void *ev0;
+};
+
+}  // namespace bko

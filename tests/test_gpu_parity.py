@@ -1,0 +1,346 @@
+"""Parity of the gfx950 path against the CPU oracle (element by element on the
+same seeded inputs), called through the C ABI.
+
+Tolerances (written per test):
+* FP64 stage-local products: forward-error bound (8 u) |A||T| per entry for
+  the operator action (Sec. III-C), gamma_s |X||C| for the combination
+  (Sec. III-B), u = 2^-53;
+* FP32 / BF16 stages: the same bounds with the stage's unit roundoff, against
+  the oracle applied to the stage's own (rounded) inputs;
+* block solve (Sec. III-A): FP64 true residual <= tol per column, and
+  ||X - X_ref||_F / ||X_ref||_F <= 1e-8 against per-column CG to 1e-13.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2510_23221_amd import capi, synth
+from tests.gpu_util import abs_csr, bf16_round, f32_round, rel_fro, stage_bound_apply, to_np
+
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+U32 = 2.0 ** -24
+UBF = 2.0 ** -8
+
+D0, AD, RB = synth.BC_DIRICHLET0, synth.BC_ADIABATIC, synth.BC_ROBIN
+
+
+def _chip(kind, seed=0):
+    rng = np.random.default_rng(seed)
+    if kind == "2d":
+        return synth.chip_2d(rng, 64)
+    if kind == "ragged":  # several tiles and a ragged tail in every direction
+        nx, ny, nz = 37, 23, 5
+        k = rng.uniform(1.0, 400.0, size=nx * ny * nz)
+        return synth.Chip(nx, ny, nz, 1.1e-3, 0.7e-3, 0.2e-3, k, (D0, AD, RB, D0, AD, RB),
+                          (0, 0, 2e4, 0, 0, 5e3))
+    if kind == "stack":
+        return synth.chip_stack(rng, 32, 32, 8)
+    if kind == "line":  # 1-D
+        k = rng.uniform(1.0, 10.0, size=300)
+        return synth.Chip(300, 1, 1, 1.0, 1.0, 1.0, k, (D0, RB, AD, AD, AD, AD), (0, 3.0, 0, 0, 0, 0))
+    raise ValueError(kind)
+
+
+@pytest.fixture(scope="module")
+def ops(dev):
+    out = {}
+    for kind in ("2d", "ragged", "stack", "line"):
+        chip = _chip(kind)
+        out[kind] = (chip, oracle.assemble_chip(chip), capi.HeatOperator.from_chip(chip, dev))
+    return out
+
+
+# ------------------------------------------------------------------ assembly
+
+@pytest.mark.parametrize("kind", ["2d", "ragged", "stack", "line"])
+def test_assembly_matches_oracle_csr(ops, kind):
+    chip, A, G = ops[kind]
+    diag, wx, wy, wz = (to_np(t) for t in G.coefficients())
+    D = np.zeros(A.n)
+    nbr = {}
+    for r in range(A.n):
+        for p in range(A.rowptr[r], A.rowptr[r + 1]):
+            c = A.col[p]
+            if c == r:
+                D[r] = A.val[p]
+            else:
+                nbr[(r, c)] = -A.val[p]
+    assert np.allclose(diag, D, rtol=1e-14, atol=0)
+    nx, ny = chip.nx, chip.ny
+    for arr, off in ((wx, 1), (wy, nx), (wz, nx * ny)):
+        for r in range(0, A.n, max(1, A.n // 997)):
+            expect = nbr.get((r, r + off), 0.0)
+            assert abs(arr[r] - expect) <= 1e-14 * abs(expect), (r, off)
+
+
+def test_assembly_rejects_bad_input(dev):
+    k = torch.ones(8, dtype=torch.float64, device=dev)
+    with pytest.raises(capi.BlockoaError) as e:
+        capi.HeatOperator(2, 2, 2, 1, 1, 1, k, [AD] * 6, [0] * 6)
+    assert e.value.status == capi.EINVAL
+    k[3] = -1.0
+    with pytest.raises(capi.BlockoaError) as e:
+        capi.HeatOperator(2, 2, 2, 1, 1, 1, k, [D0] * 6, [0] * 6)
+    assert e.value.status == capi.ENOTSPD
+    k[3] = float("nan")
+    with pytest.raises(capi.BlockoaError):
+        capi.HeatOperator(2, 2, 2, 1, 1, 1, k, [D0] * 6, [0] * 6)
+    with pytest.raises(capi.BlockoaError):
+        capi.HeatOperator(2, 2, 2, 1, 1, 1, torch.ones(8, dtype=torch.float64, device=dev), [RB] * 6, [0] * 6)
+
+
+# ------------------------------------------------------------------ operator action
+
+@pytest.mark.parametrize("kind", ["2d", "ragged", "stack", "line"])
+@pytest.mark.parametrize("m", [1, 7, 33])
+def test_apply_f64(ops, dev, kind, m):
+    chip, A, G = ops[kind]
+    rng = np.random.default_rng(m)
+    T = rng.standard_normal((m, A.n))
+    F = to_np(capi.apply_operator(G, torch.as_tensor(T, device=dev)))
+    F_ref = oracle.apply_many(A, T)
+    assert (np.abs(F - F_ref) <= stage_bound_apply(A, T, U64) + 1e-300).all()
+
+
+@pytest.mark.parametrize("tdt,fdt", [(torch.float32, torch.float32), (torch.bfloat16, torch.float32),
+                                     (torch.bfloat16, torch.bfloat16), (torch.float64, torch.float32)])
+def test_apply_low_precision(ops, dev, tdt, fdt):
+    chip, A, G = ops["ragged"]
+    rng = np.random.default_rng(5)
+    T = rng.standard_normal((9, A.n))
+    Tg = torch.as_tensor(T, device=dev).to(tdt)
+    T_used = to_np(Tg)  # the stage's own (rounded) input
+    F = to_np(capi.apply_operator(G, Tg, out_dtype=fdt, compute=capi.F32))
+    F_ref = oracle.apply_many(A, T_used)
+    # FP32 coefficients (u32 each) + FP32 accumulation + output rounding
+    u_out = UBF if fdt == torch.bfloat16 else U32
+    bound = stage_bound_apply(A, T_used, U32) + 2 * U32 * oracle.apply_many(abs_csr(A), np.abs(T_used)) \
+        + u_out * np.abs(F_ref) * 2
+    assert (np.abs(F - F_ref) <= bound * 1.01 + 1e-30).all()
+
+
+def test_apply_leading_dimension_views(ops, dev):
+    chip, A, G = ops["ragged"]
+    rng = np.random.default_rng(8)
+    big = torch.as_tensor(rng.standard_normal((4, A.n + 13)), device=dev)
+    T = big[:, 5:5 + A.n]  # ld = n + 13, offset start
+    Fbig = torch.zeros((4, A.n + 7), dtype=torch.float64, device=dev)
+    F = Fbig[:, 3:3 + A.n]
+    capi.apply_operator(G, T, F=F)
+    F_ref = oracle.apply_many(A, to_np(T))
+    assert (np.abs(to_np(F) - F_ref) <= stage_bound_apply(A, to_np(T), U64)).all()
+    # nothing outside the view was written
+    assert (to_np(Fbig[:, :3]) == 0).all() and (to_np(Fbig[:, 3 + A.n:]) == 0).all()
+
+
+def test_residual_matches_oracle(ops, dev):
+    chip, A, G = ops["stack"]
+    rng = np.random.default_rng(3)
+    B = rng.standard_normal((5, A.n))
+    X = rng.standard_normal((5, A.n))
+    R = to_np(capi.residual(G, torch.as_tensor(B, device=dev), torch.as_tensor(X, device=dev)))
+    R_ref = B - oracle.apply_many(A, X)
+    bound = stage_bound_apply(A, X, U64) + U64 * (np.abs(B) + np.abs(R_ref)) * 2
+    assert (np.abs(R - R_ref) <= bound).all()
+
+
+def test_symmetry_and_rowsum_through_gpu(ops, dev):
+    chip, A, G = ops["ragged"]
+    rng = np.random.default_rng(9)
+    v = torch.as_tensor(rng.standard_normal((1, A.n)), device=dev)
+    w = torch.as_tensor(rng.standard_normal((1, A.n)), device=dev)
+    Av = capi.apply_operator(G, v)
+    Aw = capi.apply_operator(G, w)
+    a, b = float((w * Av).sum()), float((v * Aw).sum())
+    assert abs(a - b) <= 1e-12 * (abs(a) + abs(b))
+    assert float((v * Av).sum()) > 0
+
+
+# ------------------------------------------------------------------ combination
+
+@pytest.mark.parametrize("s,m", [(8, 1000), (1, 5), (5, 77), (32, 130), (64, 65)])
+def test_combine_f64(dev, s, m):
+    rng = np.random.default_rng(s * 1000 + m)
+    n = 4096 + 37
+    X = rng.standard_normal((s, n))
+    C = rng.standard_normal((m, s))
+    T = to_np(capi.combine(torch.as_tensor(X, device=dev), torch.as_tensor(C, device=dev)))
+    T_ref = oracle.gemm(X, C)
+    bound = (s + 1) * U64 * (np.abs(C) @ np.abs(X))
+    assert (np.abs(T - T_ref) <= bound * 1.01 + 1e-300).all()
+
+
+@pytest.mark.parametrize("compute,tdt", [(capi.F32, torch.float32), (capi.F32, torch.float64),
+                                         (capi.BF16, torch.float32), (capi.BF16, torch.bfloat16)])
+def test_combine_low_precision(dev, compute, tdt):
+    rng = np.random.default_rng(21)
+    s, m, n = 64, 200, 3000 + 5
+    X = rng.standard_normal((s, n))
+    C = rng.standard_normal((m, s))
+    T = to_np(capi.combine(torch.as_tensor(X, device=dev), torch.as_tensor(C, device=dev), out_dtype=tdt,
+                           compute=compute))
+    rnd = f32_round if compute == capi.F32 else bf16_round
+    Xr, Cr = rnd(X), rnd(C)  # the stage's own rounded inputs
+    T_ref = oracle.gemm(Xr, Cr)
+    u_out = {torch.float64: 0.0, torch.float32: U32, torch.bfloat16: UBF}[tdt]
+    bound = (s + 1) * U32 * (np.abs(Cr) @ np.abs(Xr)) + u_out * np.abs(T_ref) * 1.01
+    assert (np.abs(T - T_ref) <= bound * 1.01 + 1e-30).all()
+
+
+def test_combine_ragged_ld(dev):
+    rng = np.random.default_rng(4)
+    s, m, n = 7, 19, 1001
+    Xb = torch.as_tensor(rng.standard_normal((s, n + 3)), device=dev)
+    X = Xb[:, 1:1 + n]
+    C = torch.as_tensor(rng.standard_normal((m, s)), device=dev)
+    Tb = torch.zeros((m, n + 9), dtype=torch.float32, device=dev)
+    T = Tb[:, 2:2 + n]
+    capi.combine(X, C, T=T, compute=capi.F32)
+    T_ref = oracle.gemm(f32_round(to_np(X)), f32_round(to_np(C)))
+    assert np.abs(to_np(T) - T_ref).max() <= 1e-5 * np.abs(T_ref).max()
+    assert (to_np(Tb[:, :2]) == 0).all() and (to_np(Tb[:, 2 + n:]) == 0).all()
+
+
+# ------------------------------------------------------------------ block solve
+
+def _solve_check(A, G, B, tol, compute, dev, ref_tol=1e-13, xerr=1e-8, X0=None):
+    Bg = torch.as_tensor(B, device=dev)
+    X0g = None if X0 is None else torch.as_tensor(X0, device=dev)
+    X, info = capi.block_krylov_solve(G, Bg, tol, compute=compute, X0=X0g)
+    X = to_np(X)
+    R = B - oracle.apply_many(A, X)
+    bn = np.linalg.norm(B, axis=1)
+    rel = np.linalg.norm(R, axis=1) / np.where(bn > 0, bn, 1)
+    assert rel.max() <= tol * 1.0001, (rel.max(), info)
+    # the library's FP64 residual and the oracle's differ by the rounding of
+    # evaluating b - A x itself: (8 u) ||(|A||x| + |b|)|| / ||b|| per column
+    floor = 8 * U64 * np.linalg.norm(oracle.apply_many(abs_csr(A), np.abs(X)) + np.abs(B), axis=1) \
+        / np.where(bn > 0, bn, 1)
+    assert abs(info["max_rel_res"] - rel.max()) <= 1e-3 * tol + 0.01 * rel.max() + floor.max()
+    X_ref, _, _ = oracle.cg_many(A, B, ref_tol)
+    if xerr is not None:
+        assert rel_fro(X, X_ref) <= xerr, (rel_fro(X, X_ref), info)
+    # per-column CG to the same stopping target the block solve uses
+    _, it_same, _ = oracle.cg_many(A, B, 0.5 * tol)
+    return X, info, it_same
+
+
+@pytest.mark.parametrize("kind,xerr", [("2d", 1e-8), ("ragged", 1e-8), ("line", 1e-6)])
+def test_block_solve_f64(ops, dev, kind, xerr):
+    chip, A, G = ops[kind]
+    rng = np.random.default_rng(1)
+    B = rng.standard_normal((8, A.n))
+    X, info, it_ref = _solve_check(A, G, B, 1e-12, capi.F64, dev, xerr=xerr)
+    assert info["status"] == capi.OK
+    # the shared Krylov space needs fewer iterations than one CG per column
+    # (the paper's ablation, Sec. V-E)
+    assert info["iters"] < it_ref.mean()
+
+
+def test_block_solve_config1_workload(dev):
+    w = synth.workload(0)
+    chip = w.chips[0]
+    A = oracle.assemble_chip(chip)
+    G = capi.HeatOperator.from_chip(chip, dev)
+    X, info, it_ref = _solve_check(A, G, w.B[0], w.tol, capi.F64, dev, xerr=1e-7)
+    assert info["iters"] < it_ref.mean()
+
+
+@pytest.mark.parametrize("kind", ["2d", "stack", "ragged"])
+def test_block_solve_mixed(ops, dev, kind):
+    chip, A, G = ops[kind]
+    rng = np.random.default_rng(2)
+    B = rng.standard_normal((16, A.n))
+    X, info, _ = _solve_check(A, G, B, 1e-8, capi.F32, dev, xerr=None)
+    assert info["refinements"] >= 2  # FP32 inner solves need FP64 corrections
+
+
+def test_block_solve_s1_is_cg(ops, dev):
+    chip, A, G = ops["2d"]
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal((1, A.n))
+    X, info, it_ref = _solve_check(A, G, b, 1e-10, capi.F64, dev, xerr=1e-6)
+    assert abs(info["iters"] - it_ref[0]) <= 2
+
+
+def test_block_solve_eigenmode_one_step(dev):
+    n = 24
+    chip = synth.Chip(n, n, 1, 1.0, 1.0, 1.0, np.full(n * n, 3.0), (D0, D0, D0, D0, AD, AD), (0,) * 6)
+    A = oracle.assemble_chip(chip)
+    G = capi.HeatOperator.from_chip(chip, dev)
+    i = np.arange(n) + 0.5
+    B = np.stack([np.outer(np.sin(q * np.pi * i / n), np.sin(p * np.pi * i / n)).reshape(-1)
+                  for p, q in ((1, 1), (2, 5), (4, 3))])
+    X, info, _ = _solve_check(A, G, B, 1e-12, capi.F64, dev)
+    assert info["iters"] <= 2
+
+
+def test_block_solve_degenerate_columns(ops, dev):
+    """Duplicate and zero right-hand sides: directions are deflated, the solve
+    still converges and zero columns give zero solutions."""
+    chip, A, G = ops["2d"]
+    rng = np.random.default_rng(4)
+    B = rng.standard_normal((6, A.n))
+    B[3] = B[1]
+    B[4] = 2.0 * B[0] - B[2]
+    B[5] = 0.0
+    X, info, _ = _solve_check(A, G, B, 1e-10, capi.F64, dev, xerr=1e-6)
+    assert info["deflated"] >= 1
+    assert np.abs(X[5]).max() == 0.0
+
+
+def test_block_solve_initial_guess(ops, dev):
+    chip, A, G = ops["2d"]
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((4, A.n))
+    X_ref, _, _ = oracle.cg_many(A, B, 1e-13)
+    # exact start: no iterations
+    X, info, _ = _solve_check(A, G, B, 1e-10, capi.F64, dev, X0=X_ref)
+    assert info["iters"] == 0
+    # a perturbed start takes fewer iterations than a zero start
+    _, info0, _ = _solve_check(A, G, B, 1e-10, capi.F64, dev)
+    _, info1, _ = _solve_check(A, G, B, 1e-10, capi.F64, dev, X0=X_ref * (1 + 1e-4 * rng.standard_normal(X_ref.shape)))
+    assert info1["iters"] < info0["iters"]
+
+
+def test_block_solve_no_convergence_reports(ops, dev):
+    chip, A, G = ops["2d"]
+    rng = np.random.default_rng(6)
+    B = torch.as_tensor(rng.standard_normal((4, A.n)), device=dev)
+    X, info = capi.block_krylov_solve(G, B, 1e-12, max_iter=3, check=False)
+    assert info["status"] == capi.ENOCONV
+    assert 0 < info["max_rel_res"] < 1.0
+    with pytest.raises(capi.BlockoaError):
+        capi.block_krylov_solve(G, B, 1e-12, max_iter=3)
+
+
+# ------------------------------------------------------------------ end to end
+
+def test_pipeline_config1_full(dev):
+    """Config-1 workload end to end: basis solve, 1000 combinations, operator
+    action; every pair checked against the oracle."""
+    w = synth.workload(0)
+    chip = w.chips[0]
+    A = oracle.assemble_chip(chip)
+    G = capi.HeatOperator.from_chip(chip, dev)
+    B = torch.as_tensor(w.B[0], device=dev)
+    C = torch.as_tensor(w.C[0], device=dev)
+    X, info = capi.block_krylov_solve(G, B, w.tol)
+    T = capi.combine(X, C)
+    F = capi.apply_operator(G, T)
+    Xn, Tn, Fn = to_np(X), to_np(T), to_np(F)
+    # stage-local pair consistency: F = A T to FP64 rounding
+    assert (np.abs(Fn - oracle.apply_many(A, Tn)) <= stage_bound_apply(A, Tn, U64)).all()
+    # against the oracle pipeline
+    X_ref, _, _ = oracle.cg_many(A, w.B[0], 1e-13)
+    T_ref = oracle.gemm(X_ref, w.C[0])
+    F_ref = oracle.apply_many(A, T_ref)
+    assert rel_fro(Tn, T_ref) <= 1e-8
+    assert rel_fro(Fn, F_ref) <= 1e-8
+    # invariant A (X c) = B c up to the solve residual
+    Bc = w.C[0] @ w.B[0]
+    rel = np.linalg.norm(Fn - Bc, axis=1) / np.linalg.norm(Bc, axis=1)
+    assert rel.max() <= 1e-8
