@@ -2,26 +2,46 @@
 // operator (Sec. III-A, Eq. (4)).
 //
 // The paper names block CG without fixing a variant.  This is the retooled
-// block CG that carries an orthonormal residual basis Q (R = Q C with C
-// upper triangular) so that columns converging at different rates do not
-// make the s x s systems ill conditioned, with rank-revealing (masked)
-// Cholesky factorisations that drop linearly dependent directions instead of
-// breaking down.  One iteration, with P the search block:
-//     AP    = A P                                   (stencil product)
-//     delta = P^T AP          = L_d L_d^T           (FP64 Gram, Cholesky)
-//     D    += P delta^+ C                            (solution update)
-//     W     = Q - AP delta^+                         (next residual basis)
-//     W^T W = L L^T,  S = L^T                        (Cholesky QR)
-//     Q     = W S^+,  C = S C,  P = Q + P S^T
-// and ||r_j|| = ||C e_j||, so convergence is read off C without a pass.
+// block CG that carries an orthonormal residual basis Q (R = Q C) so that
+// columns converging at different rates do not make the s x s systems ill
+// conditioned, with rank-revealing factorisations that drop linearly
+// dependent directions instead of breaking down.  One iteration, with P the
+// search block:
+//     AP    = A P                                  (stencil product)
+//     delta = P^T AP                               (FP64 Gram)
+//     W     = Q - AP delta^+                       (next residual basis)
+//     W^T W = S^T S  (S upper triangular)          (Cholesky QR, FP64)
+//     D    += P delta^+ C ;  Q = W S^+ ;  P = Q + P S^T ;  C = S C
+// and ||r_j|| = ||C e_j||, so convergence is read off C without a pass over
+// the residual.
+//
+// Kernels per iteration, all on one stream with no host round trip; the
+// kernel boundary is the only grid-wide synchronisation (an in-kernel fence
+// per workgroup costs far more on this chip than the boundary):
+//   spmm        AP = A P                       (stencil.hip)
+//   gram        per-workgroup P^T AP partials on the FP64 matrix cores
+//   reduce      the partials summed entry by entry, in index order
+//   factor      one 1024-thread workgroup: delta^+ and delta^+ C
+//   update_w    W = Q - AP delta^+ on the matrix cores, and the W^T W
+//               partials from the same registers (the 16x16 result layout is
+//               the operand layout of the FP64 Gram product)
+//   reduce
+//   factor      W^T W = S^T S, C <- S C, convergence test
+//   update_dqp  D += P delta^+ C, Q = W S^+, P = Q + P S^T
+//
+// The s x s factorisations are an LDL^T elimination of [G | I] without
+// pivoting in which a pivot below a relative threshold deactivates its index
+// (its row and column of every derived matrix are zero): one barrier per
+// pivot, every thread owning fixed entries.
 //
 // Storage: the N x s blocks are FP64 or FP32 (compute = BKO_F32); Gram
-// matrices, factorisations, the small matrices and the outer residual stay
-// FP64.  An outer loop forms R = B - A X in FP64, runs the block iteration
-// on A D = R, adds D to X, and stops when max_j ||r_j|| / ||b_j|| <= tol
-// (FP64 iterative refinement for the mixed-precision mode).
+// matrices, factorisations, small matrices and the outer residual are FP64.
+// An outer loop forms R = B - A X in FP64, runs the block iteration on
+// A D = R, adds D to X, and stops when max_j ||r_j|| / ||b_j|| <= tol (FP64
+// iterative refinement in the mixed-precision mode).
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.hpp"
@@ -31,391 +51,474 @@ namespace bko {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kGramThreads = 256;
-constexpr int kMaxParts = 128;   // Gram partials per product
-constexpr int kSmallThreads = 1024;
+constexpr int kThreads = 256;      // block kernels
+constexpr int kEpiThreads = 1024;  // factorisation kernel
 constexpr int kMaxS = 64;
+constexpr int kMaxBlocks = 512;    // partial producers per launch
+constexpr int kRedBlocks = 64;     // reducer workgroups
+constexpr int kTileRows = 256;     // rows per workgroup tile (4 waves x 64)
 
-// --------------------------------------------------------------- layout
+// ------------------------------------------------------------------ layout
 
-struct SmallLayout {
-    // doubles
-    size_t C, M1, M2, M3, M4, th, total_d;
-    // floats (after the doubles)
-    size_t M1f, M2f, M3f, M4f, total_f;
+enum Ctrl { kConverged = 0, kStop = 1, kIters = 2, kDeflated = 3, kAllDeflated = 4 };
+
+struct Small {
+    // FP64, row-major s x s: M[k][j] maps input column k to output column j
+    double *C, *M1, *M2, *M3, *M4, *th;
+    // FP32 copies for the FP32 block kernels
+    float *M1f, *M2f, *M3f, *M4f;
 };
 
-inline SmallLayout small_layout(int s)
-{
-    SmallLayout L{};
-    const size_t ss = static_cast<size_t>(s) * s;
-    size_t o = 0;
-    L.C = o; o += ss;
-    L.M1 = o; o += ss;
-    L.M2 = o; o += ss;
-    L.M3 = o; o += ss;
-    L.M4 = o; o += ss;
-    L.th = o; o += kMaxS;
-    L.total_d = align_up(o, 32);
-    size_t f = 0;
-    L.M1f = f; f += ss;
-    L.M2f = f; f += ss;
-    L.M3f = f; f += ss;
-    L.M4f = f; f += ss;
-    L.total_f = align_up(f, 64);
-    return L;
-}
-
-enum Ctrl { kDone = 0, kIters = 1, kDeflated = 2, kAllDeflated = 3, kNumCtrl = 64 };
-
 struct Workspace {
-    int64_t ldw;       // padded rows of every internal block
-    double *R64;       // outer residual, FP64
-    void *Dv, *Q, *P, *AP, *W;  // inner blocks in the compute storage type
-    double *parts;     // Gram partials [kMaxParts][s][s]
-    double *smalld;
-    float *smallf;
+    int64_t ldw;                 // padded rows of every internal block
+    double *R64;                 // outer residual, FP64
+    void *Dv, *Q, *P, *AP, *W;   // inner blocks in the storage type
+    Small sm;
+    double *parts;               // Gram partials [kMaxBlocks][s][s]
+    double *gram;                // reduced Gram [s][s]
     int *ctrl;
-    double *colparts;  // column-norm partials [kMaxParts][s]
+    double *colparts;            // column-norm partials [128][s]
     size_t bytes;
 };
 
 inline Workspace carve(void *base, int64_t n, int s, bko_dtype compute)
 {
     Workspace w{};
-    w.ldw = static_cast<int64_t>(align_up(static_cast<size_t>(n), 64));
+    w.ldw = static_cast<int64_t>(align_up(static_cast<size_t>(n), kTileRows));
     const size_t vsz = compute == BKO_F64 ? 8 : 4;
-    const size_t blk64 = align_up(sizeof(double) * w.ldw * s, 256);
-    const size_t blkv = align_up(vsz * w.ldw * s, 256);
-    const SmallLayout SL = small_layout(s);
+    const size_t ss = static_cast<size_t>(s) * s;
     char *p = static_cast<char *>(base);
     size_t o = 0;
-    w.R64 = reinterpret_cast<double *>(p + o); o += blk64;
-    w.Dv = p + o; o += blkv;
-    w.Q = p + o; o += blkv;
-    w.P = p + o; o += blkv;
-    w.AP = p + o; o += blkv;
-    w.W = p + o; o += blkv;
-    w.parts = reinterpret_cast<double *>(p + o); o += align_up(sizeof(double) * kMaxParts * s * s, 256);
-    w.smalld = reinterpret_cast<double *>(p + o); o += align_up(sizeof(double) * SL.total_d, 256);
-    w.smallf = reinterpret_cast<float *>(p + o); o += align_up(sizeof(float) * SL.total_f, 256);
-    w.ctrl = reinterpret_cast<int *>(p + o); o += 256;
-    w.colparts = reinterpret_cast<double *>(p + o); o += align_up(sizeof(double) * kMaxParts * kMaxS, 256);
+    auto take = [&](size_t bytes) {
+        char *q = p + o;
+        o = align_up(o + bytes, 256);
+        return q;
+    };
+    w.R64 = reinterpret_cast<double *>(take(sizeof(double) * w.ldw * s));
+    w.Dv = take(vsz * w.ldw * s);
+    w.Q = take(vsz * w.ldw * s);
+    w.P = take(vsz * w.ldw * s);
+    w.AP = take(vsz * w.ldw * s);
+    w.W = take(vsz * w.ldw * s);
+    w.sm.C = reinterpret_cast<double *>(take(sizeof(double) * ss));
+    w.sm.M1 = reinterpret_cast<double *>(take(sizeof(double) * ss));
+    w.sm.M2 = reinterpret_cast<double *>(take(sizeof(double) * ss));
+    w.sm.M3 = reinterpret_cast<double *>(take(sizeof(double) * ss));
+    w.sm.M4 = reinterpret_cast<double *>(take(sizeof(double) * ss));
+    w.sm.th = reinterpret_cast<double *>(take(sizeof(double) * kMaxS));
+    w.sm.M1f = reinterpret_cast<float *>(take(sizeof(float) * ss));
+    w.sm.M2f = reinterpret_cast<float *>(take(sizeof(float) * ss));
+    w.sm.M3f = reinterpret_cast<float *>(take(sizeof(float) * ss));
+    w.sm.M4f = reinterpret_cast<float *>(take(sizeof(float) * ss));
+    w.parts = reinterpret_cast<double *>(take(sizeof(double) * ss * kMaxBlocks));
+    w.gram = reinterpret_cast<double *>(take(sizeof(double) * ss));
+    w.ctrl = reinterpret_cast<int *>(take(sizeof(int) * 64));
+    w.colparts = reinterpret_cast<double *>(take(sizeof(double) * 128 * kMaxS));
     w.bytes = o;
     return w;
 }
 
-// --------------------------------------------------------------- Gram
+// ------------------------------------------------------------------ matrix-core helpers
 
-// parts[blockIdx.x] = U^T V over the rows owned by this workgroup, in FP64 on
-// the FP64 matrix cores.  U, V: ldw x s column-major, rows >= n are zero.
-template <class T, int NB, bool kSym>
-__global__ __launch_bounds__(kGramThreads) void gram_kernel(const T *__restrict__ U, const T *__restrict__ V,
-                                                            int64_t ldw, int s, int64_t rows_per_wg,
-                                                            double *__restrict__ parts, const int *__restrict__ ctrl)
+template <class T> struct MF;
+template <> struct MF<float> {
+    using V = f4;
+    static constexpr bool kF64 = false;
+    __device__ static inline V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+template <> struct MF<double> {
+    using V = d4;
+    static constexpr bool kF64 = true;
+    __device__ static inline V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+};
+
+__device__ inline d4 mma64(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+// index of the (a, b) upper block, a <= b < NB
+template <int NB> __device__ constexpr int ublock(int a, int b) { return a * NB - a * (a - 1) / 2 + (b - a); }
+
+// ------------------------------------------------------------------ Gram partials
+
+// Sum the four waves' 16x16 FP64 blocks into an s x s partial in LDS and
+// write it to parts[blockIdx.x].  kSym: only upper blocks were formed.
+template <int NB, bool kSym, int NBLK>
+__device__ void publish_partial(const d4 (&g)[NBLK], int s, double *lds, double *parts)
 {
-    if (ctrl && ctrl[kDone]) return;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int li = lane & 15;
-    const int lg = lane >> 4;
-    const int64_t r_begin = static_cast<int64_t>(blockIdx.x) * rows_per_wg;
-    const int64_t r_end = min(ldw, r_begin + rows_per_wg);
-    d4 acc[NB][NB];
-#pragma unroll
-    for (int a = 0; a < NB; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-
-    for (int64_t r0 = r_begin + wave * 16; r0 < r_end; r0 += 64) {
-        const int64_t row = r0 + lg * 4;
-        double u[NB][4], v[NB][4];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int col = b * 16 + li;
-            const bool ok = col < s;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                u[b][t] = ok ? static_cast<double>(U[static_cast<int64_t>(col) * ldw + row + t]) : 0.0;
-                if constexpr (!kSym) v[b][t] = ok ? static_cast<double>(V[static_cast<int64_t>(col) * ldw + row + t]) : 0.0;
-                else v[b][t] = u[b][t];
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int a = 0; a < NB; ++a)
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(u[a][t], v[b][t], acc[a][b], 0, 0, 0);
-    }
-    // reduce the four waves through LDS, then write this workgroup's partial
-    __shared__ double sh[kMaxS * kMaxS];
     const int ss = s * s;
-    for (int e = threadIdx.x; e < ss; e += kGramThreads) sh[e] = 0.0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    for (int e = threadIdx.x; e < ss; e += kThreads) lds[e] = 0.0;
     __syncthreads();
-    for (int w = 0; w < kGramThreads / 64; ++w) {
-        if (wave == w) {
+    for (int wv = 0; wv < kThreads / 64; ++wv) {
+        if (wave == wv) {
 #pragma unroll
             for (int a = 0; a < NB; ++a)
 #pragma unroll
-                for (int b = 0; b < NB; ++b)
+                for (int b = kSym ? a : 0; b < NB; ++b)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int i = a * 16 + mfma_row<true>(lg, r);
-                        const int j = b * 16 + li;
-                        if (i < s && j < s) sh[i * s + j] += acc[a][b][r];
+                        const int i = a * 16 + mfma_row<true>(lg, r), j = b * 16 + li;
+                        if (i < s && j < s) {
+                            const double v = kSym ? g[ublock<NB>(a, b)][r] : g[a * NB + b][r];
+                            lds[i * s + j] += v;
+                            if (kSym && a != b) lds[j * s + i] += v;
+                        }
                     }
         }
         __syncthreads();
     }
-    double *out = parts + static_cast<int64_t>(blockIdx.x) * ss;
-    for (int e = threadIdx.x; e < ss; e += kGramThreads) out[e] = sh[e];
+    double *out = parts + static_cast<size_t>(blockIdx.x) * ss;
+    for (int e = threadIdx.x; e < ss; e += kThreads) out[e] = lds[e];
 }
 
-// --------------------------------------------------------------- small dense FP64
-
-// Sum the Gram partials into G (LDS, s x s row-major).
-__device__ void reduce_parts(const double *__restrict__ parts, int nparts, int s, double *G)
+// P^T AP over this workgroup's row tiles.
+template <class T, int NB>
+__global__ __launch_bounds__(kThreads) void gram_kernel(const T *__restrict__ P, const T *__restrict__ AP, int64_t ldw,
+                                                        int s, double *__restrict__ parts, const int *__restrict__ ctrl)
 {
-    const int ss = s * s;
-    for (int e = threadIdx.x; e < ss; e += blockDim.x) {
-        double acc = 0.0;
-        for (int p = 0; p < nparts; ++p) acc += parts[static_cast<int64_t>(p) * ss + e];
-        G[e] = acc;
+    if (ctrl[kConverged]) return;
+    __shared__ double lds[kMaxS * kMaxS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t ntiles = ldw / kTileRows;
+    d4 acc[NB * NB];
+#pragma unroll
+    for (int q = 0; q < NB * NB; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        for (int rb = 0; rb < 4; ++rb) {
+            // rows row + t feed MFMA step t for lane group lg: any bijection of
+            // rows onto k slots works, since the product sums over rows
+            const int64_t row = tile * kTileRows + wave * 64 + rb * 16 + lg * 4;
+            double u[NB][4], v[NB][4];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int col = b * 16 + li;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    u[b][t] = col < s ? static_cast<double>(P[col * ldw + row + t]) : 0.0;
+                    v[b][t] = col < s ? static_cast<double>(AP[col * ldw + row + t]) : 0.0;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int a = 0; a < NB; ++a)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) acc[a * NB + b] = mma64(u[a][t], v[b][t], acc[a * NB + b]);
+        }
     }
-    __syncthreads();
+    publish_partial<NB, false>(acc, s, lds, parts);
 }
 
-// In-place masked Cholesky of the symmetric s x s matrix G (LDS): on return
-// the lower triangle holds L with G ~ L L^T on the active index set; a pivot
-// below rel_thr * max diag (or not finite) deactivates its index, whose
-// column of L is zero.  Returns the number of inactive indices (all threads).
-__device__ int masked_cholesky(double *G, int s, double rel_thr, int *active, double *scratch)
+// gram = sum over p < nparts of parts[p], entry by entry in index order.
+__global__ __launch_bounds__(kThreads) void gram_reduce_kernel(const double *__restrict__ parts, int nparts, int ss,
+                                                               double *__restrict__ gram, const int *__restrict__ ctrl)
 {
-    if (threadIdx.x == 0) {
-        double mx = 0.0;
-        for (int k = 0; k < s; ++k) mx = fmax(mx, G[k * s + k]);
-        scratch[0] = mx * rel_thr;
+    if (ctrl[kConverged]) return;
+    __shared__ double sh[kThreads];
+    const int per = (ss + gridDim.x - 1) / gridDim.x;  // entries of this workgroup (<= 64)
+    const int slices = kThreads / per;
+    const int tid = threadIdx.x;
+    const int le = tid % per, sl = tid / per;
+    const int e = blockIdx.x * per + le;
+    double a = 0.0;
+    if (sl < slices && e < ss) {
+        // slice sl sums partials sl, sl + slices, ... ; 8 loads in flight
+        for (int p0 = sl; p0 < nparts; p0 += 8 * slices) {
+            double v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int p = p0 + q * slices;
+                v[q] = p < nparts ? parts[static_cast<size_t>(p) * ss + e] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a += v[q];
+        }
     }
+    sh[tid] = a;
     __syncthreads();
-    const double thr = scratch[0];
+    if (sl == 0 && e < ss) {
+        double tot = 0.0;
+        for (int q = 0; q < slices; ++q) tot += sh[q * per + le];
+        gram[e] = tot;
+    }
+}
+
+// ------------------------------------------------------------------ factorisation (one workgroup)
+
+// LDL^T elimination of [G | I] held in A (s rows, row stride 2s), without
+// pivoting.  A pivot <= thr (or not finite) deactivates its index.  On
+// return, for active i: A[i][i] = d_i, A[i][j > i] = U (= d_i Lunit^T), and
+// the right half A[i][s + j] = E[i][j] with E = Lunit^{-1} (lower, unit).
+__device__ void ldl_eliminate(double *A, int s, double thr, int *active)
+{
+    const int w = 2 * s;
+    const int total = s * w;  // <= 8192: at most 8 entries per thread
+    int oi[8], oj[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int e = threadIdx.x + q * kEpiThreads;
+        oi[q] = e < total ? e / w : -1;
+        oj[q] = e < total ? e % w : 0;
+    }
     for (int k = 0; k < s; ++k) {
-        if (threadIdx.x == 0) {
-            const double piv = G[k * s + k];
-            const bool act = piv > thr && piv > 0.0 && isfinite(piv);
-            active[k] = act ? 1 : 0;
-            const double lkk = act ? sqrt(piv) : 0.0;
-            G[k * s + k] = lkk;
-            scratch[1] = act ? 1.0 / lkk : 0.0;
+        const double p = A[k * w + k];
+        const bool act = p > thr && isfinite(p);
+        if (act) {
+            const double inv = 1.0 / p;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int i = oi[q], j = oj[q];
+                if (i > k && ((j > k && j < s) || (j >= s && j <= s + k))) A[i * w + j] -= A[i * w + k] * inv * A[k * w + j];
+            }
         }
-        __syncthreads();
-        const double inv = scratch[1];
-        for (int i = k + 1 + threadIdx.x; i < s; i += blockDim.x) G[i * s + k] *= inv;
-        __syncthreads();
-        const int m = s - k - 1;
-        for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-            const int i = k + 1 + e / m;
-            const int j = k + 1 + e % m;
-            if (j <= i) G[i * s + j] -= G[i * s + k] * G[j * s + k];
-        }
+        if (threadIdx.x == 0) active[k] = act ? 1 : 0;
         __syncthreads();
     }
-    // clear the strict upper triangle
-    for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
-        const int i = e / s, j = e % s;
-        if (j > i) G[e] = 0.0;
+}
+
+// Factor the reduced Gram.  mode 0: delta -> M2 = delta^+, M1 = delta^+ C.
+// mode 1 / 2: W^T W -> S = D^{1/2} Lunit^T, Linv = D^{-1/2} E; C <- S C;
+// M3[k][j] = Linv[j][k] (Q = W S^+), M4[k][j] = S[j][k] (P = Q + P S^T);
+// converged when ||C e_j|| <= th_j for every column (mode 2 is the first QR
+// of the residual and is not counted as an iteration).
+__global__ __launch_bounds__(kEpiThreads) void factor_kernel(const double *__restrict__ gram, int s, double rel_thr,
+                                                             Small sm, int *ctrl, int mode)
+{
+    if (ctrl[kConverged]) return;
+    extern __shared__ __align__(16) double lds[];
+    const int ss = s * s, w = 2 * s;
+    double *A = lds;            // s x 2s
+    double *G = lds + 2 * ss;   // s x s scratch
+    double *Cl = lds + 3 * ss;  // C
+    __shared__ int active[kMaxS];
+    __shared__ double dv[kMaxS];
+    __shared__ double thl[kMaxS];
+    __shared__ double gmax;
+    __shared__ int notconv;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < s * w; e += kEpiThreads) {
+        const int i = e / w, j = e % w;
+        A[e] = j < s ? 0.5 * (gram[i * s + j] + gram[j * s + i]) : (j - s == i ? 1.0 : 0.0);
+    }
+    for (int e = tid; e < ss; e += kEpiThreads) Cl[e] = sm.C[e];
+    for (int j = tid; j < s; j += kEpiThreads) thl[j] = sm.th[j];
+    if (tid == 0) notconv = 0;
+    __syncthreads();
+    if (tid == 0) {
+        double mx = 0.0;
+        for (int k = 0; k < s; ++k) mx = fmax(mx, A[k * w + k]);
+        gmax = mx;
     }
     __syncthreads();
+    ldl_eliminate(A, s, rel_thr * gmax, active);
     int inactive = 0;
     for (int k = 0; k < s; ++k) inactive += active[k] ? 0 : 1;
-    return inactive;
-}
-
-// Li = L^+ (inverse on the active set, zero elsewhere), L lower triangular.
-__device__ void masked_lower_inverse(const double *L, int s, const int *active, double *Li)
-{
-    for (int j = threadIdx.x; j < s; j += blockDim.x) {
-        for (int i = 0; i < s; ++i) {
-            double v = 0.0;
-            if (i >= j && active[i] && active[j]) {
-                v = (i == j) ? 1.0 : 0.0;
-                for (int k = j; k < i; ++k) v -= L[i * s + k] * Li[k * s + j];
-                v /= L[i * s + i];
-            }
-            Li[i * s + j] = v;
+    if (mode == 0) {
+        for (int k = tid; k < s; k += kEpiThreads) dv[k] = active[k] ? 1.0 / A[k * w + k] : 0.0;
+        __syncthreads();
+        // delta^+[i][j] = sum_{k >= max(i,j)} E[k][i] E[k][j] / d_k over active k
+        for (int e = tid; e < ss; e += kEpiThreads) {
+            const int i = e / s, j = e % s;
+            double acc = 0.0;
+            for (int k = max(i, j); k < s; ++k) acc += A[k * w + s + i] * A[k * w + s + j] * dv[k];
+            G[e] = acc;
+            sm.M2[e] = acc;
+            sm.M2f[e] = static_cast<float>(acc);
         }
+        __syncthreads();
+        for (int e = tid; e < ss; e += kEpiThreads) {
+            const int i = e / s, j = e % s;
+            double m1 = 0.0;
+            for (int k = 0; k <= j; ++k) m1 += G[i * s + k] * Cl[k * s + j];  // C upper triangular
+            sm.M1[e] = m1;
+            sm.M1f[e] = static_cast<float>(m1);
+        }
+        return;
     }
+    for (int i = tid; i < s; i += kEpiThreads) dv[i] = active[i] ? 1.0 / sqrt(A[i * w + i]) : 0.0;
     __syncthreads();
-}
-
-// Store M (row-major s x s in LDS) transposed into global FP64 and FP32:
-// out[j * s + k] = M[k][j], the layout the block-update kernels read.
-__device__ void store_t(const double *M, int s, double *outd, float *outf)
-{
-    for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
-        const int j = e / s, k = e % s;
-        const double v = M[k * s + j];
-        outd[e] = v;
-        outf[e] = static_cast<float>(v);
-    }
-}
-
-// After delta = P^T AP: M1 = delta^+ C (for D += P M1), M2 = delta^+ (for
-// W = Q - AP M2).
-__global__ __launch_bounds__(kSmallThreads) void small_alpha_kernel(const double *__restrict__ parts, int nparts,
-                                                                    int s, double rel_thr, double *smalld,
-                                                                    float *smallf, int *ctrl, SmallLayout SL)
-{
-    if (ctrl[kDone]) return;
-    __shared__ double G[kMaxS * kMaxS];
-    __shared__ double Li[kMaxS * kMaxS];
-    __shared__ int active[kMaxS];
-    __shared__ double scratch[4];
-    reduce_parts(parts, nparts, s, G);
-    masked_cholesky(G, s, rel_thr, active, scratch);
-    masked_lower_inverse(G, s, active, Li);
-    // E = Li^T Li  (into G: L is no longer needed)
-    for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
+    // S[i][j] = U[i][j] dv[i] (j >= i);  Cn = S C into G
+    for (int e = tid; e < ss; e += kEpiThreads) {
         const int i = e / s, j = e % s;
         double acc = 0.0;
-        for (int k = max(i, j); k < s; ++k) acc += Li[k * s + i] * Li[k * s + j];
-        G[e] = acc;
+        for (int k = i; k <= j; ++k) acc += A[i * w + k] * Cl[k * s + j];
+        G[e] = acc * dv[i];
+        const int kk = i, jj = j;  // reuse e as (k, j) for M3 / M4
+        const double m3 = kk <= jj ? A[jj * w + s + kk] * dv[jj] : 0.0;
+        const double m4 = kk >= jj ? A[jj * w + kk] * dv[jj] : 0.0;
+        sm.M3[e] = m3;
+        sm.M3f[e] = static_cast<float>(m3);
+        sm.M4[e] = m4;
+        sm.M4f[e] = static_cast<float>(m4);
     }
     __syncthreads();
-    store_t(G, s, smalld + SL.M2, smallf + SL.M2f);
-    // M1 = E C (C upper triangular), into Li
-    const double *C = smalld + SL.C;
-    for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
-        const int i = e / s, j = e % s;
-        double acc = 0.0;
-        for (int k = 0; k <= j; ++k) acc += G[i * s + k] * C[k * s + j];
-        Li[e] = acc;
-    }
-    __syncthreads();
-    store_t(Li, s, smalld + SL.M1, smallf + SL.M1f);
-}
-
-// After W^T W: L = chol, S = L^T, C <- S C, Q = W S^+ (M3 = S^+), P = Q + P S^T
-// (M4 = S^T = L); convergence when ||C e_j|| <= th_j for every column.
-// With count == 0 this is the initial QR of the residual (C = I on entry).
-__global__ __launch_bounds__(kSmallThreads) void small_beta_kernel(const double *__restrict__ parts, int nparts,
-                                                                   int s, double rel_thr, double *smalld,
-                                                                   float *smallf, int *ctrl, SmallLayout SL,
-                                                                   int count)
-{
-    if (ctrl[kDone]) return;
-    __shared__ double G[kMaxS * kMaxS];
-    __shared__ double Li[kMaxS * kMaxS];
-    __shared__ int active[kMaxS];
-    __shared__ double scratch[4];
-    __shared__ int notconv;
-    reduce_parts(parts, nparts, s, G);
-    const int inactive = masked_cholesky(G, s, rel_thr, active, scratch);
-    masked_lower_inverse(G, s, active, Li);
-    // M3 = S^+ = Li^T, stored transposed: out[j][k] = M3[k][j] = Li[j][k]
-    // M4 = S^T = L,    stored transposed: out[j][k] = M4[k][j] = L[k][j]
-    for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
-        const int j = e / s, k = e % s;
-        const double v3 = Li[e];
-        const double v4 = G[k * s + j];
-        smalld[SL.M3 + e] = v3;
-        smallf[SL.M3f + e] = static_cast<float>(v3);
-        smalld[SL.M4 + e] = v4;
-        smallf[SL.M4f + e] = static_cast<float>(v4);
-    }
-    __syncthreads();
-    // Cn = L^T C (both upper triangular), into Li
-    double *C = smalld + SL.C;
-    for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
-        const int i = e / s, j = e % s;
-        double acc = 0.0;
-        for (int k = i; k <= j; ++k) acc += G[k * s + i] * C[k * s + j];
-        Li[e] = acc;
-    }
-    if (threadIdx.x == 0) notconv = 0;
-    __syncthreads();
-    for (int j = threadIdx.x; j < s; j += blockDim.x) {
+    for (int j = tid; j < s; j += kEpiThreads) {
         double nrm2 = 0.0;
-        for (int i = 0; i <= j; ++i) nrm2 += Li[i * s + j] * Li[i * s + j];
-        if (!(sqrt(nrm2) <= smalld[SL.th + j])) atomicAdd(&notconv, 1);
+        for (int i = 0; i <= j; ++i) nrm2 += G[i * s + j] * G[i * s + j];
+        if (!(sqrt(nrm2) <= thl[j])) atomicAdd(&notconv, 1);
     }
+    for (int e = tid; e < ss; e += kEpiThreads) sm.C[e] = G[e];
     __syncthreads();
-    for (int e = threadIdx.x; e < s * s; e += blockDim.x) C[e] = Li[e];
-    if (threadIdx.x == 0) {
-        ctrl[kIters] += count;
+    if (tid == 0) {
+        ctrl[kIters] += mode == 1 ? 1 : 0;
         ctrl[kDeflated] = inactive;
         if (inactive == s) ctrl[kAllDeflated] = 1;
-        if (notconv == 0 || inactive == s) ctrl[kDone] = 1;
+        if (notconv == 0 || inactive == s) ctrl[kConverged] = 1;
     }
 }
 
-// --------------------------------------------------------------- block updates
+// ------------------------------------------------------------------ block updates
 
-// One thread per row; the s x s matrices are read as wave-uniform values.
-// D += P M1 ;  W = Q - AP M2
-template <class T, int SM>
-__global__ __launch_bounds__(256) void update_xw_kernel(int64_t n, int64_t ldw, int s, T *__restrict__ D,
-                                                        const T *__restrict__ P, const T *__restrict__ Q,
-                                                        const T *__restrict__ AP, T *__restrict__ W,
-                                                        const T *__restrict__ M1t, const T *__restrict__ M2t,
-                                                        const int *__restrict__ ctrl)
+// W = Q - AP M2 (matrix cores in the storage precision) and the W^T W
+// partials from the same registers.  With init != 0, W already holds the
+// residual and only its Gram is formed.
+template <class T, int NB>
+__global__ __launch_bounds__(kThreads) void update_w_kernel(const T *__restrict__ Q, const T *__restrict__ AP,
+                                                            T *__restrict__ W, const T *__restrict__ M2g, int64_t ldw,
+                                                            int s, double *__restrict__ parts, const int *__restrict__ ctrl,
+                                                            int init)
 {
-    if (ctrl[kDone]) return;
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    T p[SM], ap[SM];
-#pragma unroll
-    for (int k = 0; k < SM; ++k) {
-        p[k] = k < s ? P[k * ldw + r] : T(0);
-        ap[k] = k < s ? AP[k * ldw + r] : T(0);
+    if (ctrl[kConverged]) return;
+    using V = typename MF<T>::V;
+    constexpr bool kF64 = MF<T>::kF64;
+    constexpr int KS = 4 * NB;  // k steps of 4 over the padded width 16 NB
+    constexpr int SP = 16 * NB;
+    constexpr int MST = SP + 1;
+    __shared__ T Ms[SP * MST];  // -M2
+    __shared__ double lds[kMaxS * kMaxS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    if (!init) {
+        for (int e = threadIdx.x; e < SP * MST; e += kThreads) {
+            const int k = e / MST, j = e % MST;
+            Ms[e] = (k < s && j < s) ? -M2g[k * s + j] : T(0);
+        }
+        __syncthreads();
     }
-    for (int j = 0; j < s; ++j) {
-        T a1 = 0, a2 = 0;
+    d4 g[NB * (NB + 1) / 2];
 #pragma unroll
-        for (int k = 0; k < SM; ++k) {
-            if (k < s) {
-                a1 += p[k] * M1t[j * s + k];
-                a2 += ap[k] * M2t[j * s + k];
+    for (int q = 0; q < NB * (NB + 1) / 2; ++q) g[q] = d4{0.0, 0.0, 0.0, 0.0};
+    const int64_t ntiles = ldw / kTileRows;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        for (int rb = 0; rb < 4; ++rb) {
+            const int64_t r0 = tile * kTileRows + wave * 64 + rb * 16;
+            T a[KS];
+            if (!init) {
+#pragma unroll
+                for (int t = 0; t < KS; ++t) {
+                    const int col = 4 * t + lg;
+                    a[t] = col < s ? AP[col * ldw + r0 + li] : T(0);
+                }
+            }
+            V wv[NB];
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+                const int colj = jb * 16 + li;
+                V acc;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = r0 + mfma_row<kF64>(lg, r);
+                    acc[r] = colj < s ? (init ? W[colj * ldw + row] : Q[colj * ldw + row]) : T(0);
+                }
+                if (!init) {
+#pragma unroll
+                    for (int t = 0; t < KS; ++t) acc = MF<T>::mma(a[t], Ms[(4 * t + lg) * MST + colj], acc);
+                    if (colj < s) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) W[colj * ldw + r0 + mfma_row<kF64>(lg, r)] = acc[r];
+                    }
+                }
+                wv[jb] = acc;
+            }
+            // W^T W: result register r of lane group lg holds row
+            // mfma_row(lg, r) of the block -- the k slot lg of an FP64 step
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int ab = 0; ab < NB; ++ab)
+#pragma unroll
+                    for (int bb = ab; bb < NB; ++bb)
+                        g[ublock<NB>(ab, bb)] = mma64(static_cast<double>(wv[ab][r]), static_cast<double>(wv[bb][r]),
+                                                      g[ublock<NB>(ab, bb)]);
+        }
+    }
+    publish_partial<NB, true>(g, s, lds, parts);
+}
+
+// D += P M1 ;  Q = W M3 ;  P = Q + P M4   (matrix cores, storage precision)
+template <class T, int NB>
+__global__ __launch_bounds__(kThreads) void update_dqp_kernel(T *__restrict__ D, T *__restrict__ P, T *__restrict__ Q,
+                                                              const T *__restrict__ W, const T *__restrict__ M1g,
+                                                              const T *__restrict__ M3g, const T *__restrict__ M4g,
+                                                              int64_t ldw, int s, const int *__restrict__ ctrl)
+{
+    if (ctrl[kStop]) return;
+    using V = typename MF<T>::V;
+    constexpr bool kF64 = MF<T>::kF64;
+    constexpr int KS = 4 * NB;
+    constexpr int SP = 16 * NB;
+    constexpr int MST = SP + 1;
+    extern __shared__ __align__(16) double lds[];
+    T *M1 = reinterpret_cast<T *>(lds);
+    T *M3 = M1 + SP * MST;
+    T *M4 = M3 + SP * MST;
+    for (int e = threadIdx.x; e < SP * MST; e += kThreads) {
+        const int k = e / MST, j = e % MST;
+        const bool ok = k < s && j < s;
+        M1[e] = ok ? M1g[k * s + j] : T(0);
+        M3[e] = ok ? M3g[k * s + j] : T(0);
+        M4[e] = ok ? M4g[k * s + j] : T(0);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t ntiles = ldw / kTileRows;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        for (int rb = 0; rb < 4; ++rb) {
+            const int64_t r0 = tile * kTileRows + wave * 64 + rb * 16;
+            T pa[KS], wa[KS];
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+                const int col = 4 * t + lg;
+                pa[t] = col < s ? P[col * ldw + r0 + li] : T(0);
+                wa[t] = col < s ? W[col * ldw + r0 + li] : T(0);
+            }
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+                const int colj = jb * 16 + li;
+                V ad, aq;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    ad[r] = colj < s ? D[colj * ldw + r0 + mfma_row<kF64>(lg, r)] : T(0);
+                    aq[r] = T(0);
+                }
+#pragma unroll
+                for (int t = 0; t < KS; ++t) {
+                    const int k = 4 * t + lg;
+                    ad = MF<T>::mma(pa[t], M1[k * MST + colj], ad);
+                    aq = MF<T>::mma(wa[t], M3[k * MST + colj], aq);
+                }
+                V ap = aq;
+#pragma unroll
+                for (int t = 0; t < KS; ++t) ap = MF<T>::mma(pa[t], M4[(4 * t + lg) * MST + colj], ap);
+                if (colj < s) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t idx = colj * ldw + r0 + mfma_row<kF64>(lg, r);
+                        D[idx] = ad[r];
+                        Q[idx] = aq[r];
+                        P[idx] = ap[r];
+                    }
+                }
             }
         }
-        D[j * ldw + r] += a1;
-        W[j * ldw + r] = Q[j * ldw + r] - a2;
     }
 }
 
-// Q = W M3 ; P = Q + P M4   (M3 upper, M4 lower triangular)
-template <class T, int SM>
-__global__ __launch_bounds__(256) void update_qp_kernel(int64_t n, int64_t ldw, int s, const T *__restrict__ W,
-                                                        T *__restrict__ Q, T *__restrict__ P,
-                                                        const T *__restrict__ M3t, const T *__restrict__ M4t,
-                                                        const int *__restrict__ ctrl)
-{
-    if (ctrl[kDone]) return;
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    T w[SM], p[SM];
-#pragma unroll
-    for (int k = 0; k < SM; ++k) {
-        w[k] = k < s ? W[k * ldw + r] : T(0);
-        p[k] = k < s ? P[k * ldw + r] : T(0);
-    }
-    for (int j = 0; j < s; ++j) {
-        T q = 0, pp = 0;
-#pragma unroll
-        for (int k = 0; k < SM; ++k) {
-            if (k < s) {
-                if (k <= j) q += w[k] * M3t[j * s + k];
-                if (k >= j) pp += p[k] * M4t[j * s + k];
-            }
-        }
-        Q[j * ldw + r] = q;
-        P[j * ldw + r] = q + pp;
-    }
-}
-
-// --------------------------------------------------------------- misc kernels
+// ------------------------------------------------------------------ misc kernels
 
 // colparts[chunk * s + j] = sum over the chunk of column j squared (FP64).
 __global__ __launch_bounds__(256) void colnorm_kernel(const double *__restrict__ A, int64_t lda, int64_t n, int s,
@@ -472,66 +575,73 @@ __global__ void set_identity_kernel(double *C, int s)
     for (int e = threadIdx.x; e < s * s; e += blockDim.x) C[e] = (e / s == e % s) ? 1.0 : 0.0;
 }
 
-// --------------------------------------------------------------- driver
+// ------------------------------------------------------------------ host side
 
-template <class T>
-struct Inner {
-    static constexpr bool kF64 = sizeof(T) == 8;
-};
+inline int nb_for(int s) { return (s + 15) / 16; }
 
-inline int sm_for(int s) { return s <= 8 ? 8 : s <= 16 ? 16 : s <= 32 ? 32 : 64; }
-
-template <class T>
-bko_status launch_gram(const T *U, const T *V, int64_t ldw, int s, double *parts, int nparts,
-                       const int *ctrl, hipStream_t st)
+inline unsigned grid_for(int64_t ldw)
 {
-    const int64_t rows = static_cast<int64_t>(align_up(static_cast<size_t>((ldw + nparts - 1) / nparts), 64));
-    const int nb = (s + 15) / 16;
-    const bool sym = U == V;
-    TimedLaunch tl(kGram, st);
-#define BKO_GRAM(NB)                                                                                          \
-    if (sym) hipLaunchKernelGGL((gram_kernel<T, NB, true>), dim3(nparts), dim3(kGramThreads), 0, st, U, V, ldw, \
-                                s, rows, parts, ctrl);                                                        \
-    else hipLaunchKernelGGL((gram_kernel<T, NB, false>), dim3(nparts), dim3(kGramThreads), 0, st, U, V, ldw, s, \
-                            rows, parts, ctrl);
-    if (nb == 1) { BKO_GRAM(1) }
-    else if (nb == 2) { BKO_GRAM(2) }
-    else if (nb == 3) { BKO_GRAM(3) }
-    else { BKO_GRAM(4) }
-#undef BKO_GRAM
-    BKO_HIP(hipGetLastError());
-    return BKO_OK;
+    return static_cast<unsigned>(std::min<int64_t>(ldw / kTileRows, kMaxBlocks));
 }
 
-template <class T>
-bko_status launch_update_xw(int64_t n, int64_t ldw, int s, T *D, const T *P, const T *Q, const T *AP, T *W,
-                            const T *M1t, const T *M2t, const int *ctrl, hipStream_t st)
+enum Step { kGramStep = 0, kUpdateW = 1, kUpdateDQP = 2 };
+
+template <class T, int NB>
+bko_status launch_block_kernel(Step which, const Workspace &ws, int s, int init, hipStream_t st)
 {
-    const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
-    TimedLaunch tl(kUpdate, st);
-    switch (sm_for(s)) {
-    case 8: hipLaunchKernelGGL((update_xw_kernel<T, 8>), dim3(blocks), dim3(256), 0, st, n, ldw, s, D, P, Q, AP, W, M1t, M2t, ctrl); break;
-    case 16: hipLaunchKernelGGL((update_xw_kernel<T, 16>), dim3(blocks), dim3(256), 0, st, n, ldw, s, D, P, Q, AP, W, M1t, M2t, ctrl); break;
-    case 32: hipLaunchKernelGGL((update_xw_kernel<T, 32>), dim3(blocks), dim3(256), 0, st, n, ldw, s, D, P, Q, AP, W, M1t, M2t, ctrl); break;
-    default: hipLaunchKernelGGL((update_xw_kernel<T, 64>), dim3(blocks), dim3(256), 0, st, n, ldw, s, D, P, Q, AP, W, M1t, M2t, ctrl); break;
+    const int64_t ldw = ws.ldw;
+    const unsigned grid = grid_for(ldw);
+    const bool f64 = sizeof(T) == 8;
+    T *Dv = static_cast<T *>(ws.Dv), *Q = static_cast<T *>(ws.Q), *P = static_cast<T *>(ws.P);
+    T *AP = static_cast<T *>(ws.AP), *W = static_cast<T *>(ws.W);
+    const T *M1 = f64 ? reinterpret_cast<const T *>(ws.sm.M1) : reinterpret_cast<const T *>(ws.sm.M1f);
+    const T *M2 = f64 ? reinterpret_cast<const T *>(ws.sm.M2) : reinterpret_cast<const T *>(ws.sm.M2f);
+    const T *M3 = f64 ? reinterpret_cast<const T *>(ws.sm.M3) : reinterpret_cast<const T *>(ws.sm.M3f);
+    const T *M4 = f64 ? reinterpret_cast<const T *>(ws.sm.M4) : reinterpret_cast<const T *>(ws.sm.M4f);
+    const int sp = 16 * NB;
+    const size_t mbytes = sizeof(T) * sp * (sp + 1);
+    if (which == kGramStep) {
+        TimedLaunch tl(kGram, st);
+        hipLaunchKernelGGL((gram_kernel<T, NB>), dim3(grid), dim3(kThreads), 0, st, P, AP, ldw, s, ws.parts, ws.ctrl);
+    } else if (which == kUpdateW) {
+        TimedLaunch tl(kUpdate, st);
+        hipLaunchKernelGGL((update_w_kernel<T, NB>), dim3(grid), dim3(kThreads), 0, st, Q, AP, W, M2, ldw, s, ws.parts,
+                           ws.ctrl, init);
+    } else {
+        TimedLaunch tl(kUpdate, st);
+        hipLaunchKernelGGL((update_dqp_kernel<T, NB>), dim3(grid), dim3(kThreads), 3 * mbytes, st, Dv, P, Q, W, M1, M3,
+                           M4, ldw, s, ws.ctrl);
     }
     BKO_HIP(hipGetLastError());
     return BKO_OK;
 }
 
 template <class T>
-bko_status launch_update_qp(int64_t n, int64_t ldw, int s, const T *W, T *Q, T *P, const T *M3t, const T *M4t,
-                            const int *ctrl, hipStream_t st)
+bko_status launch_block(Step which, const Workspace &ws, int s, int init, hipStream_t st)
 {
-    const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
-    TimedLaunch tl(kUpdate, st);
-    switch (sm_for(s)) {
-    case 8: hipLaunchKernelGGL((update_qp_kernel<T, 8>), dim3(blocks), dim3(256), 0, st, n, ldw, s, W, Q, P, M3t, M4t, ctrl); break;
-    case 16: hipLaunchKernelGGL((update_qp_kernel<T, 16>), dim3(blocks), dim3(256), 0, st, n, ldw, s, W, Q, P, M3t, M4t, ctrl); break;
-    case 32: hipLaunchKernelGGL((update_qp_kernel<T, 32>), dim3(blocks), dim3(256), 0, st, n, ldw, s, W, Q, P, M3t, M4t, ctrl); break;
-    default: hipLaunchKernelGGL((update_qp_kernel<T, 64>), dim3(blocks), dim3(256), 0, st, n, ldw, s, W, Q, P, M3t, M4t, ctrl); break;
+    switch (nb_for(s)) {
+    case 1: return launch_block_kernel<T, 1>(which, ws, s, init, st);
+    case 2: return launch_block_kernel<T, 2>(which, ws, s, init, st);
+    case 3: return launch_block_kernel<T, 3>(which, ws, s, init, st);
+    default: return launch_block_kernel<T, 4>(which, ws, s, init, st);
     }
-    BKO_HIP(hipGetLastError());
+}
+
+// reduce the partials of the last Gram step, then factor (mode as factor_kernel)
+bko_status launch_reduce_factor(const Workspace &ws, int s, double rel_thr, int mode, hipStream_t st)
+{
+    const int ss = s * s;
+    const unsigned nparts = grid_for(ws.ldw);
+    const unsigned rblocks = static_cast<unsigned>(std::min(kRedBlocks, ss));
+    {
+        TimedLaunch tl(kSmall, st);
+        hipLaunchKernelGGL(gram_reduce_kernel, dim3(rblocks), dim3(kThreads), 0, st, ws.parts, static_cast<int>(nparts),
+                           ss, ws.gram, ws.ctrl);
+        BKO_HIP(hipGetLastError());
+        hipLaunchKernelGGL(factor_kernel, dim3(1), dim3(kEpiThreads), sizeof(double) * 4 * ss, st, ws.gram, s, rel_thr,
+                           ws.sm, ws.ctrl, mode);
+        BKO_HIP(hipGetLastError());
+    }
     return BKO_OK;
 }
 
@@ -539,7 +649,7 @@ bko_status launch_update_qp(int64_t n, int64_t ldw, int s, const T *W, T *Q, T *
 bko_status host_colnorms(const double *A, int64_t lda, int64_t n, int s, double *colparts, std::vector<double> &out,
                          hipStream_t st)
 {
-    const int chunks = static_cast<int>(std::min<int64_t>(kMaxParts, (n + 4095) / 4096));
+    const int chunks = static_cast<int>(std::min<int64_t>(128, (n + 4095) / 4096));
     const int64_t rows = (n + chunks - 1) / chunks;
     hipLaunchKernelGGL(colnorm_kernel, dim3(chunks, s), dim3(256), 0, st, A, lda, n, s, rows, colparts);
     BKO_HIP(hipGetLastError());
@@ -554,49 +664,40 @@ bko_status host_colnorms(const double *A, int64_t lda, int64_t n, int s, double 
 }
 
 // Inner block iteration on A D = R (R = ws.R64, FP64), storage type T.
-// th: per-column absolute residual targets.  Returns iterations taken.
+// th: per-column absolute residual targets.
 template <class T>
 bko_status inner_solve(const Operator &op, int s, const Workspace &ws, const std::vector<double> &th, int budget,
                        int &iters_out, int &deflated_out, bool &all_deflated, hipStream_t st)
 {
     const int64_t n = op.n, ldw = ws.ldw;
-    const SmallLayout SL = small_layout(s);
     const bool f64 = sizeof(T) == 8;
     const double rel_thr = f64 ? 1e-13 : 1e-12;
-    const int nparts = static_cast<int>(std::min<int64_t>(kMaxParts, std::max<int64_t>(1, ldw / 1024)));
-    T *Dv = static_cast<T *>(ws.Dv), *Q = static_cast<T *>(ws.Q), *P = static_cast<T *>(ws.P);
-    T *AP = static_cast<T *>(ws.AP), *W = static_cast<T *>(ws.W);
-    const T *M1t = f64 ? reinterpret_cast<const T *>(ws.smalld + SL.M1) : reinterpret_cast<const T *>(ws.smallf + SL.M1f);
-    const T *M2t = f64 ? reinterpret_cast<const T *>(ws.smalld + SL.M2) : reinterpret_cast<const T *>(ws.smallf + SL.M2f);
-    const T *M3t = f64 ? reinterpret_cast<const T *>(ws.smalld + SL.M3) : reinterpret_cast<const T *>(ws.smallf + SL.M3f);
-    const T *M4t = f64 ? reinterpret_cast<const T *>(ws.smalld + SL.M4) : reinterpret_cast<const T *>(ws.smallf + SL.M4f);
     const size_t blkv = sizeof(T) * static_cast<size_t>(ldw) * s;
+    const size_t ss = static_cast<size_t>(s) * s;
     bko_status rc;
 
-    // fresh state: blocks zero (padding rows stay zero for the Gram), C = I
+    // fresh state: blocks zero (padding rows stay zero), C = I, M1 = 0
     for (void *b : {ws.Dv, ws.Q, ws.P, ws.AP, ws.W})
         if ((rc = launch_zero(b, blkv, st)) != BKO_OK) return rc;
-    if ((rc = launch_zero(ws.ctrl, 256, st)) != BKO_OK) return rc;
-    hipLaunchKernelGGL(set_identity_kernel, dim3(1), dim3(256), 0, st, ws.smalld + SL.C, s);
+    if ((rc = launch_zero(ws.ctrl, sizeof(int) * 64, st)) != BKO_OK) return rc;
+    if ((rc = launch_zero(ws.sm.M1, sizeof(double) * ss, st)) != BKO_OK) return rc;
+    if ((rc = launch_zero(ws.sm.M1f, sizeof(float) * ss, st)) != BKO_OK) return rc;
+    hipLaunchKernelGGL(set_identity_kernel, dim3(1), dim3(256), 0, st, ws.sm.C, s);
     BKO_HIP(hipGetLastError());
     std::vector<double> thp(kMaxS, 0.0);
     std::copy(th.begin(), th.end(), thp.begin());
-    BKO_HIP(hipMemcpyAsync(ws.smalld + SL.th, thp.data(), sizeof(double) * kMaxS, hipMemcpyHostToDevice, st));
+    BKO_HIP(hipMemcpyAsync(ws.sm.th, thp.data(), sizeof(double) * kMaxS, hipMemcpyHostToDevice, st));
     const unsigned rblocks = static_cast<unsigned>((n + 255) / 256);
-    hipLaunchKernelGGL((cast_in_kernel<T>), dim3(rblocks), dim3(256), 0, st, ws.R64, ldw, W, ldw, n, s);
+    hipLaunchKernelGGL((cast_in_kernel<T>), dim3(rblocks), dim3(256), 0, st, ws.R64, ldw, static_cast<T *>(ws.W), ldw,
+                       n, s);
     BKO_HIP(hipGetLastError());
-    // initial QR of the residual: W = Q C
-    if ((rc = launch_gram<T>(W, W, ldw, s, ws.parts, nparts, ws.ctrl, st)) != BKO_OK) return rc;
-    {
-        TimedLaunch tl(kSmall, st);
-        hipLaunchKernelGGL(small_beta_kernel, dim3(1), dim3(kSmallThreads), 0, st, ws.parts, nparts, s, rel_thr,
-                           ws.smalld, ws.smallf, ws.ctrl, SL, 0);
-    }
-    BKO_HIP(hipGetLastError());
-    if ((rc = launch_update_qp<T>(n, ldw, s, W, Q, P, M3t, M4t, ws.ctrl, st)) != BKO_OK) return rc;
+    // first QR of the residual, then Q = W S^+, P = Q (P is zero), D = 0 (M1 = 0)
+    if ((rc = launch_block<T>(kUpdateW, ws, s, 1, st)) != BKO_OK) return rc;
+    if ((rc = launch_reduce_factor(ws, s, rel_thr, 2, st)) != BKO_OK) return rc;
+    if ((rc = launch_block<T>(kUpdateDQP, ws, s, 0, st)) != BKO_OK) return rc;
 
     const bko_dtype vt = f64 ? BKO_F64 : BKO_F32;
-    int h_ctrl[4] = {0, 0, 0, 0};
+    int h_ctrl[8] = {0};
     int launched = 0;
     int chunk = 4;
     while (true) {
@@ -604,36 +705,25 @@ bko_status inner_solve(const Operator &op, int s, const Workspace &ws, const std
         for (int it = 0; it < todo; ++it) {
             {
                 TimedLaunch tl(kSpmm, st);
-                if ((rc = launch_stencil(op, s, P, ldw, vt, AP, ldw, vt, vt, nullptr, 0, st, ws.ctrl)) != BKO_OK)
+                if ((rc = launch_stencil(op, s, ws.P, ldw, vt, ws.AP, ldw, vt, vt, nullptr, 0, st, ws.ctrl + kConverged,
+                                         ws.ctrl + kStop)) != BKO_OK)
                     return rc;
             }
-            if ((rc = launch_gram<T>(P, AP, ldw, s, ws.parts, nparts, ws.ctrl, st)) != BKO_OK) return rc;
-            {
-                TimedLaunch tl(kSmall, st);
-                hipLaunchKernelGGL(small_alpha_kernel, dim3(1), dim3(kSmallThreads), 0, st, ws.parts, nparts, s,
-                                   rel_thr, ws.smalld, ws.smallf, ws.ctrl, SL);
-            }
-            BKO_HIP(hipGetLastError());
-            if ((rc = launch_update_xw<T>(n, ldw, s, Dv, P, Q, AP, W, M1t, M2t, ws.ctrl, st)) != BKO_OK) return rc;
-            if ((rc = launch_gram<T>(W, W, ldw, s, ws.parts, nparts, ws.ctrl, st)) != BKO_OK) return rc;
-            {
-                TimedLaunch tl(kSmall, st);
-                hipLaunchKernelGGL(small_beta_kernel, dim3(1), dim3(kSmallThreads), 0, st, ws.parts, nparts, s,
-                                   rel_thr, ws.smalld, ws.smallf, ws.ctrl, SL, 1);
-            }
-            BKO_HIP(hipGetLastError());
-            if ((rc = launch_update_qp<T>(n, ldw, s, W, Q, P, M3t, M4t, ws.ctrl, st)) != BKO_OK) return rc;
+            if ((rc = launch_block<T>(kGramStep, ws, s, 0, st)) != BKO_OK) return rc;
+            if ((rc = launch_reduce_factor(ws, s, rel_thr, 0, st)) != BKO_OK) return rc;
+            if ((rc = launch_block<T>(kUpdateW, ws, s, 0, st)) != BKO_OK) return rc;
+            if ((rc = launch_reduce_factor(ws, s, rel_thr, 1, st)) != BKO_OK) return rc;
+            if ((rc = launch_block<T>(kUpdateDQP, ws, s, 0, st)) != BKO_OK) return rc;
         }
         launched += todo;
         BKO_HIP(hipMemcpyAsync(h_ctrl, ws.ctrl, sizeof(h_ctrl), hipMemcpyDeviceToHost, st));
         BKO_HIP(hipStreamSynchronize(st));
-        if (h_ctrl[kDone] || launched >= budget) break;
-        chunk = std::min(chunk * 2, 32);
+        if (h_ctrl[kConverged] || launched >= budget) break;
+        chunk = std::min(chunk * 2, 64);
     }
     iters_out = h_ctrl[kIters];
     deflated_out = h_ctrl[kDeflated];
     all_deflated = h_ctrl[kAllDeflated] != 0;
-    // X += D happens in the caller
     return BKO_OK;
 }
 
@@ -653,6 +743,17 @@ bko_status block_solve(const Operator &op, int s, const double *B, int64_t ldb, 
     const int64_t n = op.n;
     const unsigned rblocks = static_cast<unsigned>((n + 255) / 256);
     bko_status rc;
+    // LDS needed by the FP64 update kernel at this s
+    {
+        const size_t sp = 16 * static_cast<size_t>(nb_for(s));
+        const size_t need = 3 * (compute == BKO_F64 ? 8 : 4) * sp * (sp + 1);
+        const size_t cap = device_max_lds();
+        if (need > cap || sizeof(double) * 4 * s * s > cap) {
+            set_error("s = %d needs %zu bytes of LDS per workgroup in this precision; the device grants %zu", s, need,
+                      cap);
+            return BKO_EINVAL;
+        }
+    }
     std::vector<double> bnorm, rnorm;
     if ((rc = host_colnorms(B, ldb, n, s, ws.colparts, bnorm, st)) != BKO_OK) return rc;
     for (int j = 0; j < s; ++j)
@@ -674,8 +775,7 @@ bko_status block_solve(const Operator &op, int s, const double *B, int64_t ldb, 
     int stagnant = 0;
     const double inner_rel_f32 = 1e-5;
     for (int outer = 0; outer < 100; ++outer) {
-        // R = B - A X in FP64 (padding rows of R64 stay untouched; the cast
-        // below only reads rows < n)
+        // R = B - A X in FP64 (the cast into the inner blocks reads rows < n)
         {
             TimedLaunch tl(kResid, st);
             if ((rc = launch_stencil(op, s, X, ldx, BKO_F64, ws.R64, ws.ldw, BKO_F64, BKO_F64, B, ldb, st)) != BKO_OK)

@@ -28,6 +28,14 @@ bko_status hip_fail(hipError_t e, const char *what)
     return BKO_EHIP;
 }
 
+size_t device_max_lds()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) return 65536;
+    return static_cast<size_t>(v);
+}
+
 CoeffLayout coeff_layout(int64_t n)
 {
     CoeffLayout L{};

@@ -112,6 +112,9 @@ __device__ inline uint32_t remap_block(uint32_t bid, uint32_t nblocks)
 void set_error(const char *fmt, ...);
 bko_status hip_fail(hipError_t e, const char *what);
 
+// LDS bytes one workgroup may allocate on the current device.
+size_t device_max_lds();
+
 #define BKO_HIP(call)                                                   \
     do {                                                                \
         hipError_t e_ = (call);                                         \

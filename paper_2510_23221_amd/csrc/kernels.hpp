@@ -9,7 +9,8 @@ namespace bko {
 // 5/7-point stencil.  t_in / t_out / compute are bko_dtype values.
 bko_status launch_stencil(const Operator &op, int m, const void *X, int64_t ldx, bko_dtype t_in,
                           void *Y, int64_t ldy, bko_dtype t_out, bko_dtype compute,
-                          const double *Bres, int64_t ldb, hipStream_t stream, const int *skip = nullptr);
+                          const double *Bres, int64_t ldb, hipStream_t stream, const int *skip = nullptr,
+                          int *stop = nullptr);
 
 bko_status launch_combine(int64_t n, int s, int64_t m, const void *X, int64_t ldx, bko_dtype x_t,
                           const void *C, int64_t ldc, bko_dtype c_t, void *T, int64_t ldt,

@@ -27,9 +27,13 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(
     const Tc *__restrict__ diag, const Tc *__restrict__ wx, const Tc *__restrict__ wy,
     const Tc *__restrict__ wz, int nx, int ny, int nz, const Tin *__restrict__ X, int64_t ldx,
     Tout *__restrict__ Y, int64_t ldy, const double *__restrict__ Bres, int64_t ldb, int m,
-    int cols_per_group, uint32_t ntiles, uint32_t nblocks, const int *__restrict__ skip)
+    int cols_per_group, uint32_t ntiles, uint32_t nblocks, const int *__restrict__ skip, int *stop)
 {
-    if (skip && *skip) return;
+    if (skip && *skip) {
+        // the iteration before this one converged: tell the later kernels
+        if (stop && blockIdx.x == 0 && threadIdx.x == 0) *stop = 1;
+        return;
+    }
     const uint32_t lb = remap_block(blockIdx.x, nblocks);
     const uint32_t tile = lb % ntiles;
     const uint32_t group = lb / ntiles;
@@ -72,7 +76,7 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(
 template <class Tin, class Tout, class Tc, class Acc, bool kResidual>
 bko_status run(const Operator &op, const Tc *diag, const Tc *wx, const Tc *wy, const Tc *wz, int m,
                const void *X, int64_t ldx, void *Y, int64_t ldy, const double *Bres, int64_t ldb,
-               hipStream_t stream, const int *skip)
+               hipStream_t stream, const int *skip, int *stop)
 {
     const uint32_t ntiles = static_cast<uint32_t>((op.n + kThreads - 1) / kThreads);
     // enough column groups to fill the chip, few enough that each thread
@@ -88,30 +92,30 @@ bko_status run(const Operator &op, const Tc *diag, const Tc *wx, const Tc *wy, c
     hipLaunchKernelGGL((stencil_kernel<Tin, Tout, Tc, Acc, kResidual>), dim3(static_cast<uint32_t>(nb)),
                        dim3(kThreads), 0, stream, diag, wx, wy, wz, op.nx, op.ny, op.nz,
                        static_cast<const Tin *>(X), ldx, static_cast<Tout *>(Y), ldy, Bres, ldb, m, cols,
-                       ntiles, static_cast<uint32_t>(nb), skip);
+                       ntiles, static_cast<uint32_t>(nb), skip, stop);
     BKO_HIP(hipGetLastError());
     return BKO_OK;
 }
 
 template <class Tin, class Tout>
 bko_status dispatch_compute(const Operator &op, int m, const void *X, int64_t ldx, void *Y, int64_t ldy,
-                            bko_dtype compute, hipStream_t stream, const int *skip)
+                            bko_dtype compute, hipStream_t stream, const int *skip, int *stop)
 {
     if (compute == BKO_F64)
         return run<Tin, Tout, double, double, false>(op, op.diag64, op.wx64, op.wy64, op.wz64, m, X, ldx, Y,
-                                                     ldy, nullptr, 0, stream, skip);
+                                                     ldy, nullptr, 0, stream, skip, stop);
     return run<Tin, Tout, float, float, false>(op, op.diag32, op.wx32, op.wy32, op.wz32, m, X, ldx, Y, ldy,
-                                               nullptr, 0, stream, skip);
+                                               nullptr, 0, stream, skip, stop);
 }
 
 template <class Tin>
 bko_status dispatch_out(const Operator &op, int m, const void *X, int64_t ldx, void *Y, int64_t ldy,
-                        bko_dtype t_out, bko_dtype compute, hipStream_t stream, const int *skip)
+                        bko_dtype t_out, bko_dtype compute, hipStream_t stream, const int *skip, int *stop)
 {
     switch (t_out) {
-    case BKO_F64: return dispatch_compute<Tin, double>(op, m, X, ldx, Y, ldy, compute, stream, skip);
-    case BKO_F32: return dispatch_compute<Tin, float>(op, m, X, ldx, Y, ldy, compute, stream, skip);
-    default: return dispatch_compute<Tin, bf16>(op, m, X, ldx, Y, ldy, compute, stream, skip);
+    case BKO_F64: return dispatch_compute<Tin, double>(op, m, X, ldx, Y, ldy, compute, stream, skip, stop);
+    case BKO_F32: return dispatch_compute<Tin, float>(op, m, X, ldx, Y, ldy, compute, stream, skip, stop);
+    default: return dispatch_compute<Tin, bf16>(op, m, X, ldx, Y, ldy, compute, stream, skip, stop);
     }
 }
 
@@ -119,18 +123,18 @@ bko_status dispatch_out(const Operator &op, int m, const void *X, int64_t ldx, v
 
 bko_status launch_stencil(const Operator &op, int m, const void *X, int64_t ldx, bko_dtype t_in, void *Y,
                           int64_t ldy, bko_dtype t_out, bko_dtype compute, const double *Bres, int64_t ldb,
-                          hipStream_t stream, const int *skip)
+                          hipStream_t stream, const int *skip, int *stop)
 {
     if (m <= 0) return BKO_OK;
     if (Bres != nullptr) {
         // residual form is FP64 only
         return run<double, double, double, double, true>(op, op.diag64, op.wx64, op.wy64, op.wz64, m, X, ldx, Y,
-                                                         ldy, Bres, ldb, stream, skip);
+                                                         ldy, Bres, ldb, stream, skip, stop);
     }
     switch (t_in) {
-    case BKO_F64: return dispatch_out<double>(op, m, X, ldx, Y, ldy, t_out, compute, stream, skip);
-    case BKO_F32: return dispatch_out<float>(op, m, X, ldx, Y, ldy, t_out, compute, stream, skip);
-    default: return dispatch_out<bf16>(op, m, X, ldx, Y, ldy, t_out, compute, stream, skip);
+    case BKO_F64: return dispatch_out<double>(op, m, X, ldx, Y, ldy, t_out, compute, stream, skip, stop);
+    case BKO_F32: return dispatch_out<float>(op, m, X, ldx, Y, ldy, t_out, compute, stream, skip, stop);
+    default: return dispatch_out<bf16>(op, m, X, ldx, Y, ldy, t_out, compute, stream, skip, stop);
     }
 }
 
