@@ -201,14 +201,16 @@ bko_status bko_residual(bko_op A, int m, const double *B, int ldb, const double 
 /* ---------------------------------------------------- kernel timing hooks */
 
 /*
- * Optional per-kernel timing: when enabled, the library records a HIP event
- * pair around every launch of the named kernel family on the launch stream
- * and accumulates the elapsed time when queried (which synchronises).
- * Families: 0 = operator action, 1 = combine, 2 = gram, 3 = block
- * update, 4 = small dense solve, 5 = block-solve stencil product, 6 = FP64
- * residual.  Used to report per-kernel bandwidth.
+ * Optional per-kernel timing: `mask` selects kernel families (bit f = family
+ * f, 0 = off).  For a selected family the library records a HIP event pair
+ * around every launch on the launch stream and accumulates the elapsed time
+ * when queried (which synchronises).
+ * Families: 0 = operator action, 1 = combine, 2 = Gram partials, 3 = block
+ * update W, 4 = Gram reduction + s x s factorisation, 5 = block-solve stencil
+ * product, 6 = FP64 residual, 7 = block update D, Q, P.  Used to report
+ * per-kernel bandwidth.
  */
-bko_status bko_timing_enable(int enable);
+bko_status bko_timing_enable(int mask);
 bko_status bko_timing_query(int family, int *launches, double *total_ms);
 bko_status bko_timing_reset(void);
 

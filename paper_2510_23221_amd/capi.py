@@ -269,11 +269,20 @@ def residual(A: HeatOperator, B: torch.Tensor, X: torch.Tensor, R: Optional[torc
 
 # ------------------------------------------------------------------ timing hooks
 
-FAMILY = {"apply": 0, "combine": 1, "gram": 2, "update": 3, "small": 4, "spmm": 5, "resid": 6}
+FAMILY = {"apply": 0, "combine": 1, "gram": 2, "update_w": 3, "factor": 4, "spmm": 5, "resid": 6, "update_dqp": 7}
 
 
-def timing_enable(on: bool = True):
-    _check(load_library().bko_timing_enable(1 if on else 0))
+def timing_enable(families=None):
+    """Time the named kernel families (None: all; [] or False: none)."""
+    if families is True or families is None:
+        mask = (1 << len(FAMILY)) - 1
+    elif families is False:
+        mask = 0
+    else:
+        mask = 0
+        for f in families:
+            mask |= 1 << FAMILY[f]
+    _check(load_library().bko_timing_enable(mask))
 
 
 def timing_reset():

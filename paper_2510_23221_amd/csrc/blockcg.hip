@@ -54,7 +54,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;      // block kernels
-constexpr int kEpiThreads = 1024;  // factorisation kernel
+constexpr int kFacThreads = 256;   // factorisation kernel
 constexpr int kMaxS = 64;
 constexpr int kMaxBlocks = 512;    // partial producers per launch
 constexpr int kRedBlocks = 64;     // reducer workgroups
@@ -248,34 +248,73 @@ __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(const double *__r
 
 // ------------------------------------------------------------------ factorisation (one workgroup)
 
-// LDL^T elimination of [G | I] held in A (s rows, row stride 2s), without
-// pivoting.  A pivot <= thr (or not finite) deactivates its index.  On
-// return, for active i: A[i][i] = d_i, A[i][j > i] = U (= d_i Lunit^T), and
-// the right half A[i][s + j] = E[i][j] with E = Lunit^{-1} (lower, unit).
-__device__ void ldl_eliminate(double *A, int s, double thr, int *active)
+__device__ __forceinline__ double readlane_f64(double v, int lane)
 {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffu), lane);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), lane);
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// Masked LDL^T elimination of [G | I] by one wavefront, for s <= SP <= 32:
+// lane c holds column c of the 2 SP columns in registers; each pivot row of
+// the column is broadcast with readlane, so no LDS traffic or barrier per
+// pivot.  Indices s <= i < SP are decoupled padding with pivot gmax.
+// Writes the result (A[i][j], j < 2s: left half U, right half E) to LDS.
+template <int SP>
+__device__ __forceinline__ void wave_eliminate(const double *__restrict__ gram, int s, double rel_thr, double *A,
+                                               int *active)
+{
+    const int lane = threadIdx.x & 63;
     const int w = 2 * s;
-    const int total = s * w;  // <= 8192: at most 8 entries per thread
-    int oi[8], oj[8];
+    double gmax = lane < s ? gram[lane * s + lane] : 0.0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int e = threadIdx.x + q * kEpiThreads;
-        oi[q] = e < total ? e / w : -1;
-        oj[q] = e < total ? e % w : 0;
+    for (int off = 32; off > 0; off >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, off));
+    const double thr = rel_thr * gmax;
+    double a[SP];
+#pragma unroll
+    for (int i = 0; i < SP; ++i) {
+        if (lane < SP)
+            a[i] = (i < s && lane < s) ? 0.5 * (gram[i * s + lane] + gram[lane * s + i]) : (i == lane ? gmax : 0.0);
+        else
+            a[i] = (i == lane - SP) ? 1.0 : 0.0;
     }
-    for (int k = 0; k < s; ++k) {
-        const double p = A[k * w + k];
-        const bool act = p > thr && isfinite(p);
-        if (act) {
-            const double inv = 1.0 / p;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int i = oi[q], j = oj[q];
-                if (i > k && ((j > k && j < s) || (j >= s && j <= s + k))) A[i * w + j] -= A[i * w + k] * inv * A[k * w + j];
-            }
+    for (int k = 0; k < SP; ++k) {
+        const double p = readlane_f64(a[k], k);
+        const bool act = p > thr && isfinite(p);
+        // this column's pivot-row entry, scaled; zero when the pivot is inactive
+        const double m = act ? -a[k] * (1.0 / p) : 0.0;
+#pragma unroll
+        for (int i = k + 1; i < SP; ++i) a[i] = fma(readlane_f64(a[i], k), m, a[i]);
+        if (lane == 0 && k < s) active[k] = act ? 1 : 0;
+    }
+    const int col = lane < SP ? (lane < s ? lane : -1) : (lane - SP < s ? s + lane - SP : -1);
+    if (lane < 2 * SP && col >= 0) {
+#pragma unroll
+        for (int i = 0; i < SP; ++i)
+            if (i < s) A[i * w + col] = a[i];
+    }
+}
+
+// Publish pivot row r of the register-held [G | I], its reciprocal pivot
+// (*inv) and column r into the LDS vectors rn / cn.
+template <int E>
+__device__ __forceinline__ void publish_pivot(const double (&a)[E], int i, int j0, int w, bool live, int r, double *rn,
+                                              double *cn, double *inv)
+{
+    if (!live) return;
+    if (i == r) {
+#pragma unroll
+        for (int q = 0; q < E; ++q)
+            if (j0 + q < w) rn[j0 + q] = a[q];
+    }
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        if (j0 + q == r) {
+            cn[i] = a[q];
+            if (i == r) *inv = 1.0 / a[q];  // read only when the pivot is active
         }
-        if (threadIdx.x == 0) active[k] = act ? 1 : 0;
-        __syncthreads();
     }
 }
 
@@ -284,83 +323,186 @@ __device__ void ldl_eliminate(double *A, int s, double thr, int *active)
 // M3[k][j] = Linv[j][k] (Q = W S^+), M4[k][j] = S[j][k] (P = Q + P S^T);
 // converged when ||C e_j|| <= th_j for every column (mode 2 is the first QR
 // of the residual and is not counted as an iteration).
-__global__ __launch_bounds__(kEpiThreads) void factor_kernel(const double *__restrict__ gram, int s, double rel_thr,
+//
+// Work layout: each of the 256 threads owns E consecutive entries of one row
+// of [G | I] in registers; per pivot the owners publish the pivot row (with
+// its reciprocal) and column into double-buffered LDS vectors, one barrier
+// per pivot.  The s x s products afterwards use the same row-segment
+// ownership with E / 2 outputs per thread.
+// SP > 0 selects the one-wavefront elimination (s <= SP <= 32).
+template <int E, int SP>
+__global__ __launch_bounds__(kFacThreads) void factor_kernel(const double *__restrict__ gram, int s, double rel_thr,
                                                              Small sm, int *ctrl, int mode)
 {
     if (ctrl[kConverged]) return;
+    constexpr int E2 = E > 1 ? E / 2 : 1;
+    constexpr int EA = SP > 0 ? 1 : E;  // register row segment of the LDS elimination
     extern __shared__ __align__(16) double lds[];
     const int ss = s * s, w = 2 * s;
-    double *A = lds;            // s x 2s
-    double *G = lds + 2 * ss;   // s x s scratch
-    double *Cl = lds + 3 * ss;  // C
+    // every region is padded by E doubles so that a row segment can be read
+    // whole; padding is zeroed, masked lanes multiply it by zero
+    double *A = lds;                        // s x 2s
+    double *G = A + 2 * ss + E;             // s x s scratch
+    double *Cl = G + ss + E;                // C
+    double *rowbuf = Cl + ss + E;           // 2 x (w + E)
+    double *colbuf = rowbuf + 2 * (w + E);  // 2 x s
     __shared__ int active[kMaxS];
     __shared__ double dv[kMaxS];
-    __shared__ double thl[kMaxS];
+    __shared__ double invb[2];
     __shared__ double gmax;
     __shared__ int notconv;
     const int tid = threadIdx.x;
-    for (int e = tid; e < s * w; e += kEpiThreads) {
-        const int i = e / w, j = e % w;
-        A[e] = j < s ? 0.5 * (gram[i * s + j] + gram[j * s + i]) : (j - s == i ? 1.0 : 0.0);
+    for (int e = tid; e < E; e += kFacThreads) {
+        A[2 * ss + e] = 0.0;
+        G[ss + e] = 0.0;
+        Cl[ss + e] = 0.0;
+        rowbuf[w + e] = 0.0;
+        rowbuf[2 * w + E + e] = 0.0;
     }
-    for (int e = tid; e < ss; e += kEpiThreads) Cl[e] = sm.C[e];
-    for (int j = tid; j < s; j += kEpiThreads) thl[j] = sm.th[j];
+    for (int e = tid; e < ss; e += kFacThreads) Cl[e] = sm.C[e];
     if (tid == 0) notconv = 0;
-    __syncthreads();
-    if (tid == 0) {
-        double mx = 0.0;
-        for (int k = 0; k < s; ++k) mx = fmax(mx, A[k * w + k]);
-        gmax = mx;
+    if constexpr (SP > 0) {
+        if (tid < 64) wave_eliminate<SP>(gram, s, rel_thr, A, active);
+    } else {
+        const int tpr = (w + EA - 1) / EA;
+        const int i = tid / tpr, j0 = (tid % tpr) * EA;
+        const bool live = i < s;
+        double a[EA];
+#pragma unroll
+        for (int q = 0; q < EA; ++q) {
+            const int j = j0 + q;
+            a[q] = 0.0;
+            if (live && j < w) a[q] = j < s ? 0.5 * (gram[i * s + j] + gram[j * s + i]) : (j - s == i ? 1.0 : 0.0);
+        }
+        if (tid < 64) {
+            double v = tid < s ? gram[tid * s + tid] : 0.0;
+            for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+            if (tid == 0) gmax = v;
+        }
+        publish_pivot<EA>(a, i, j0, w, live, 0, rowbuf, colbuf, &invb[0]);
+        __syncthreads();
+        const double thr = rel_thr * gmax;
+        const int ic = live ? i : 0;
+        for (int k = 0; k < s; ++k) {
+            const int b = k & 1;
+            const double *rb = rowbuf + b * (w + E);
+            const double *cb = colbuf + b * s;
+            const double p = rb[k];
+            const bool act = p > thr && isfinite(p);
+            // branch-free update: read the whole pivot-row segment, mask the multiplier
+            double r[EA];
+#pragma unroll
+            for (int q = 0; q < EA; ++q) r[q] = rb[j0 + q];
+            const double cv = cb[ic];
+            const double l = (act && live && i > k) ? cv * invb[b] : 0.0;
+#pragma unroll
+            for (int q = 0; q < EA; ++q) {
+                const int j = j0 + q;
+                const bool upd = (j > k && j < s) || (j >= s && j <= s + k);
+                a[q] = fma(upd ? -l : 0.0, r[q], a[q]);
+            }
+            if (k + 1 < s)
+                publish_pivot<EA>(a, i, j0, w, live, k + 1, rowbuf + (b ^ 1) * (w + E), colbuf + (b ^ 1) * s,
+                                  &invb[b ^ 1]);
+            if (tid == 0) active[k] = act ? 1 : 0;
+            __syncthreads();
+        }
+        if (live) {
+#pragma unroll
+            for (int q = 0; q < EA; ++q)
+                if (j0 + q < w) A[i * w + j0 + q] = a[q];
+        }
     }
     __syncthreads();
-    ldl_eliminate(A, s, rel_thr * gmax, active);
+    for (int k = tid; k < s; k += kFacThreads)
+        dv[k] = !active[k] ? 0.0 : (mode == 0 ? 1.0 / A[k * w + k] : 1.0 / sqrt(A[k * w + k]));
+    __syncthreads();
     int inactive = 0;
     for (int k = 0; k < s; ++k) inactive += active[k] ? 0 : 1;
+    // s x s outputs: thread owns row i2, columns j2 .. j2 + E2
+    const int tpr2 = (s + E2 - 1) / E2;
+    const int i2 = tid / tpr2, j2 = (tid % tpr2) * E2;
+    const bool live2 = i2 < s;
+    double acc[E2];
     if (mode == 0) {
-        for (int k = tid; k < s; k += kEpiThreads) dv[k] = active[k] ? 1.0 / A[k * w + k] : 0.0;
-        __syncthreads();
-        // delta^+[i][j] = sum_{k >= max(i,j)} E[k][i] E[k][j] / d_k over active k
-        for (int e = tid; e < ss; e += kEpiThreads) {
-            const int i = e / s, j = e % s;
-            double acc = 0.0;
-            for (int k = max(i, j); k < s; ++k) acc += A[k * w + s + i] * A[k * w + s + j] * dv[k];
-            G[e] = acc;
-            sm.M2[e] = acc;
-            sm.M2f[e] = static_cast<float>(acc);
+        // delta^+[i][j] = sum_{k >= max(i,j)} E[k][i] E[k][j] / d_k, E = right half
+#pragma unroll
+        for (int q = 0; q < E2; ++q) acc[q] = 0.0;
+        if (live2) {
+            for (int k = i2; k < s; ++k) {
+                const double c = A[k * w + s + i2] * dv[k];
+#pragma unroll
+                for (int q = 0; q < E2; ++q)
+                    acc[q] += c * A[k * w + s + j2 + q];  // columns >= s: padding, not stored
+            }
+#pragma unroll
+            for (int q = 0; q < E2; ++q) {
+                if (j2 + q < s) {
+                    const int e = i2 * s + j2 + q;
+                    G[e] = acc[q];
+                    sm.M2[e] = acc[q];
+                    sm.M2f[e] = static_cast<float>(acc[q]);
+                }
+            }
         }
         __syncthreads();
-        for (int e = tid; e < ss; e += kEpiThreads) {
-            const int i = e / s, j = e % s;
-            double m1 = 0.0;
-            for (int k = 0; k <= j; ++k) m1 += G[i * s + k] * Cl[k * s + j];  // C upper triangular
-            sm.M1[e] = m1;
-            sm.M1f[e] = static_cast<float>(m1);
+        // M1 = delta^+ C
+#pragma unroll
+        for (int q = 0; q < E2; ++q) acc[q] = 0.0;
+        if (live2) {
+            for (int k = 0; k < s; ++k) {
+                const double c = G[i2 * s + k];
+#pragma unroll
+                for (int q = 0; q < E2; ++q)
+                    acc[q] += c * Cl[k * s + j2 + q];
+            }
+#pragma unroll
+            for (int q = 0; q < E2; ++q) {
+                if (j2 + q < s) {
+                    const int e = i2 * s + j2 + q;
+                    sm.M1[e] = acc[q];
+                    sm.M1f[e] = static_cast<float>(acc[q]);
+                }
+            }
         }
         return;
     }
-    for (int i = tid; i < s; i += kEpiThreads) dv[i] = active[i] ? 1.0 / sqrt(A[i * w + i]) : 0.0;
-    __syncthreads();
-    // S[i][j] = U[i][j] dv[i] (j >= i);  Cn = S C into G
-    for (int e = tid; e < ss; e += kEpiThreads) {
-        const int i = e / s, j = e % s;
-        double acc = 0.0;
-        for (int k = i; k <= j; ++k) acc += A[i * w + k] * Cl[k * s + j];
-        G[e] = acc * dv[i];
-        const int kk = i, jj = j;  // reuse e as (k, j) for M3 / M4
-        const double m3 = kk <= jj ? A[jj * w + s + kk] * dv[jj] : 0.0;
-        const double m4 = kk >= jj ? A[jj * w + kk] * dv[jj] : 0.0;
+    // S[i][k] = U[i][k] dv[i] (k >= i);  Cn = S C into G
+#pragma unroll
+    for (int q = 0; q < E2; ++q) acc[q] = 0.0;
+    if (live2) {
+        for (int k = i2; k < s; ++k) {
+            const double c = A[i2 * w + k];
+#pragma unroll
+            for (int q = 0; q < E2; ++q)
+                acc[q] += c * Cl[k * s + j2 + q];
+        }
+#pragma unroll
+        for (int q = 0; q < E2; ++q)
+            if (j2 + q < s) G[i2 * s + j2 + q] = acc[q] * dv[i2];
+    }
+    // M3[k][j] = Linv[j][k] = E[j][k] dv[j] (k <= j);  M4[k][j] = S[j][k] = U[j][k] dv[j] (k >= j)
+    for (int e = tid; e < ss; e += kFacThreads) {
+        const int k = e / s, j = e % s;
+        const double m3 = k <= j ? A[j * w + s + k] * dv[j] : 0.0;
+        const double m4 = k >= j ? A[j * w + k] * dv[j] : 0.0;
         sm.M3[e] = m3;
         sm.M3f[e] = static_cast<float>(m3);
         sm.M4[e] = m4;
         sm.M4f[e] = static_cast<float>(m4);
     }
     __syncthreads();
-    for (int j = tid; j < s; j += kEpiThreads) {
-        double nrm2 = 0.0;
-        for (int i = 0; i <= j; ++i) nrm2 += G[i * s + j] * G[i * s + j];
-        if (!(sqrt(nrm2) <= thl[j])) atomicAdd(&notconv, 1);
+    for (int j = tid; j < s; j += kFacThreads) {
+        double n0 = 0.0, n1 = 0.0;
+        int r = 0;
+        for (; r + 1 <= j; r += 2) {
+            n0 += G[r * s + j] * G[r * s + j];
+            n1 += G[(r + 1) * s + j] * G[(r + 1) * s + j];
+        }
+        if (r <= j) n0 += G[r * s + j] * G[r * s + j];
+        if (!(sqrt(n0 + n1) <= sm.th[j])) atomicAdd(&notconv, 1);
     }
-    for (int e = tid; e < ss; e += kEpiThreads) sm.C[e] = G[e];
+    for (int e = tid; e < ss; e += kFacThreads) sm.C[e] = G[e];
     __syncthreads();
     if (tid == 0) {
         ctrl[kIters] += mode == 1 ? 1 : 0;
@@ -368,6 +510,15 @@ __global__ __launch_bounds__(kEpiThreads) void factor_kernel(const double *__res
         if (inactive == s) ctrl[kAllDeflated] = 1;
         if (notconv == 0 || inactive == s) ctrl[kConverged] = 1;
     }
+}
+
+// Smallest row-segment width E (power of two) with s rows x ceil(2s / E)
+// threads fitting one workgroup.
+inline int factor_segment(int s)
+{
+    int e = 1;
+    while (s * ((2 * s + e - 1) / e) > kFacThreads) e *= 2;
+    return e;
 }
 
 // ------------------------------------------------------------------ block updates
@@ -584,7 +735,7 @@ inline unsigned grid_for(int64_t ldw)
     return static_cast<unsigned>(std::min<int64_t>(ldw / kTileRows, kMaxBlocks));
 }
 
-enum Step { kGramStep = 0, kUpdateW = 1, kUpdateDQP = 2 };
+enum Step { kStepGram = 0, kStepW = 1, kStepDQP = 2 };
 
 template <class T, int NB>
 bko_status launch_block_kernel(Step which, const Workspace &ws, int s, int init, hipStream_t st)
@@ -600,15 +751,15 @@ bko_status launch_block_kernel(Step which, const Workspace &ws, int s, int init,
     const T *M4 = f64 ? reinterpret_cast<const T *>(ws.sm.M4) : reinterpret_cast<const T *>(ws.sm.M4f);
     const int sp = 16 * NB;
     const size_t mbytes = sizeof(T) * sp * (sp + 1);
-    if (which == kGramStep) {
+    if (which == kStepGram) {
         TimedLaunch tl(kGram, st);
         hipLaunchKernelGGL((gram_kernel<T, NB>), dim3(grid), dim3(kThreads), 0, st, P, AP, ldw, s, ws.parts, ws.ctrl);
-    } else if (which == kUpdateW) {
+    } else if (which == kStepW) {
         TimedLaunch tl(kUpdate, st);
         hipLaunchKernelGGL((update_w_kernel<T, NB>), dim3(grid), dim3(kThreads), 0, st, Q, AP, W, M2, ldw, s, ws.parts,
                            ws.ctrl, init);
     } else {
-        TimedLaunch tl(kUpdate, st);
+        TimedLaunch tl(::bko::kUpdateDQP, st);
         hipLaunchKernelGGL((update_dqp_kernel<T, NB>), dim3(grid), dim3(kThreads), 3 * mbytes, st, Dv, P, Q, W, M1, M3,
                            M4, ldw, s, ws.ctrl);
     }
@@ -638,8 +789,20 @@ bko_status launch_reduce_factor(const Workspace &ws, int s, double rel_thr, int 
         hipLaunchKernelGGL(gram_reduce_kernel, dim3(rblocks), dim3(kThreads), 0, st, ws.parts, static_cast<int>(nparts),
                            ss, ws.gram, ws.ctrl);
         BKO_HIP(hipGetLastError());
-        hipLaunchKernelGGL(factor_kernel, dim3(1), dim3(kEpiThreads), sizeof(double) * 4 * ss, st, ws.gram, s, rel_thr,
-                           ws.sm, ws.ctrl, mode);
+        // A, G, C (each padded by E <= 32), two pivot rows (padded) and columns
+        const size_t lds = sizeof(double) * (4 * ss + 3 * 32 + 2 * (2 * s + 32) + 2 * s);
+#define BKO_FACTOR(E, SP)                                                                                   \
+    hipLaunchKernelGGL((factor_kernel<E, SP>), dim3(1), dim3(kFacThreads), lds, st, ws.gram, s, rel_thr, ws.sm, \
+                       ws.ctrl, mode)
+        const int e = factor_segment(s);
+        if (s <= 8) BKO_FACTOR(1, 8);
+        else if (s <= 16 && e == 1) BKO_FACTOR(1, 16);
+        else if (s <= 16) BKO_FACTOR(2, 16);
+        else if (s <= 32 && e == 4) BKO_FACTOR(4, 32);
+        else if (s <= 32) BKO_FACTOR(8, 32);
+        else if (e == 16) BKO_FACTOR(16, 0);
+        else BKO_FACTOR(32, 0);
+#undef BKO_FACTOR
         BKO_HIP(hipGetLastError());
     }
     return BKO_OK;
@@ -692,9 +855,9 @@ bko_status inner_solve(const Operator &op, int s, const Workspace &ws, const std
                        n, s);
     BKO_HIP(hipGetLastError());
     // first QR of the residual, then Q = W S^+, P = Q (P is zero), D = 0 (M1 = 0)
-    if ((rc = launch_block<T>(kUpdateW, ws, s, 1, st)) != BKO_OK) return rc;
+    if ((rc = launch_block<T>(kStepW, ws, s, 1, st)) != BKO_OK) return rc;
     if ((rc = launch_reduce_factor(ws, s, rel_thr, 2, st)) != BKO_OK) return rc;
-    if ((rc = launch_block<T>(kUpdateDQP, ws, s, 0, st)) != BKO_OK) return rc;
+    if ((rc = launch_block<T>(kStepDQP, ws, s, 0, st)) != BKO_OK) return rc;
 
     const bko_dtype vt = f64 ? BKO_F64 : BKO_F32;
     int h_ctrl[8] = {0};
@@ -709,11 +872,11 @@ bko_status inner_solve(const Operator &op, int s, const Workspace &ws, const std
                                          ws.ctrl + kStop)) != BKO_OK)
                     return rc;
             }
-            if ((rc = launch_block<T>(kGramStep, ws, s, 0, st)) != BKO_OK) return rc;
+            if ((rc = launch_block<T>(kStepGram, ws, s, 0, st)) != BKO_OK) return rc;
             if ((rc = launch_reduce_factor(ws, s, rel_thr, 0, st)) != BKO_OK) return rc;
-            if ((rc = launch_block<T>(kUpdateW, ws, s, 0, st)) != BKO_OK) return rc;
+            if ((rc = launch_block<T>(kStepW, ws, s, 0, st)) != BKO_OK) return rc;
             if ((rc = launch_reduce_factor(ws, s, rel_thr, 1, st)) != BKO_OK) return rc;
-            if ((rc = launch_block<T>(kUpdateDQP, ws, s, 0, st)) != BKO_OK) return rc;
+            if ((rc = launch_block<T>(kStepDQP, ws, s, 0, st)) != BKO_OK) return rc;
         }
         launched += todo;
         BKO_HIP(hipMemcpyAsync(h_ctrl, ws.ctrl, sizeof(h_ctrl), hipMemcpyDeviceToHost, st));

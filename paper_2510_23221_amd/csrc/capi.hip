@@ -58,7 +58,7 @@ CoeffLayout coeff_layout(int64_t n)
 namespace {
 struct TimingState {
     std::mutex mu;
-    bool enabled = false;
+    unsigned mask = 0;  // timed families, bit f = family f
     std::vector<hipEvent_t> pool;
     struct Pair { int family; hipEvent_t a, b; };
     std::vector<Pair> pending;
@@ -100,7 +100,7 @@ bko_status drain(TimingState &t)
 TimedLaunch::TimedLaunch(int fam, hipStream_t s) : family(fam), stream(s), ev0(nullptr)
 {
     TimingState &t = timing();
-    if (!t.enabled) return;
+    if (!(t.mask & (1u << fam))) return;
     std::lock_guard<std::mutex> g(t.mu);
     hipEvent_t e = take_event(t);
     if (e && hipEventRecord(e, s) == hipSuccess) ev0 = e;
@@ -426,7 +426,7 @@ bko_status bko_timing_enable(int enable)
 {
     TimingState &t = timing();
     std::lock_guard<std::mutex> g(t.mu);
-    t.enabled = enable != 0;
+    t.mask = static_cast<unsigned>(enable);
     return BKO_OK;
 }
 

@@ -159,7 +159,8 @@ enum TimingFamily {
     kSmall = 4,    // one-workgroup FP64 factorisations
     kSpmm = 5,     // stencil product inside the block iteration
     kResid = 6,    // FP64 residual B - A X
-    kNumFamilies = 7
+    kUpdateDQP = 7,  // second block update (D, Q, P)
+    kNumFamilies = 8
 };
 
 struct TimedLaunch {
