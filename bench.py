@@ -39,7 +39,46 @@ def parse():
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-fields", type=int, default=200)
+    ap.add_argument("--only", choices=["apply", "combine", "copy"], default=None,
+                    help="run one kernel family at the workload's shape (for counter profiles)")
     return ap.parse_args()
+
+
+def only_kernel(args, w, G, X, C, T, F, t_dtype, comb_compute, apply_compute):
+    """Launch one kernel family `steps` times at the workload shape and print
+    its event-timed average.  `copy` is a plain device copy of T into F (the
+    calibration kernel for HBM byte counters)."""
+    import torch
+
+    from paper_2510_23221_amd import capi
+
+    n, m = T.shape[1], T.shape[0]
+    wt = T.element_size()
+
+    def run():
+        if args.only == "apply":
+            capi.apply_operator(G, T, out_dtype=t_dtype, compute=apply_compute, F=F)
+        elif args.only == "combine":
+            capi.combine(X, C, out_dtype=t_dtype, compute=comb_compute, T=T)
+        else:
+            F.copy_(T)
+
+    T.normal_()
+    X.normal_()
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        run()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    nbytes = {"apply": n * m * 2 * wt, "combine": n * m * wt, "copy": n * m * 2 * wt}[args.only]
+    print(json.dumps({"only": args.only, "avg_ms": round(ms, 4), "bytes": nbytes,
+                      "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1), "shape": [m, n], "dtype": str(t_dtype)}),
+          flush=True)
 
 
 def main():
@@ -72,7 +111,9 @@ def main():
     wbytes = capi.workspace_bytes(G, s, compute)
     work = torch.empty(wbytes + 256, dtype=torch.uint8, device=dev)
     wview = work[(-work.data_ptr()) % 256:]
-    stream = torch.cuda.current_stream()
+    if args.only:
+        only_kernel(args, w, G, X, C, T, F, t_dtype, comb_compute, apply_compute)
+        return
 
     infos = []
 

@@ -14,6 +14,8 @@
 // them for every column of the group.  The workgroup order is remapped so
 // that each XCD walks a contiguous range of (column group, cell tile) pairs,
 // keeping the neighbouring tiles that supply the y / z halo in one L2.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace bko {
@@ -73,11 +75,247 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(
     }
 }
 
+// ---------------------------------------------------------------- LDS-tiled kernel
+
+// N consecutive elements moved with the widest aligned accesses.
+template <class T, int N>
+struct alignas(N * sizeof(T) >= 16 ? 16 : N * sizeof(T)) Vec {
+    T v[N];
+};
+
+template <class T, int N>
+__device__ __forceinline__ Vec<T, N> vload(const T *p)
+{
+    Vec<T, N> r;
+    constexpr int B = N * sizeof(T);
+    if constexpr (B % 16 == 0) {
+#pragma unroll
+        for (int c = 0; c < B / 16; ++c) reinterpret_cast<uint4 *>(&r)[c] = reinterpret_cast<const uint4 *>(p)[c];
+    } else if constexpr (B == 8) {
+        *reinterpret_cast<uint2 *>(&r) = *reinterpret_cast<const uint2 *>(p);
+    } else if constexpr (B == 4) {
+        *reinterpret_cast<uint32_t *>(&r) = *reinterpret_cast<const uint32_t *>(p);
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) r.v[i] = p[i];
+    }
+    return r;
+}
+
+template <class T, int N>
+__device__ __forceinline__ void vstore(T *p, const Vec<T, N> &r)
+{
+    constexpr int B = N * sizeof(T);
+    if constexpr (B % 16 == 0) {
+#pragma unroll
+        for (int c = 0; c < B / 16; ++c) reinterpret_cast<uint4 *>(p)[c] = reinterpret_cast<const uint4 *>(&r)[c];
+    } else if constexpr (B == 8) {
+        *reinterpret_cast<uint2 *>(p) = *reinterpret_cast<const uint2 *>(&r);
+    } else if constexpr (B == 4) {
+        *reinterpret_cast<uint32_t *>(p) = *reinterpret_cast<const uint32_t *>(&r);
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) p[i] = r.v[i];
+    }
+}
+
+constexpr int kTileVecs = 4;  // 16-byte vectors per thread and plane
+
+// A workgroup owns full-width rows [j0, j0 + TY) of one field and marches
+// through the nz planes.  The current plane of the tile plus one halo row on
+// each side sits in LDS (double-buffered, so one barrier per plane); the
+// planes below and above are carried in registers.  Every global access of
+// the field is a 16-byte vector access of consecutive cells.  Workgroups are
+// ordered tile-fastest within a field and each XCD walks a contiguous range,
+// so the halo rows (read by the neighbouring tile of the same field) and the
+// coefficients of the tiles are served from that XCD's L2.
+template <class Tin, class Tout, class Tc, class Acc, bool kResidual>
+__global__ __launch_bounds__(kThreads) void stencil_tile_kernel(
+    const Tc *__restrict__ diag, const Tc *__restrict__ wx, const Tc *__restrict__ wy, const Tc *__restrict__ wz,
+    int nx, int ny, int nz, const Tin *__restrict__ X, int64_t ldx, Tout *__restrict__ Y, int64_t ldy,
+    const double *__restrict__ Bres, int64_t ldb, int TY, int ntiles, uint32_t nblocks, const int *__restrict__ skip,
+    int *stop)
+{
+    constexpr int VX = 16 / sizeof(Tin);
+    constexpr int R = kTileVecs;
+    if (skip && *skip) {
+        if (stop && blockIdx.x == 0 && threadIdx.x == 0) *stop = 1;
+        return;
+    }
+    const uint32_t lb = remap_block(blockIdx.x, nblocks);
+    const int tile = static_cast<int>(lb % ntiles);
+    const int64_t field = lb / ntiles;
+    const int j0 = tile * TY;
+    const int rows = min(TY, ny - j0);
+    const int64_t plane = static_cast<int64_t>(nx) * ny;
+    const int nvx = nx / VX;  // vectors per row
+    const int nv = rows * nvx;
+    extern __shared__ __align__(16) unsigned char smem[];
+    Acc *buf0 = reinterpret_cast<Acc *>(smem);
+    const int bufsz = (TY + 2) * nx;
+    const Tin *xf = X + field * ldx;
+    Tout *yf = Y + field * ldy;
+    const double *bf = kResidual ? Bres + field * ldb : nullptr;
+    const int tid = threadIdx.x;
+
+    int vrow[R], vx0[R];
+    bool vok[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int q = tid + r * kThreads;
+        vok[r] = q < nv;
+        vrow[r] = vok[r] ? q / nvx : 0;
+        vx0[r] = vok[r] ? (q % nvx) * VX : 0;
+    }
+    Acc prev[R][VX], cur[R][VX], nxt[R][VX], wzm[R][VX];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int e = 0; e < VX; ++e) {
+            prev[r][e] = Acc(0);
+            wzm[r][e] = Acc(0);
+            cur[r][e] = Acc(0);
+        }
+        if (vok[r]) {
+            const Vec<Tin, VX> v = vload<Tin, VX>(xf + static_cast<int64_t>(j0 + vrow[r]) * nx + vx0[r]);
+#pragma unroll
+            for (int e = 0; e < VX; ++e) cur[r][e] = load_as<Acc>(&v.v[e]);
+        }
+    }
+    // halo work: rows j0 - 1 and j0 + rows of the current plane
+    const int hq = tid;  // < 2 * nvx handled by this thread
+    const bool hok = hq < 2 * nvx;
+    const int hside = hok ? hq / nvx : 0;
+    const int hx0 = hok ? (hq % nvx) * VX : 0;
+    const int hy = hside == 0 ? j0 - 1 : j0 + rows;
+    const bool hin = hok && hy >= 0 && hy < ny;
+    const int hlrow = hside == 0 ? 0 : rows + 1;
+
+    for (int l = 0; l < nz; ++l) {
+        const int64_t pl = static_cast<int64_t>(l) * plane;
+        // prefetch the plane above
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+#pragma unroll
+            for (int e = 0; e < VX; ++e) nxt[r][e] = Acc(0);
+            if (vok[r] && l + 1 < nz) {
+                const Vec<Tin, VX> v = vload<Tin, VX>(xf + pl + plane + static_cast<int64_t>(j0 + vrow[r]) * nx + vx0[r]);
+#pragma unroll
+                for (int e = 0; e < VX; ++e) nxt[r][e] = load_as<Acc>(&v.v[e]);
+            }
+        }
+        // current plane of the tile into LDS, with the halo rows (zero outside the grid)
+        Acc *buf = buf0 + (l & 1) * bufsz;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (vok[r]) {
+#pragma unroll
+                for (int e = 0; e < VX; ++e) buf[(vrow[r] + 1) * nx + vx0[r] + e] = cur[r][e];
+            }
+        }
+        if (hok) {
+            Acc hv[VX];
+#pragma unroll
+            for (int e = 0; e < VX; ++e) hv[e] = Acc(0);
+            if (hin) {
+                const Vec<Tin, VX> v = vload<Tin, VX>(xf + pl + static_cast<int64_t>(hy) * nx + hx0);
+#pragma unroll
+                for (int e = 0; e < VX; ++e) hv[e] = load_as<Acc>(&v.v[e]);
+            }
+#pragma unroll
+            for (int e = 0; e < VX; ++e) buf[hlrow * nx + hx0 + e] = hv[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!vok[r]) continue;
+            const int j = j0 + vrow[r];
+            const int64_t a = pl + static_cast<int64_t>(j) * nx + vx0[r];
+            const Vec<Tc, VX> d = vload<Tc, VX>(diag + a);
+            const Vec<Tc, VX> cx = vload<Tc, VX>(wx + a);
+            const Vec<Tc, VX> cy = vload<Tc, VX>(wy + a);
+            const Vec<Tc, VX> cz = vload<Tc, VX>(wz + a);
+            Acc cym[VX];
+            if (j > 0) {
+                const Vec<Tc, VX> t = vload<Tc, VX>(wy + a - nx);
+#pragma unroll
+                for (int e = 0; e < VX; ++e) cym[e] = static_cast<Acc>(t.v[e]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VX; ++e) cym[e] = Acc(0);
+            }
+            const Acc cxm0 = vx0[r] > 0 ? static_cast<Acc>(wx[a - 1]) : Acc(0);
+            const Acc *brow = buf + (vrow[r] + 1) * nx + vx0[r];
+            const Acc left = vx0[r] > 0 ? brow[-1] : Acc(0);
+            const Acc right = vx0[r] + VX < nx ? brow[VX] : Acc(0);
+            Vec<Tout, VX> out;
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                const Acc xm = e > 0 ? cur[r][e - 1] : left;
+                const Acc xp = e < VX - 1 ? cur[r][e + 1] : right;
+                const Acc cxm = e > 0 ? static_cast<Acc>(cx.v[e - 1]) : cxm0;
+                const Acc up = brow[e - nx];
+                const Acc dn = brow[e + nx];
+                const Acc nb = cxm * xm + static_cast<Acc>(cx.v[e]) * xp + cym[e] * up +
+                               static_cast<Acc>(cy.v[e]) * dn + wzm[r][e] * prev[r][e] +
+                               static_cast<Acc>(cz.v[e]) * nxt[r][e];
+                Acc y = static_cast<Acc>(d.v[e]) * cur[r][e] - nb;
+                if constexpr (kResidual) y = static_cast<Acc>(bf[a + e]) - y;
+                out.v[e] = store_from<Tout, Acc>(y);
+                wzm[r][e] = static_cast<Acc>(cz.v[e]);
+            }
+            vstore<Tout, VX>(yf + a, out);
+        }
+        // roll the register planes
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                prev[r][e] = cur[r][e];
+                cur[r][e] = nxt[r][e];
+            }
+    }
+}
+
+// Tile height: about kThreads * VX * kTileVecs cells per plane, lowered until
+// the launch has enough workgroups to fill the chip.
+inline int tile_rows(int nx, int ny, int m, int vx)
+{
+    int ty = std::max(1, std::min(ny, kThreads * vx * kTileVecs / nx));
+    while (ty > 2 && static_cast<int64_t>((ny + ty - 1) / ty) * m < 2048) ty = (ty + 1) / 2;
+    return ty;
+}
+
 template <class Tin, class Tout, class Tc, class Acc, bool kResidual>
 bko_status run(const Operator &op, const Tc *diag, const Tc *wx, const Tc *wy, const Tc *wz, int m,
                const void *X, int64_t ldx, void *Y, int64_t ldy, const double *Bres, int64_t ldb,
                hipStream_t stream, const int *skip, int *stop)
 {
+    constexpr int VX = 16 / sizeof(Tin);
+    // one halo vector per thread: two halo rows of nx / VX vectors each
+    const bool tiled = op.nx % VX == 0 && 2 * (op.nx / VX) <= kThreads &&
+                       reinterpret_cast<uintptr_t>(X) % 16 == 0 && (ldx * sizeof(Tin)) % 16 == 0 &&
+                       reinterpret_cast<uintptr_t>(Y) % (VX * sizeof(Tout) >= 16 ? 16 : VX * sizeof(Tout)) == 0 &&
+                       (ldy * sizeof(Tout)) % (VX * sizeof(Tout) >= 16 ? 16 : VX * sizeof(Tout)) == 0;
+    if (tiled) {
+        const int ty = tile_rows(op.nx, op.ny, m, VX);
+        // short tiles waste the halo and most threads: the per-cell kernel is
+        // better there (e.g. the few-column products inside the block solve)
+        if ((ty >= 8 || ty == op.ny) &&
+            static_cast<int64_t>(ty) * op.nx <= static_cast<int64_t>(kThreads) * VX * kTileVecs) {
+            const int ntiles = (op.ny + ty - 1) / ty;
+            const uint64_t nb = static_cast<uint64_t>(ntiles) * m;
+            if (nb <= 0x7fffffffu) {
+                const size_t lds = 2 * sizeof(Acc) * static_cast<size_t>(ty + 2) * op.nx;
+                hipLaunchKernelGGL((stencil_tile_kernel<Tin, Tout, Tc, Acc, kResidual>), dim3(static_cast<uint32_t>(nb)),
+                                   dim3(kThreads), lds, stream, diag, wx, wy, wz, op.nx, op.ny, op.nz,
+                                   static_cast<const Tin *>(X), ldx, static_cast<Tout *>(Y), ldy, Bres, ldb, ty, ntiles,
+                                   static_cast<uint32_t>(nb), skip, stop);
+                BKO_HIP(hipGetLastError());
+                return BKO_OK;
+            }
+        }
+    }
     const uint32_t ntiles = static_cast<uint32_t>((op.n + kThreads - 1) / kThreads);
     // enough column groups to fill the chip, few enough that each thread
     // reuses its coefficients over several columns
