@@ -164,6 +164,29 @@ bko_status bko_block_krylov_solve(bko_op A, int s, const double *B, int ldb, dou
                                   int max_iter, void *work, size_t work_bytes,
                                   bko_solve_info *info, void *stream);
 
+/* ------------------------------------------- per-sample CG (the baseline) */
+
+/* Workspace bytes for bko_cg_solve with m right-hand sides. */
+bko_status bko_cg_workspace_bytes(bko_op A, int m, size_t *bytes);
+
+/*
+ * The direct method the paper compares against (Sec. III, the per-sample
+ * baseline of Table 1): an independent conjugate gradient solve of
+ * A x_j = b_j for each of m columns, without sharing a Krylov space.  Columns
+ * are batched so one stencil launch serves them all, but every column has
+ * its own step lengths and stops on its own recurrence residual
+ * ||r_j|| <= tol ||b_j|| (x_0 = 0, FP64, no preconditioner).
+ *   B (n x m, ldb >= n) and X (n x m, ldx >= n) FP64 device.
+ *   iters (host, may be NULL) receives m per-column iteration counts.
+ *   info (host, may be NULL): iters = the largest column count, max_rel_res
+ *   the largest FP64 true relative residual at exit.
+ * Returns BKO_ENOCONV if a column is still running after max_iter
+ * iterations.  Synchronises the stream.
+ */
+bko_status bko_cg_solve(bko_op A, int m, const double *B, int ldb, double *X, int ldx, double tol,
+                        int max_iter, void *work, size_t work_bytes, int *iters, bko_solve_info *info,
+                        void *stream);
+
 /* ------------------------------------------------- combination (T = X C) */
 
 /*

@@ -33,7 +33,8 @@ DTYPE_NAME = {"f64": F64, "f32": F32, "bf16": BF16}
 EXPORTED = ("bko_version", "bko_last_error", "bko_operator_bytes", "bko_assemble_heat_operator",
             "bko_operator_dims", "bko_destroy_operator", "bko_block_krylov_workspace_bytes",
             "bko_block_krylov_solve", "bko_combine", "bko_apply_operator", "bko_residual",
-            "bko_timing_enable", "bko_timing_query", "bko_timing_reset")
+            "bko_timing_enable", "bko_timing_query", "bko_timing_reset", "bko_cg_workspace_bytes",
+            "bko_cg_solve")
 
 
 class BlockoaError(RuntimeError):
@@ -80,6 +81,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bko_timing_enable": (i32, [i32]),
         "bko_timing_query": (i32, [i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
         "bko_timing_reset": (i32, []),
+        "bko_cg_workspace_bytes": (i32, [vp, i32, ctypes.POINTER(sz)]),
+        "bko_cg_solve": (i32, [vp, i32, vp, i32, vp, i32, dbl, i32, vp, sz, ctypes.POINTER(i32),
+                               ctypes.POINTER(SolveInfo), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -223,6 +227,39 @@ def block_krylov_solve(A: HeatOperator, B: torch.Tensor, tol: float, compute: in
     d = info.as_dict()
     d["status_name"] = STATUS_NAMES.get(st, str(st))
     return X, d
+
+
+def cg_workspace_bytes(A: HeatOperator, m: int) -> int:
+    out = ctypes.c_size_t()
+    _check(load_library().bko_cg_workspace_bytes(A.handle, m, ctypes.byref(out)))
+    return out.value
+
+
+def cg_solve(A: HeatOperator, B: torch.Tensor, tol: float, max_iter: int = 100000,
+             X: Optional[torch.Tensor] = None, stream=None, check: bool = True):
+    """Per-sample CG baseline: an independent FP64 CG for every row of B
+    ((m, N) FP64 on the GPU).  Returns (X, per-column iteration counts as a
+    numpy array, info dict)."""
+    import numpy as np
+
+    m = B.shape[0]
+    bp, ldb, bt = _block(B, "B")
+    if bt != F64:
+        raise ValueError("B must be float64")
+    if X is None:
+        X = torch.empty_like(B)
+    xp, ldx, _ = _block(X, "X")
+    nbytes = cg_workspace_bytes(A, m)
+    buf, wptr = _aligned_workspace(nbytes, B.device)
+    iters = (ctypes.c_int * m)()
+    info = SolveInfo()
+    st = load_library().bko_cg_solve(A.handle, m, bp, ldb, xp, ldx, tol, max_iter, ctypes.c_void_p(wptr), nbytes,
+                                     iters, ctypes.byref(info), _stream(stream))
+    if check and st != OK:
+        _check(st)
+    d = info.as_dict()
+    d["status_name"] = STATUS_NAMES.get(st, str(st))
+    return X, np.array(iters[:], dtype=np.int64), d
 
 
 def combine(X: torch.Tensor, C: torch.Tensor, out_dtype=torch.float64, compute: int = F64,

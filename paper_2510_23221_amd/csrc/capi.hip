@@ -422,6 +422,35 @@ bko_status bko_block_krylov_solve(bko_op A, int s, const double *B, int ldb, dou
     BKO_GUARD_END
 }
 
+bko_status bko_cg_workspace_bytes(bko_op A, int m, size_t *bytes)
+{
+    BKO_CHECK(A != nullptr && bytes != nullptr, "NULL argument");
+    BKO_CHECK(m >= 1 && m <= 65535, "m = %d outside [1, 65535]", m);
+    *bytes = cg_workspace_bytes(reinterpret_cast<const Operator *>(A)->n, m);
+    return BKO_OK;
+}
+
+bko_status bko_cg_solve(bko_op A, int m, const double *B, int ldb, double *X, int ldx, double tol, int max_iter,
+                        void *work, size_t work_bytes, int *iters, bko_solve_info *info, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(A != nullptr, "operator handle is NULL");
+    const Operator &op = *reinterpret_cast<const Operator *>(A);
+    BKO_CHECK(m >= 1 && m <= 65535, "m = %d outside [1, 65535]", m);
+    BKO_CHECK(B && X && work, "NULL array");
+    BKO_CHECK(ldb >= op.n && ldx >= op.n, "leading dimensions must be >= n");
+    BKO_CHECK(tol > 0.0 && std::isfinite(tol), "tol must be positive");
+    BKO_CHECK(max_iter >= 1, "max_iter must be >= 1");
+    BKO_CHECK(reinterpret_cast<uintptr_t>(work) % 256 == 0, "workspace must be 256-byte aligned");
+    const size_t need = cg_workspace_bytes(op.n, m);
+    if (work_bytes < need) {
+        set_error("workspace has %zu bytes, need %zu", work_bytes, need);
+        return BKO_ENOMEM;
+    }
+    return cg_solve(op, m, B, ldb, X, ldx, tol, max_iter, work, iters, info, static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
 bko_status bko_timing_enable(int enable)
 {
     TimingState &t = timing();

@@ -26,4 +26,9 @@ bko_status block_solve(const Operator &op, int s, const double *B, int64_t ldb, 
                        int max_iter, void *work, size_t work_bytes, bko_solve_info *info,
                        hipStream_t stream);
 
+size_t cg_workspace_bytes(int64_t n, int m);
+
+bko_status cg_solve(const Operator &op, int m, const double *B, int64_t ldb, double *X, int64_t ldx, double tol,
+                    int max_iter, void *work, int *iters_host, bko_solve_info *info, hipStream_t stream);
+
 }  // namespace bko

@@ -344,3 +344,54 @@ def test_pipeline_config1_full(dev):
     Bc = w.C[0] @ w.B[0]
     rel = np.linalg.norm(Fn - Bc, axis=1) / np.linalg.norm(Bc, axis=1)
     assert rel.max() <= 1e-8
+
+
+# ------------------------------------------------------------------ per-sample CG baseline
+
+@pytest.mark.parametrize("kind", ["2d", "ragged", "stack"])
+def test_per_sample_cg_matches_oracle(ops, dev, kind):
+    """Independent CG per column (the paper's direct baseline): same stopping
+    rule as the oracle's CG, so per-column iteration counts agree up to
+    rounding, and the solutions meet the residual target."""
+    chip, A, G = ops[kind]
+    rng = np.random.default_rng(11)
+    B = rng.standard_normal((9, A.n))
+    B[4] = 0.0
+    tol = 1e-10
+    X, iters, info = capi.cg_solve(G, torch.as_tensor(B, device=dev), tol)
+    X = to_np(X)
+    X_ref, it_ref, _ = oracle.cg_many(A, B, tol)
+    assert np.abs(iters - it_ref).max() <= 2, (iters, it_ref)
+    assert iters[4] == 0 and np.abs(X[4]).max() == 0.0
+    R = B - oracle.apply_many(A, X)
+    bn = np.linalg.norm(B, axis=1)
+    rel = np.linalg.norm(R, axis=1) / np.where(bn > 0, bn, 1)
+    floor = 8 * U64 * np.linalg.norm(oracle.apply_many(abs_csr(A), np.abs(X)) + np.abs(B), axis=1) \
+        / np.where(bn > 0, bn, 1)
+    # the recurrence residual stops at tol; the true one drifts by rounding
+    assert (rel <= 10 * tol + floor).all(), rel.max()
+    assert abs(info["max_rel_res"] - rel.max()) <= 0.01 * rel.max() + floor.max()
+    assert info["iters"] == iters.max()
+    X13, _, _ = oracle.cg_many(A, B, 1e-13)
+    assert rel_fro(X, X13) <= 1e-6
+
+
+def test_per_sample_cg_no_convergence_reports(ops, dev):
+    chip, A, G = ops["2d"]
+    rng = np.random.default_rng(12)
+    B = torch.as_tensor(rng.standard_normal((3, A.n)), device=dev)
+    X, iters, info = capi.cg_solve(G, B, 1e-12, max_iter=5, check=False)
+    assert info["status"] == capi.ENOCONV and (iters == 5).all()
+    with pytest.raises(capi.BlockoaError):
+        capi.cg_solve(G, B, 1e-12, max_iter=5)
+
+
+def test_block_beats_per_sample_cg_iterations(dev):
+    """Sec. V-E: the shared Krylov space of the block solve needs fewer
+    iterations than one CG per right-hand side on the config-1 workload."""
+    w = synth.workload(0)
+    G = capi.HeatOperator.from_chip(w.chips[0], dev)
+    B = torch.as_tensor(w.B[0], device=dev)
+    _, info_b = capi.block_krylov_solve(G, B, w.tol)
+    _, iters, _ = capi.cg_solve(G, B, w.tol)
+    assert info_b["iters"] < iters.mean()
