@@ -140,10 +140,9 @@ def main():
     per_launch_bytes = {
         "apply": n * m * 2 * wt + n * 4 * wc,
         "combine": n * m * wt + n * s * 8 + s * m * 8,
-        "spmm": n * s * 2 * wv + n * 4 * wcv,
-        "gram": ldw * s * 2 * wv,
-        "update_w": ldw * s * 3 * wv,
-        "update_dqp": ldw * s * 6 * wv,
+        "spmm": n * s * 2 * wv + n * 4 * wcv,    # stencil + P^T AP Gram: P read, AP written
+        "update_w": ldw * s * 3 * wv,           # W, AP read; W written
+        "update_dqp": ldw * s * 5 * wv,         # D, P, W read; D, P written
         "resid": n * s * 3 * 8 + n * 4 * 8,
     }
 

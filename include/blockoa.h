@@ -164,6 +164,51 @@ bko_status bko_block_krylov_solve(bko_op A, int s, const double *B, int ldb, dou
                                   int max_iter, void *work, size_t work_bytes,
                                   bko_solve_info *info, void *stream);
 
+/* ------------------------------------------------- batches of chips */
+
+typedef struct bko_batch_plan *bko_batch;
+
+/*
+ * A batch of chips solved together: the chip index j of Eq. (4) (Sec. III-A)
+ * runs over the batch, each chip with its own operator and grid, all with
+ * the same s and inner compute dtype.  Every kernel of a block iteration
+ * covers all chips in one launch (a workgroup table maps workgroups to
+ * chips), chips that have converged drop out at the next launch, and the
+ * iteration chunks between convergence checks are captured into HIP graphs
+ * and replayed when the stream is not the null stream.
+ *   ops   host array of nchips operator handles (they must outlive the plan).
+ * The plan holds host metadata only.
+ */
+bko_status bko_batch_plan_create(int nchips, const bko_op *ops, int s, bko_dtype compute, bko_batch *out);
+bko_status bko_batch_plan_destroy(bko_batch plan);
+
+/* Workspace bytes of a batch solve (caller-owned, 256-byte aligned). */
+bko_status bko_batch_workspace_bytes(bko_batch plan, size_t *bytes);
+
+/*
+ * Autotuner: times the row kernels of the whole batch for each candidate
+ * per-chip workgroup count (64, 128, 256, 512: how many row tiles each
+ * workgroup walks and how many Gram partials each reduction sums) and keeps
+ * the fastest in the plan.  The workspace contents are overwritten.  wg_cap
+ * (host, may be NULL) receives the choice.  bko_batch_solve tunes on its
+ * first call if this was not called.  Synchronises the stream.
+ */
+bko_status bko_batch_tune(bko_batch plan, void *work, size_t work_bytes, int *wg_cap, void *stream);
+
+/*
+ * Solve A_c X_c = B_c for every chip c of the plan (semantics of
+ * bko_block_krylov_solve per chip).  B, X, X0 are host arrays of nchips
+ * device pointers (n_c x s, column major, leading dimensions in ldb, ldx,
+ * ldx0); X0 may be NULL, or hold NULL for a zero start of that chip.
+ * infos (host, may be NULL) receives nchips records.  Returns BKO_OK when
+ * every chip converged, else the first failing chip's status (each chip's
+ * own status is in infos).  Synchronises the stream.
+ */
+bko_status bko_batch_solve(bko_batch plan, const double *const *B, const int *ldb, double *const *X,
+                           const int *ldx, const double *const *X0, const int *ldx0, double tol,
+                           int max_iter, void *work, size_t work_bytes, bko_solve_info *infos,
+                           void *stream);
+
 /* ------------------------------------------- per-sample CG (the baseline) */
 
 /* Workspace bytes for bko_cg_solve with m right-hand sides. */

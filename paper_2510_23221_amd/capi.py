@@ -34,7 +34,8 @@ EXPORTED = ("bko_version", "bko_last_error", "bko_operator_bytes", "bko_assemble
             "bko_operator_dims", "bko_destroy_operator", "bko_block_krylov_workspace_bytes",
             "bko_block_krylov_solve", "bko_combine", "bko_apply_operator", "bko_residual",
             "bko_timing_enable", "bko_timing_query", "bko_timing_reset", "bko_cg_workspace_bytes",
-            "bko_cg_solve")
+            "bko_cg_solve", "bko_batch_plan_create", "bko_batch_plan_destroy", "bko_batch_workspace_bytes",
+            "bko_batch_tune", "bko_batch_solve")
 
 
 class BlockoaError(RuntimeError):
@@ -82,6 +83,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bko_timing_query": (i32, [i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
         "bko_timing_reset": (i32, []),
         "bko_cg_workspace_bytes": (i32, [vp, i32, ctypes.POINTER(sz)]),
+        "bko_batch_plan_create": (i32, [i32, ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp)]),
+        "bko_batch_plan_destroy": (i32, [vp]),
+        "bko_batch_workspace_bytes": (i32, [vp, ctypes.POINTER(sz)]),
+        "bko_batch_tune": (i32, [vp, vp, sz, ctypes.POINTER(i32), vp]),
+        "bko_batch_solve": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(vp),
+                                  ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(i32), dbl, i32, vp, sz,
+                                  ctypes.POINTER(SolveInfo), vp]),
         "bko_cg_solve": (i32, [vp, i32, vp, i32, vp, i32, dbl, i32, vp, sz, ctypes.POINTER(i32),
                                ctypes.POINTER(SolveInfo), vp]),
     }
@@ -227,6 +235,97 @@ def block_krylov_solve(A: HeatOperator, B: torch.Tensor, tol: float, compute: in
     d = info.as_dict()
     d["status_name"] = STATUS_NAMES.get(st, str(st))
     return X, d
+
+
+class BatchPlan:
+    """A batch of chips solved together (one s and compute dtype for all):
+    grouped launches over every chip, graph-captured iteration chunks on a
+    non-null stream, per-chip workgroup counts chosen by the autotuner."""
+
+    def __init__(self, ops: Sequence[HeatOperator], s: int, compute: int = F64):
+        lib = load_library()
+        self.ops = list(ops)
+        self.s = s
+        self.compute = compute
+        arr = (ctypes.c_void_p * len(self.ops))(*[o.handle.value for o in self.ops])
+        h = ctypes.c_void_p()
+        _check(lib.bko_batch_plan_create(len(self.ops), arr, s, compute, ctypes.byref(h)))
+        self.handle = h
+        self._work = None
+
+    def workspace_bytes(self) -> int:
+        out = ctypes.c_size_t()
+        _check(load_library().bko_batch_workspace_bytes(self.handle, ctypes.byref(out)))
+        return out.value
+
+    def _workspace(self, device):
+        nbytes = self.workspace_bytes()
+        if self._work is None or self._work[2] < nbytes:
+            buf, ptr = _aligned_workspace(nbytes, device)
+            self._work = (buf, ptr, nbytes)
+        return self._work[1], self._work[2]
+
+    def tune(self, device="cuda", stream=None) -> int:
+        ptr, nbytes = self._workspace(device)
+        cap = ctypes.c_int()
+        _check(load_library().bko_batch_tune(self.handle, ctypes.c_void_p(ptr), nbytes, ctypes.byref(cap),
+                                             _stream(stream)))
+        return cap.value
+
+    def solve(self, Bs: Sequence[torch.Tensor], tol: float, max_iter: int = 100000, X0s=None, Xs=None,
+              stream=None, check: bool = True):
+        """Bs: one (s, N_c) FP64 tensor per chip.  Returns (Xs, list of info dicts)."""
+        nc = len(self.ops)
+        if len(Bs) != nc:
+            raise ValueError("one right-hand-side block per chip")
+        if Xs is None:
+            Xs = [torch.empty_like(b) for b in Bs]
+        bp, lb, xp, lx = [], [], [], []
+        for b, x in zip(Bs, Xs):
+            p, ld, t = _block(b, "B")
+            if t != F64:
+                raise ValueError("B must be float64")
+            bp.append(p.value)
+            lb.append(ld)
+            p, ld, _ = _block(x, "X")
+            xp.append(p.value)
+            lx.append(ld)
+        VP, I32 = ctypes.c_void_p * nc, ctypes.c_int * nc
+        x0a, lx0a = None, None
+        if X0s is not None:
+            x0p, lx0 = [], []
+            for x0 in X0s:
+                if x0 is None:
+                    x0p.append(None)
+                    lx0.append(0)
+                else:
+                    p, ld, _ = _block(x0, "X0")
+                    x0p.append(p.value)
+                    lx0.append(ld)
+            x0a, lx0a = VP(*x0p), I32(*lx0)
+        ptr, nbytes = self._workspace(Bs[0].device)
+        infos = (SolveInfo * nc)()
+        st = load_library().bko_batch_solve(self.handle, VP(*bp), I32(*lb), VP(*xp), I32(*lx), x0a, lx0a, tol,
+                                            max_iter, ctypes.c_void_p(ptr), nbytes, infos, _stream(stream))
+        if check and st != OK:
+            _check(st)
+        out = []
+        for i in infos:
+            d = i.as_dict()
+            d["status_name"] = STATUS_NAMES.get(d["status"], str(d["status"]))
+            out.append(d)
+        return Xs, out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load_library().bko_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def cg_workspace_bytes(A: HeatOperator, m: int) -> int:

@@ -1,5 +1,6 @@
 // Block Krylov solve of A X = B for s right-hand sides sharing one heat
-// operator (Sec. III-A, Eq. (4)).
+// operator (Sec. III-A, Eq. (4)), for one chip or for a batch of chips of
+// different grids at once (the chip index j of Eq. (4) runs over the batch).
 //
 // The paper names block CG without fixing a variant.  This is the retooled
 // block CG that carries an orthonormal residual basis Q (R = Q C) so that
@@ -9,30 +10,37 @@
 // search block:
 //     AP    = A P                                  (stencil product)
 //     delta = P^T AP                               (FP64 Gram)
-//     W     = Q - AP delta^+                       (next residual basis)
-//     W^T W = S^T S  (S upper triangular)          (Cholesky QR, FP64)
-//     D    += P delta^+ C ;  Q = W S^+ ;  P = Q + P S^T ;  C = S C
+//     W'    = Q - AP delta^+                       (next residual basis)
+//     W'^T W' = S^T S  (S upper triangular)        (Cholesky QR, FP64)
+//     D    += P delta^+ C ;  Q' = W' S^+ ;  P = Q' + P S^T ;  C = S C
 // and ||r_j|| = ||C e_j||, so convergence is read off C without a pass over
-// the residual.
+// the residual.  Q is never stored: the kernels form Q = W S^+ from the W of
+// the previous step when they need it (W is updated in place).
 //
-// Kernels per iteration, all on one stream with no host round trip; the
-// kernel boundary is the only grid-wide synchronisation (an in-kernel fence
-// per workgroup costs far more on this chip than the boundary):
-//   spmm        AP = A P                       (stencil.hip)
-//   gram        per-workgroup P^T AP partials on the FP64 matrix cores
+// Grouped launches: every kernel of an iteration covers all chips of the
+// batch in one launch.  A table maps each workgroup to its chip, and each
+// chip's parameters (grid, coefficient and block pointers, small matrices,
+// control words) sit in a device array that the kernels read; a chip that
+// has converged makes its workgroups return at once.  Kernels per iteration,
+// all on one stream with no host round trip (the kernel boundary is the only
+// grid-wide synchronisation: an in-kernel fence per workgroup costs far more
+// on this chip than the boundary):
+//   spmm_gram   AP = A P (matrix-free stencil), with P and AP staged in LDS
+//               and their per-workgroup P^T AP partials on the FP64 matrix
+//               cores
 //   reduce      the partials summed entry by entry, in index order
-//   factor      one 1024-thread workgroup: delta^+ and delta^+ C
-//   update_w    W = Q - AP delta^+ on the matrix cores, and the W^T W
-//               partials from the same registers (the 16x16 result layout is
-//               the operand layout of the FP64 Gram product)
+//   factor      one workgroup per chip: delta^+ and delta^+ C
+//   update_w    W <- W S^+ - AP delta^+ on the matrix cores, and the W^T W
+//               partials from the same registers
 //   reduce
 //   factor      W^T W = S^T S, C <- S C, convergence test
-//   update_dqp  D += P delta^+ C, Q = W S^+, P = Q + P S^T
+//   update_dqp  D += P delta^+ C, P = W S^+ + P S^T
+// The iteration chunks between convergence checks can be replayed from
+// captured HIP graphs.
 //
 // The s x s factorisations are an LDL^T elimination of [G | I] without
 // pivoting in which a pivot below a relative threshold deactivates its index
-// (its row and column of every derived matrix are zero): one barrier per
-// pivot, every thread owning fixed entries.
+// (its row and column of every derived matrix are zero).
 //
 // Storage: the N x s blocks are FP64 or FP32 (compute = BKO_F32); Gram
 // matrices, factorisations, small matrices and the outer residual are FP64.
@@ -41,6 +49,8 @@
 // iterative refinement in the mixed-precision mode).
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <map>
 #include <type_traits>
 #include <vector>
 
@@ -53,16 +63,16 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 256;      // block kernels
+constexpr int kThreads = 256;      // row kernels
 constexpr int kFacThreads = 256;   // factorisation kernel
 constexpr int kMaxS = 64;
-constexpr int kMaxBlocks = 512;    // partial producers per launch
-constexpr int kRedBlocks = 64;     // reducer workgroups
-constexpr int kTileRows = 256;     // rows per workgroup tile (4 waves x 64)
+constexpr int kRedBlocks = 64;     // reducer workgroups per chip
+constexpr int kTileRows = 256;     // rows per tile of the row kernels (4 waves x 64)
+constexpr int kCtrlInts = 16;      // control words per chip
 
 // ------------------------------------------------------------------ layout
 
-enum Ctrl { kConverged = 0, kStop = 1, kIters = 2, kDeflated = 3, kAllDeflated = 4 };
+enum Ctrl { kConverged = 0, kStop = 1, kIters = 2, kDeflated = 3, kAllDeflated = 4, kActive = 5 };
 
 struct Small {
     // FP64, row-major s x s: M[k][j] maps input column k to output column j
@@ -71,54 +81,30 @@ struct Small {
     float *M1f, *M2f, *M3f, *M4f;
 };
 
-struct Workspace {
-    int64_t ldw;                 // padded rows of every internal block
-    double *R64;                 // outer residual, FP64
-    void *Dv, *Q, *P, *AP, *W;   // inner blocks in the storage type
+// What a grouped kernel knows about one chip.
+struct ChipDev {
+    // operator: coefficients in the block precision, and in FP64
+    const void *cdiag, *cwx, *cwy, *cwz;
+    const double *d64, *x64, *y64, *z64;
+    int nx, ny, nz, wgs;   // wgs: workgroups of the row kernels for this chip
+    int64_t n, ldw;        // cells, padded rows of every internal block
+    int wg_base, pad;
+    // caller arrays (FP64, column major)
+    const double *B;
+    int64_t ldb;
+    double *X;
+    int64_t ldx;
+    const double *X0;
+    int64_t ldx0;
+    // inner blocks (block precision) and the FP64 residual
+    void *Dv, *P, *AP, *W;
+    double *R64;
     Small sm;
-    double *parts;               // Gram partials [kMaxBlocks][s][s]
-    double *gram;                // reduced Gram [s][s]
-    int *ctrl;
-    double *colparts;            // column-norm partials [128][s]
-    size_t bytes;
+    double *parts;  // [wgs][s][s] Gram partials, also [wgs][s] column sums
+    double *gram;   // [s][s]
+    double *norms;  // [kMaxS] squared column norms
+    int *ctrl;      // kCtrlInts control words
 };
-
-inline Workspace carve(void *base, int64_t n, int s, bko_dtype compute)
-{
-    Workspace w{};
-    w.ldw = static_cast<int64_t>(align_up(static_cast<size_t>(n), kTileRows));
-    const size_t vsz = compute == BKO_F64 ? 8 : 4;
-    const size_t ss = static_cast<size_t>(s) * s;
-    char *p = static_cast<char *>(base);
-    size_t o = 0;
-    auto take = [&](size_t bytes) {
-        char *q = p + o;
-        o = align_up(o + bytes, 256);
-        return q;
-    };
-    w.R64 = reinterpret_cast<double *>(take(sizeof(double) * w.ldw * s));
-    w.Dv = take(vsz * w.ldw * s);
-    w.Q = take(vsz * w.ldw * s);
-    w.P = take(vsz * w.ldw * s);
-    w.AP = take(vsz * w.ldw * s);
-    w.W = take(vsz * w.ldw * s);
-    w.sm.C = reinterpret_cast<double *>(take(sizeof(double) * ss));
-    w.sm.M1 = reinterpret_cast<double *>(take(sizeof(double) * ss));
-    w.sm.M2 = reinterpret_cast<double *>(take(sizeof(double) * ss));
-    w.sm.M3 = reinterpret_cast<double *>(take(sizeof(double) * ss));
-    w.sm.M4 = reinterpret_cast<double *>(take(sizeof(double) * ss));
-    w.sm.th = reinterpret_cast<double *>(take(sizeof(double) * kMaxS));
-    w.sm.M1f = reinterpret_cast<float *>(take(sizeof(float) * ss));
-    w.sm.M2f = reinterpret_cast<float *>(take(sizeof(float) * ss));
-    w.sm.M3f = reinterpret_cast<float *>(take(sizeof(float) * ss));
-    w.sm.M4f = reinterpret_cast<float *>(take(sizeof(float) * ss));
-    w.parts = reinterpret_cast<double *>(take(sizeof(double) * ss * kMaxBlocks));
-    w.gram = reinterpret_cast<double *>(take(sizeof(double) * ss));
-    w.ctrl = reinterpret_cast<int *>(take(sizeof(int) * 64));
-    w.colparts = reinterpret_cast<double *>(take(sizeof(double) * 128 * kMaxS));
-    w.bytes = o;
-    return w;
-}
 
 // ------------------------------------------------------------------ matrix-core helpers
 
@@ -139,12 +125,21 @@ __device__ inline d4 mma64(double a, double b, d4 c) { return __builtin_amdgcn_m
 // index of the (a, b) upper block, a <= b < NB
 template <int NB> __device__ constexpr int ublock(int a, int b) { return a * NB - a * (a - 1) / 2 + (b - a); }
 
+// Chip of this workgroup and the workgroup's index within the chip.
+__device__ inline const ChipDev &chip_of(const ChipDev *cds, const uint16_t *tab, int &local)
+{
+    const ChipDev &cd = cds[tab[blockIdx.x]];
+    local = static_cast<int>(blockIdx.x) - cd.wg_base;
+    return cd;
+}
+
 // ------------------------------------------------------------------ Gram partials
 
-// Sum the four waves' 16x16 FP64 blocks into an s x s partial in LDS and
-// write it to parts[blockIdx.x].  kSym: only upper blocks were formed.
+// Sum the four waves' 16x16 FP64 blocks into an s x s partial in LDS (lds:
+// at least s * s doubles) and write it to out.  kSym: only upper blocks were
+// formed.
 template <int NB, bool kSym, int NBLK>
-__device__ void publish_partial(const d4 (&g)[NBLK], int s, double *lds, double *parts)
+__device__ void publish_partial(const d4 (&g)[NBLK], int s, double *lds, double *out)
 {
     const int ss = s * s;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -169,54 +164,141 @@ __device__ void publish_partial(const d4 (&g)[NBLK], int s, double *lds, double 
         }
         __syncthreads();
     }
-    double *out = parts + static_cast<size_t>(blockIdx.x) * ss;
     for (int e = threadIdx.x; e < ss; e += kThreads) out[e] = lds[e];
 }
 
-// P^T AP over this workgroup's row tiles.
-template <class T, int NB>
-__global__ __launch_bounds__(kThreads) void gram_kernel(const T *__restrict__ P, const T *__restrict__ AP, int64_t ldw,
-                                                        int s, double *__restrict__ parts, const int *__restrict__ ctrl)
+// ------------------------------------------------------------------ stencil product + Gram
+
+// Rows of a 256-row tile staged in LDS at once: the whole tile when P and AP
+// of all 16 NB columns fit in 70 KB (two workgroups per CU), else half.
+template <class T, int NB> __host__ __device__ constexpr int stage_rows()
 {
-    if (ctrl[kConverged]) return;
-    __shared__ double lds[kMaxS * kMaxS];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    return 2 * 16 * NB * (kTileRows + 1) * static_cast<int>(sizeof(T)) <= 70 * 1024 ? kTileRows : kTileRows / 2;
+}
+
+template <class T, int NB> __host__ __device__ constexpr size_t spmm_gram_lds()
+{
+    return 2 * sizeof(T) * 16 * NB * (stage_rows<T, NB>() + 1);
+}
+
+// AP = A P for the chip's tiles, and the chip's P^T AP partial of this
+// workgroup.  Stencil phase: thread (cell, column class) forms the 7-point
+// product of its cell for every column of its class, writes AP, and stages
+// P and AP in LDS; Gram phase: each wave takes a quarter of the staged rows
+// on the FP64 matrix cores.
+template <class T, int NB>
+__global__ __launch_bounds__(kThreads) void spmm_gram_kernel(const ChipDev *__restrict__ cds,
+                                                             const uint16_t *__restrict__ tab, int s)
+{
+    constexpr int TR = stage_rows<T, NB>();
+    constexpr int SP = 16 * NB;
+    constexpr int LD = TR + 1;
+    constexpr int CSTEP = kThreads / TR;  // column classes
+    int local;
+    const ChipDev &cd = chip_of(cds, tab, local);
+    int *ctrl = cd.ctrl;
+    if (ctrl[kConverged]) {
+        // the iteration before this one converged: tell the later kernels
+        if (local == 0 && threadIdx.x == 0) ctrl[kStop] = 1;
+        return;
+    }
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *Ps = reinterpret_cast<T *>(smem);
+    T *APs = Ps + SP * LD;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    const int64_t ntiles = ldw / kTileRows;
+    // columns s .. SP of the staged tiles stay zero
+    for (int e = s * LD + tid; e < SP * LD; e += kThreads) {
+        Ps[e] = T(0);
+        APs[e] = T(0);
+    }
+    const T *__restrict__ P = static_cast<const T *>(cd.P);
+    T *__restrict__ AP = static_cast<T *>(cd.AP);
+    const T *__restrict__ cdiag = static_cast<const T *>(cd.cdiag);
+    const T *__restrict__ cwx = static_cast<const T *>(cd.cwx);
+    const T *__restrict__ cwy = static_cast<const T *>(cd.cwy);
+    const T *__restrict__ cwz = static_cast<const T *>(cd.cwz);
+    const int nx = cd.nx, ny = cd.ny, nz = cd.nz;
+    const int64_t n = cd.n, ldw = cd.ldw;
+    const int64_t plane = static_cast<int64_t>(nx) * ny;
+    const int cell = tid % TR, cls = tid / TR;
+
     d4 acc[NB * NB];
 #pragma unroll
     for (int q = 0; q < NB * NB; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        for (int rb = 0; rb < 4; ++rb) {
-            // rows row + t feed MFMA step t for lane group lg: any bijection of
-            // rows onto k slots works, since the product sums over rows
-            const int64_t row = tile * kTileRows + wave * 64 + rb * 16 + lg * 4;
-            double u[NB][4], v[NB][4];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const int col = b * 16 + li;
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    u[b][t] = col < s ? static_cast<double>(P[col * ldw + row + t]) : 0.0;
-                    v[b][t] = col < s ? static_cast<double>(AP[col * ldw + row + t]) : 0.0;
+    const int64_t ntiles = ldw / kTileRows;
+    for (int64_t tile = local; tile < ntiles; tile += cd.wgs) {
+        for (int half = 0; half < kTileRows / TR; ++half) {
+            const int64_t a = tile * kTileRows + half * TR + cell;
+            if (a < n) {
+                const int i = static_cast<int>(a % nx);
+                const int64_t q = a / nx;
+                const int j = static_cast<int>(q % ny);
+                const int l = static_cast<int>(q / ny);
+                // a missing neighbour reads the cell itself with a zero coupling
+                const int64_t oxm = i > 0 ? -1 : 0, oxp = i < nx - 1 ? 1 : 0;
+                const int64_t oym = j > 0 ? -static_cast<int64_t>(nx) : 0, oyp = j < ny - 1 ? nx : 0;
+                const int64_t ozm = l > 0 ? -plane : 0, ozp = l < nz - 1 ? plane : 0;
+                const T d = cdiag[a];
+                const T cxp = cwx[a], cxm = i > 0 ? cwx[a - 1] : T(0);
+                const T cyp = cwy[a], cym = j > 0 ? cwy[a - nx] : T(0);
+                const T czp = cwz[a], czm = l > 0 ? cwz[a - plane] : T(0);
+#pragma unroll 4
+                for (int c = cls; c < s; c += CSTEP) {
+                    const T *x = P + c * ldw + a;
+                    const T xc = x[0];
+                    const T nb = cxm * x[oxm] + cxp * x[oxp] + cym * x[oym] + cyp * x[oyp] + czm * x[ozm] + czp * x[ozp];
+                    const T y = d * xc - nb;
+                    AP[c * ldw + a] = y;
+                    Ps[c * LD + cell] = xc;
+                    APs[c * LD + cell] = y;
+                }
+            } else {
+                // padding rows of the tile: zero in the Gram (AP keeps its zero padding)
+                for (int c = cls; c < s; c += CSTEP) {
+                    Ps[c * LD + cell] = T(0);
+                    APs[c * LD + cell] = T(0);
                 }
             }
+            __syncthreads();
+            // Gram phase: rows r + t feed MFMA step t for lane group lg (any
+            // bijection of rows onto k slots works, since the product sums
+            // over rows)
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
+            for (int rb = 0; rb < TR / 64; ++rb) {
+                const int r = wave * (TR / 4) + rb * 16 + lg * 4;
+                double u[NB][4], v[NB][4];
 #pragma unroll
-                for (int a = 0; a < NB; ++a)
+                for (int b = 0; b < NB; ++b) {
+                    const int col = b * 16 + li;
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) acc[a * NB + b] = mma64(u[a][t], v[b][t], acc[a * NB + b]);
+                    for (int t = 0; t < 4; ++t) {
+                        u[b][t] = static_cast<double>(Ps[col * LD + r + t]);
+                        v[b][t] = static_cast<double>(APs[col * LD + r + t]);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int x = 0; x < NB; ++x)
+#pragma unroll
+                        for (int y = 0; y < NB; ++y) acc[x * NB + y] = mma64(u[x][t], v[y][t], acc[x * NB + y]);
+            }
+            __syncthreads();
         }
     }
-    publish_partial<NB, false>(acc, s, lds, parts);
+    publish_partial<NB, false>(acc, s, reinterpret_cast<double *>(smem), cd.parts + static_cast<size_t>(local) * s * s);
 }
 
-// gram = sum over p < nparts of parts[p], entry by entry in index order.
-__global__ __launch_bounds__(kThreads) void gram_reduce_kernel(const double *__restrict__ parts, int nparts, int ss,
-                                                               double *__restrict__ gram, const int *__restrict__ ctrl)
+// gram = sum over the chip's partials, entry by entry in index order
+// (grid: kRedBlocks x chips).
+__global__ __launch_bounds__(kThreads) void gram_reduce_kernel(const ChipDev *__restrict__ cds, int ss)
 {
-    if (ctrl[kConverged]) return;
+    const ChipDev &cd = cds[blockIdx.y];
+    if (cd.ctrl[kConverged]) return;
+    const double *__restrict__ parts = cd.parts;
+    const int nparts = cd.wgs;
     __shared__ double sh[kThreads];
     const int per = (ss + gridDim.x - 1) / gridDim.x;  // entries of this workgroup (<= 64)
     const int slices = kThreads / per;
@@ -242,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(const double *__r
     if (sl == 0 && e < ss) {
         double tot = 0.0;
         for (int q = 0; q < slices; ++q) tot += sh[q * per + le];
-        gram[e] = tot;
+        cd.gram[e] = tot;
     }
 }
 
@@ -318,7 +400,7 @@ __device__ __forceinline__ void publish_pivot(const double (&a)[E], int i, int j
     }
 }
 
-// Factor the reduced Gram.  mode 0: delta -> M2 = delta^+, M1 = delta^+ C.
+// Factor the reduced Gram of the chip.  mode 0: delta -> M2 = delta^+, M1 = delta^+ C.
 // mode 1 / 2: W^T W -> S = D^{1/2} Lunit^T, Linv = D^{-1/2} E; C <- S C;
 // M3[k][j] = Linv[j][k] (Q = W S^+), M4[k][j] = S[j][k] (P = Q + P S^T);
 // converged when ||C e_j|| <= th_j for every column (mode 2 is the first QR
@@ -331,10 +413,14 @@ __device__ __forceinline__ void publish_pivot(const double (&a)[E], int i, int j
 // ownership with E / 2 outputs per thread.
 // SP > 0 selects the one-wavefront elimination (s <= SP <= 32).
 template <int E, int SP>
-__global__ __launch_bounds__(kFacThreads) void factor_kernel(const double *__restrict__ gram, int s, double rel_thr,
-                                                             Small sm, int *ctrl, int mode)
+__global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__restrict__ cds, int s, double rel_thr,
+                                                             int mode)
 {
+    const ChipDev &cd = cds[blockIdx.x];  // one workgroup per chip
+    int *ctrl = cd.ctrl;
     if (ctrl[kConverged]) return;
+    const double *__restrict__ gram = cd.gram;
+    const Small sm = cd.sm;
     constexpr int E2 = E > 1 ? E / 2 : 1;
     constexpr int EA = SP > 0 ? 1 : E;  // register row segment of the LDS elimination
     extern __shared__ __align__(16) double lds[];
@@ -523,66 +609,96 @@ inline int factor_segment(int s)
 
 // ------------------------------------------------------------------ block updates
 
-// W = Q - AP M2 (matrix cores in the storage precision) and the W^T W
-// partials from the same registers.  With init != 0, W already holds the
-// residual and only its Gram is formed.
-template <class T, int NB>
-__global__ __launch_bounds__(kThreads) void update_w_kernel(const T *__restrict__ Q, const T *__restrict__ AP,
-                                                            T *__restrict__ W, const T *__restrict__ M2g, int64_t ldw,
-                                                            int s, double *__restrict__ parts, const int *__restrict__ ctrl,
-                                                            int init)
+// Stage an s x s FP64 matrix (row-major, ld s) as a padded SP x MST tile of T
+// in LDS, optionally negated; entries outside s x s are zero.
+template <class T, int SP, int MST>
+__device__ inline void stage_small(T *dst, const T *src, int s, bool neg)
 {
-    if (ctrl[kConverged]) return;
+    for (int e = threadIdx.x; e < SP * MST; e += kThreads) {
+        const int k = e / MST, j = e % MST;
+        const T v = (k < s && j < s) ? src[k * s + j] : T(0);
+        dst[e] = neg ? -v : v;
+    }
+}
+
+// W <- W M3 - AP M2 (the previous step's Q = W S^+ formed on the fly, matrix
+// cores in the storage precision) and the W^T W partials from the same
+// registers.  With init != 0, W holds the residual and only its Gram is
+// formed.  W is updated in place: each wave reads a 16-row block of every
+// column before it writes that block.
+template <class T, int NB>
+__global__ __launch_bounds__(kThreads) void update_w_kernel(const ChipDev *__restrict__ cds,
+                                                            const uint16_t *__restrict__ tab, int s, int init)
+{
+    int local;
+    const ChipDev &cd = chip_of(cds, tab, local);
+    if (cd.ctrl[kConverged]) return;
     using V = typename MF<T>::V;
     constexpr bool kF64 = MF<T>::kF64;
     constexpr int KS = 4 * NB;  // k steps of 4 over the padded width 16 NB
     constexpr int SP = 16 * NB;
     constexpr int MST = SP + 1;
-    __shared__ T Ms[SP * MST];  // -M2
+    __shared__ T M3s[SP * MST];
+    __shared__ T M2s[SP * MST];  // -M2
     __shared__ double lds[kMaxS * kMaxS];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int li = lane & 15, lg = lane >> 4;
+    const bool f64 = sizeof(T) == 8;
     if (!init) {
-        for (int e = threadIdx.x; e < SP * MST; e += kThreads) {
-            const int k = e / MST, j = e % MST;
-            Ms[e] = (k < s && j < s) ? -M2g[k * s + j] : T(0);
-        }
+        stage_small<T, SP, MST>(M3s, f64 ? reinterpret_cast<const T *>(cd.sm.M3) : reinterpret_cast<const T *>(cd.sm.M3f),
+                                s, false);
+        stage_small<T, SP, MST>(M2s, f64 ? reinterpret_cast<const T *>(cd.sm.M2) : reinterpret_cast<const T *>(cd.sm.M2f),
+                                s, true);
         __syncthreads();
     }
+    T *__restrict__ W = static_cast<T *>(cd.W);
+    const T *__restrict__ AP = static_cast<const T *>(cd.AP);
+    const int64_t ldw = cd.ldw;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
     d4 g[NB * (NB + 1) / 2];
 #pragma unroll
     for (int q = 0; q < NB * (NB + 1) / 2; ++q) g[q] = d4{0.0, 0.0, 0.0, 0.0};
     const int64_t ntiles = ldw / kTileRows;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int64_t tile = local; tile < ntiles; tile += cd.wgs) {
         for (int rb = 0; rb < 4; ++rb) {
             const int64_t r0 = tile * kTileRows + wave * 64 + rb * 16;
-            T a[KS];
-            if (!init) {
+            V wv[NB];
+            if (init) {
+#pragma unroll
+                for (int jb = 0; jb < NB; ++jb) {
+                    const int colj = jb * 16 + li;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        wv[jb][r] = colj < s ? W[colj * ldw + r0 + mfma_row<kF64>(lg, r)] : T(0);
+                }
+            } else {
+                T wa[KS], aa[KS];
 #pragma unroll
                 for (int t = 0; t < KS; ++t) {
                     const int col = 4 * t + lg;
-                    a[t] = col < s ? AP[col * ldw + r0 + li] : T(0);
+                    wa[t] = col < s ? W[col * ldw + r0 + li] : T(0);
+                    aa[t] = col < s ? AP[col * ldw + r0 + li] : T(0);
                 }
-            }
-            V wv[NB];
 #pragma unroll
-            for (int jb = 0; jb < NB; ++jb) {
-                const int colj = jb * 16 + li;
-                V acc;
+                for (int jb = 0; jb < NB; ++jb) {
+                    const int colj = jb * 16 + li;
+                    V acc;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t row = r0 + mfma_row<kF64>(lg, r);
-                    acc[r] = colj < s ? (init ? W[colj * ldw + row] : Q[colj * ldw + row]) : T(0);
+                    for (int r = 0; r < 4; ++r) acc[r] = T(0);
+#pragma unroll
+                    for (int t = 0; t < KS; ++t) acc = MF<T>::mma(wa[t], M3s[(4 * t + lg) * MST + colj], acc);
+#pragma unroll
+                    for (int t = 0; t < KS; ++t) acc = MF<T>::mma(aa[t], M2s[(4 * t + lg) * MST + colj], acc);
+                    wv[jb] = acc;
                 }
-                if (!init) {
+                // every lane has read its rows of W: write the new block
 #pragma unroll
-                    for (int t = 0; t < KS; ++t) acc = MF<T>::mma(a[t], Ms[(4 * t + lg) * MST + colj], acc);
+                for (int jb = 0; jb < NB; ++jb) {
+                    const int colj = jb * 16 + li;
                     if (colj < s) {
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) W[colj * ldw + r0 + mfma_row<kF64>(lg, r)] = acc[r];
+                        for (int r = 0; r < 4; ++r) W[colj * ldw + r0 + mfma_row<kF64>(lg, r)] = wv[jb][r];
                     }
                 }
-                wv[jb] = acc;
             }
             // W^T W: result register r of lane group lg holds row
             // mfma_row(lg, r) of the block -- the k slot lg of an FP64 step
@@ -596,38 +712,42 @@ __global__ __launch_bounds__(kThreads) void update_w_kernel(const T *__restrict_
                                                       g[ublock<NB>(ab, bb)]);
         }
     }
-    publish_partial<NB, true>(g, s, lds, parts);
+    publish_partial<NB, true>(g, s, lds, cd.parts + static_cast<size_t>(local) * s * s);
 }
 
-// D += P M1 ;  Q = W M3 ;  P = Q + P M4   (matrix cores, storage precision)
+// D += P M1 ;  P = W M3 + P M4   (matrix cores, storage precision; Q = W M3)
 template <class T, int NB>
-__global__ __launch_bounds__(kThreads) void update_dqp_kernel(T *__restrict__ D, T *__restrict__ P, T *__restrict__ Q,
-                                                              const T *__restrict__ W, const T *__restrict__ M1g,
-                                                              const T *__restrict__ M3g, const T *__restrict__ M4g,
-                                                              int64_t ldw, int s, const int *__restrict__ ctrl)
+__global__ __launch_bounds__(kThreads) void update_dqp_kernel(const ChipDev *__restrict__ cds,
+                                                              const uint16_t *__restrict__ tab, int s)
 {
-    if (ctrl[kStop]) return;
+    int local;
+    const ChipDev &cd = chip_of(cds, tab, local);
+    if (cd.ctrl[kStop]) return;
     using V = typename MF<T>::V;
     constexpr bool kF64 = MF<T>::kF64;
     constexpr int KS = 4 * NB;
     constexpr int SP = 16 * NB;
     constexpr int MST = SP + 1;
-    extern __shared__ __align__(16) double lds[];
-    T *M1 = reinterpret_cast<T *>(lds);
+    extern __shared__ __align__(16) double dlds[];
+    T *M1 = reinterpret_cast<T *>(dlds);
     T *M3 = M1 + SP * MST;
     T *M4 = M3 + SP * MST;
-    for (int e = threadIdx.x; e < SP * MST; e += kThreads) {
-        const int k = e / MST, j = e % MST;
-        const bool ok = k < s && j < s;
-        M1[e] = ok ? M1g[k * s + j] : T(0);
-        M3[e] = ok ? M3g[k * s + j] : T(0);
-        M4[e] = ok ? M4g[k * s + j] : T(0);
-    }
+    const bool f64 = sizeof(T) == 8;
+    stage_small<T, SP, MST>(M1, f64 ? reinterpret_cast<const T *>(cd.sm.M1) : reinterpret_cast<const T *>(cd.sm.M1f), s,
+                            false);
+    stage_small<T, SP, MST>(M3, f64 ? reinterpret_cast<const T *>(cd.sm.M3) : reinterpret_cast<const T *>(cd.sm.M3f), s,
+                            false);
+    stage_small<T, SP, MST>(M4, f64 ? reinterpret_cast<const T *>(cd.sm.M4) : reinterpret_cast<const T *>(cd.sm.M4f), s,
+                            false);
     __syncthreads();
+    T *__restrict__ D = static_cast<T *>(cd.Dv);
+    T *__restrict__ P = static_cast<T *>(cd.P);
+    const T *__restrict__ W = static_cast<const T *>(cd.W);
+    const int64_t ldw = cd.ldw;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int64_t ntiles = ldw / kTileRows;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int64_t tile = local; tile < ntiles; tile += cd.wgs) {
         for (int rb = 0; rb < 4; ++rb) {
             const int64_t r0 = tile * kTileRows + wave * 64 + rb * 16;
             T pa[KS], wa[KS];
@@ -637,31 +757,34 @@ __global__ __launch_bounds__(kThreads) void update_dqp_kernel(T *__restrict__ D,
                 pa[t] = col < s ? P[col * ldw + r0 + li] : T(0);
                 wa[t] = col < s ? W[col * ldw + r0 + li] : T(0);
             }
+            V ad[NB], ap[NB];
 #pragma unroll
             for (int jb = 0; jb < NB; ++jb) {
                 const int colj = jb * 16 + li;
-                V ad, aq;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    ad[r] = colj < s ? D[colj * ldw + r0 + mfma_row<kF64>(lg, r)] : T(0);
-                    aq[r] = T(0);
+                    ad[jb][r] = colj < s ? D[colj * ldw + r0 + mfma_row<kF64>(lg, r)] : T(0);
+                    ap[jb][r] = T(0);
                 }
 #pragma unroll
                 for (int t = 0; t < KS; ++t) {
                     const int k = 4 * t + lg;
-                    ad = MF<T>::mma(pa[t], M1[k * MST + colj], ad);
-                    aq = MF<T>::mma(wa[t], M3[k * MST + colj], aq);
+                    ad[jb] = MF<T>::mma(pa[t], M1[k * MST + colj], ad[jb]);
+                    ap[jb] = MF<T>::mma(wa[t], M3[k * MST + colj], ap[jb]);
                 }
-                V ap = aq;
 #pragma unroll
-                for (int t = 0; t < KS; ++t) ap = MF<T>::mma(pa[t], M4[(4 * t + lg) * MST + colj], ap);
+                for (int t = 0; t < KS; ++t) ap[jb] = MF<T>::mma(pa[t], M4[(4 * t + lg) * MST + colj], ap[jb]);
+            }
+            // every lane has read its rows of P: write the new blocks
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+                const int colj = jb * 16 + li;
                 if (colj < s) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int64_t idx = colj * ldw + r0 + mfma_row<kF64>(lg, r);
-                        D[idx] = ad[r];
-                        Q[idx] = aq[r];
-                        P[idx] = ap[r];
+                        D[idx] = ad[jb][r];
+                        P[idx] = ap[jb][r];
                     }
                 }
             }
@@ -669,232 +792,625 @@ __global__ __launch_bounds__(kThreads) void update_dqp_kernel(T *__restrict__ D,
     }
 }
 
-// ------------------------------------------------------------------ misc kernels
+// ------------------------------------------------------------------ outer-loop kernels (grouped)
 
-// colparts[chunk * s + j] = sum over the chunk of column j squared (FP64).
-__global__ __launch_bounds__(256) void colnorm_kernel(const double *__restrict__ A, int64_t lda, int64_t n, int s,
-                                                      int64_t rows_per_chunk, double *__restrict__ colparts)
+// R64 = B - A X in FP64 for the chip's rows (padding rows zero).
+__global__ __launch_bounds__(kThreads) void residual_kernel(const ChipDev *__restrict__ cds,
+                                                            const uint16_t *__restrict__ tab, int s)
 {
-    const int j = blockIdx.y;
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows_per_chunk;
-    const int64_t r1 = min(n, r0 + rows_per_chunk);
-    double acc = 0.0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-        const double v = A[j * lda + r];
-        acc += v * v;
+    int local;
+    const ChipDev &cd = chip_of(cds, tab, local);
+    if (!cd.ctrl[kActive]) return;
+    const int nx = cd.nx, ny = cd.ny, nz = cd.nz;
+    const int64_t n = cd.n, ldw = cd.ldw, plane = static_cast<int64_t>(nx) * ny;
+    const int64_t ntiles = ldw / kTileRows;
+    for (int64_t tile = local; tile < ntiles; tile += cd.wgs) {
+        const int64_t a = tile * kTileRows + threadIdx.x;
+        if (a >= n) {
+            for (int c = 0; c < s; ++c) cd.R64[c * ldw + a] = 0.0;
+            continue;
+        }
+        const int i = static_cast<int>(a % nx);
+        const int64_t q = a / nx;
+        const int j = static_cast<int>(q % ny);
+        const int l = static_cast<int>(q / ny);
+        const int64_t oxm = i > 0 ? -1 : 0, oxp = i < nx - 1 ? 1 : 0;
+        const int64_t oym = j > 0 ? -static_cast<int64_t>(nx) : 0, oyp = j < ny - 1 ? nx : 0;
+        const int64_t ozm = l > 0 ? -plane : 0, ozp = l < nz - 1 ? plane : 0;
+        const double d = cd.d64[a];
+        const double cxp = cd.x64[a], cxm = i > 0 ? cd.x64[a - 1] : 0.0;
+        const double cyp = cd.y64[a], cym = j > 0 ? cd.y64[a - nx] : 0.0;
+        const double czp = cd.z64[a], czm = l > 0 ? cd.z64[a - plane] : 0.0;
+        for (int c = 0; c < s; ++c) {
+            const double *x = cd.X + c * cd.ldx + a;
+            const double nb = cxm * x[oxm] + cxp * x[oxp] + cym * x[oym] + cyp * x[oyp] + czm * x[ozm] + czp * x[ozp];
+            cd.R64[c * ldw + a] = cd.B[c * cd.ldb + a] - (d * x[0] - nb);
+        }
     }
-    __shared__ double sh[256];
-    sh[threadIdx.x] = acc;
+}
+
+// Per-workgroup column sums of squares of B (which = 0) or R64 (which = 1)
+// over the chip's rows, into parts[local * s + c].
+__global__ __launch_bounds__(kThreads) void colsq_kernel(const ChipDev *__restrict__ cds, const uint16_t *__restrict__ tab,
+                                                         int s, int which)
+{
+    int local;
+    const ChipDev &cd = chip_of(cds, tab, local);
+    if (which == 1 && !cd.ctrl[kActive]) return;
+    __shared__ double sh[kThreads / 64][kMaxS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double *src = which == 0 ? cd.B : cd.R64;
+    const int64_t ld = which == 0 ? cd.ldb : cd.ldw;
+    const int64_t ntiles = cd.ldw / kTileRows;
+    for (int c = 0; c < s; ++c) {
+        double acc = 0.0;
+        for (int64_t tile = local; tile < ntiles; tile += cd.wgs) {
+            const int64_t a = tile * kTileRows + threadIdx.x;
+            if (a < cd.n) {
+                const double v = src[c * ld + a];
+                acc = fma(v, v, acc);
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) sh[wave][c] = acc;
+    }
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
+    for (int c = threadIdx.x; c < s; c += kThreads) {
+        double t = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) t += sh[w][c];
+        cd.parts[static_cast<size_t>(local) * s + c] = t;
     }
-    if (threadIdx.x == 0) colparts[static_cast<int64_t>(blockIdx.x) * s + j] = sh[0];
 }
 
-// dst (ldw-padded, type T) = src (FP64, lds)  for rows < n
+// norms[c] = sum over the chip's workgroups of the column partials, in order
+// (one workgroup per chip).
+__global__ __launch_bounds__(kThreads) void colsq_reduce_kernel(const ChipDev *__restrict__ cds, int s, int which)
+{
+    const ChipDev &cd = cds[blockIdx.x];
+    if (which == 1 && !cd.ctrl[kActive]) return;
+    for (int c = threadIdx.x; c < s; c += kThreads) {
+        double t = 0.0;
+        for (int p = 0; p < cd.wgs; ++p) t += cd.parts[static_cast<size_t>(p) * s + c];
+        cd.norms[c] = t;
+    }
+}
+
+// Inner-solve start for active chips: W = (T) R64, D = P = AP = 0 (padding
+// rows included); C = I and M1 = 0.
 template <class T>
-__global__ __launch_bounds__(256) void cast_in_kernel(const double *__restrict__ src, int64_t lds, T *__restrict__ dst,
-                                                      int64_t ldd, int64_t n, int s)
+__global__ __launch_bounds__(kThreads) void inner_start_kernel(const ChipDev *__restrict__ cds,
+                                                               const uint16_t *__restrict__ tab, int s)
 {
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    for (int j = 0; j < s; ++j) dst[j * ldd + r] = static_cast<T>(src[j * lds + r]);
+    int local;
+    const ChipDev &cd = chip_of(cds, tab, local);
+    if (!cd.ctrl[kActive]) return;
+    const int64_t ldw = cd.ldw, ntiles = ldw / kTileRows;
+    T *W = static_cast<T *>(cd.W), *D = static_cast<T *>(cd.Dv), *P = static_cast<T *>(cd.P), *AP = static_cast<T *>(cd.AP);
+    for (int64_t tile = local; tile < ntiles; tile += cd.wgs) {
+        const int64_t a = tile * kTileRows + threadIdx.x;
+        for (int c = 0; c < s; ++c) {
+            const int64_t e = c * ldw + a;
+            W[e] = static_cast<T>(cd.R64[e]);
+            D[e] = T(0);
+            P[e] = T(0);
+            AP[e] = T(0);
+        }
+    }
+    if (local == 0) {
+        for (int e = threadIdx.x; e < s * s; e += kThreads) {
+            cd.sm.C[e] = (e / s == e % s) ? 1.0 : 0.0;
+            cd.sm.M1[e] = 0.0;
+            cd.sm.M1f[e] = 0.0f;
+        }
+    }
 }
 
-// X (FP64) += D (type T)
+// X = X0 (or 0) for the chip's rows.
+__global__ __launch_bounds__(kThreads) void start_x_kernel(const ChipDev *__restrict__ cds,
+                                                           const uint16_t *__restrict__ tab, int s)
+{
+    int local;
+    const ChipDev &cd = chip_of(cds, tab, local);
+    const int64_t ntiles = cd.ldw / kTileRows;
+    for (int64_t tile = local; tile < ntiles; tile += cd.wgs) {
+        const int64_t a = tile * kTileRows + threadIdx.x;
+        if (a >= cd.n) continue;
+        for (int c = 0; c < s; ++c) cd.X[c * cd.ldx + a] = cd.X0 ? cd.X0[c * cd.ldx0 + a] : 0.0;
+    }
+}
+
+// X (FP64) += D (type T) for active chips.
 template <class T>
-__global__ __launch_bounds__(256) void add_out_kernel(double *__restrict__ X, int64_t ldx, const T *__restrict__ D,
-                                                      int64_t ldd, int64_t n, int s)
+__global__ __launch_bounds__(kThreads) void add_out_kernel(const ChipDev *__restrict__ cds,
+                                                           const uint16_t *__restrict__ tab, int s)
 {
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    for (int j = 0; j < s; ++j) X[j * ldx + r] += static_cast<double>(D[j * ldd + r]);
-}
-
-__global__ void copy_block_kernel(const double *__restrict__ src, int64_t lds, double *__restrict__ dst, int64_t ldd,
-                                  int64_t n, int s)
-{
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    for (int j = 0; j < s; ++j) dst[j * ldd + r] = src[j * lds + r];
-}
-
-__global__ void set_identity_kernel(double *C, int s)
-{
-    for (int e = threadIdx.x; e < s * s; e += blockDim.x) C[e] = (e / s == e % s) ? 1.0 : 0.0;
+    int local;
+    const ChipDev &cd = chip_of(cds, tab, local);
+    if (!cd.ctrl[kActive]) return;
+    const T *D = static_cast<const T *>(cd.Dv);
+    const int64_t ntiles = cd.ldw / kTileRows;
+    for (int64_t tile = local; tile < ntiles; tile += cd.wgs) {
+        const int64_t a = tile * kTileRows + threadIdx.x;
+        if (a >= cd.n) continue;
+        for (int c = 0; c < s; ++c) cd.X[c * cd.ldx + a] += static_cast<double>(D[c * cd.ldw + a]);
+    }
 }
 
 // ------------------------------------------------------------------ host side
 
 inline int nb_for(int s) { return (s + 15) / 16; }
 
-inline unsigned grid_for(int64_t ldw)
+// Workspace layout of a batch: a header (chip table, workgroup table,
+// thresholds, control words, norms) and one region per chip.
+struct ChipHost {
+    const Operator *op;
+    int64_t n, ldw;
+    int tiles, wgs, wg_base;
+    size_t off;  // chip region
+};
+
+struct Layout {
+    int nchips = 0, s = 0, total_wgs = 0, wg_cap = 0;
+    bko_dtype compute = BKO_F64;
+    size_t off_cds = 0, off_tab = 0, off_th = 0, off_ctrl = 0, off_norms = 0, bytes = 0;
+    std::vector<ChipHost> chips;
+};
+
+constexpr int kMaxWgs = 512;  // partial producers per chip (upper bound of the tuned cap)
+
+inline size_t chip_region_bytes(int64_t ldw, int s, bko_dtype compute, size_t *offs)
 {
-    return static_cast<unsigned>(std::min<int64_t>(ldw / kTileRows, kMaxBlocks));
+    const size_t vsz = compute == BKO_F64 ? 8 : 4;
+    const size_t ss = static_cast<size_t>(s) * s;
+    const size_t sizes[] = {sizeof(double) * ldw * s,                     // R64
+                            vsz * ldw * s, vsz * ldw * s, vsz * ldw * s,  // Dv, P, AP
+                            vsz * ldw * s,                                // W
+                            sizeof(double) * ss * 5,                      // C, M1..M4
+                            sizeof(double) * kMaxS,                       // (unused slot)
+                            sizeof(float) * ss * 4,                       // M1f..M4f
+                            sizeof(double) * ss * kMaxWgs,                // parts
+                            sizeof(double) * ss};                         // gram
+    size_t o = 0;
+    for (size_t k = 0; k < sizeof(sizes) / sizeof(sizes[0]); ++k) {
+        if (offs) offs[k] = o;
+        o = align_up(o + sizes[k], 256);
+    }
+    return o;
 }
 
-enum Step { kStepGram = 0, kStepW = 1, kStepDQP = 2 };
+Layout make_layout(const Operator *const *ops, int nchips, int s, bko_dtype compute, int wg_cap)
+{
+    Layout L;
+    L.nchips = nchips;
+    L.s = s;
+    L.compute = compute;
+    L.wg_cap = wg_cap;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t q = o;
+        o = align_up(o + bytes, 256);
+        return q;
+    };
+    L.off_cds = take(sizeof(ChipDev) * nchips);
+    int total = 0;
+    L.chips.resize(nchips);
+    for (int c = 0; c < nchips; ++c) {
+        ChipHost &h = L.chips[c];
+        h.op = ops[c];
+        h.n = ops[c]->n;
+        h.ldw = static_cast<int64_t>(align_up(static_cast<size_t>(h.n), kTileRows));
+        h.tiles = static_cast<int>(h.ldw / kTileRows);
+        h.wgs = std::min(h.tiles, wg_cap);
+        h.wg_base = total;
+        total += h.wgs;
+    }
+    L.total_wgs = total;
+    int table = 0;  // sized for the largest cap, so offsets do not depend on the cap
+    for (int c = 0; c < nchips; ++c) table += std::min(L.chips[c].tiles, kMaxWgs);
+    L.off_tab = take(sizeof(uint16_t) * table);
+    L.off_th = take(sizeof(double) * kMaxS * nchips);
+    L.off_ctrl = take(sizeof(int) * kCtrlInts * nchips);
+    L.off_norms = take(sizeof(double) * kMaxS * nchips);
+    for (int c = 0; c < nchips; ++c) L.chips[c].off = take(chip_region_bytes(L.chips[c].ldw, s, compute, nullptr));
+    L.bytes = o;
+    return L;
+}
+
+// Device chip records for one call.
+std::vector<ChipDev> chip_records(const Layout &L, void *work, const double *const *B, const int64_t *ldb,
+                                  double *const *X, const int64_t *ldx, const double *const *X0, const int64_t *ldx0)
+{
+    char *base = static_cast<char *>(work);
+    const bool f64 = L.compute == BKO_F64;
+    const size_t ss = static_cast<size_t>(L.s) * L.s;
+    std::vector<ChipDev> v(L.nchips);
+    for (int c = 0; c < L.nchips; ++c) {
+        const ChipHost &h = L.chips[c];
+        const Operator &op = *h.op;
+        ChipDev &d = v[c];
+        std::memset(&d, 0, sizeof(d));
+        d.cdiag = f64 ? static_cast<const void *>(op.diag64) : static_cast<const void *>(op.diag32);
+        d.cwx = f64 ? static_cast<const void *>(op.wx64) : static_cast<const void *>(op.wx32);
+        d.cwy = f64 ? static_cast<const void *>(op.wy64) : static_cast<const void *>(op.wy32);
+        d.cwz = f64 ? static_cast<const void *>(op.wz64) : static_cast<const void *>(op.wz32);
+        d.d64 = op.diag64;
+        d.x64 = op.wx64;
+        d.y64 = op.wy64;
+        d.z64 = op.wz64;
+        d.nx = op.nx;
+        d.ny = op.ny;
+        d.nz = op.nz;
+        d.wgs = h.wgs;
+        d.n = h.n;
+        d.ldw = h.ldw;
+        d.wg_base = h.wg_base;
+        d.B = B ? B[c] : nullptr;
+        d.ldb = ldb ? ldb[c] : 0;
+        d.X = X ? X[c] : nullptr;
+        d.ldx = ldx ? ldx[c] : 0;
+        d.X0 = X0 ? X0[c] : nullptr;
+        d.ldx0 = ldx0 ? ldx0[c] : 0;
+        size_t off[10];
+        chip_region_bytes(h.ldw, L.s, L.compute, off);
+        char *r = base + h.off;
+        d.R64 = reinterpret_cast<double *>(r + off[0]);
+        d.Dv = r + off[1];
+        d.P = r + off[2];
+        d.AP = r + off[3];
+        d.W = r + off[4];
+        double *sm = reinterpret_cast<double *>(r + off[5]);
+        d.sm.C = sm;
+        d.sm.M1 = sm + ss;
+        d.sm.M2 = sm + 2 * ss;
+        d.sm.M3 = sm + 3 * ss;
+        d.sm.M4 = sm + 4 * ss;
+        float *smf = reinterpret_cast<float *>(r + off[7]);
+        d.sm.M1f = smf;
+        d.sm.M2f = smf + ss;
+        d.sm.M3f = smf + 2 * ss;
+        d.sm.M4f = smf + 3 * ss;
+        d.sm.th = reinterpret_cast<double *>(base + L.off_th) + static_cast<size_t>(c) * kMaxS;
+        d.parts = reinterpret_cast<double *>(r + off[8]);
+        d.gram = reinterpret_cast<double *>(r + off[9]);
+        d.norms = reinterpret_cast<double *>(base + L.off_norms) + static_cast<size_t>(c) * kMaxS;
+        d.ctrl = reinterpret_cast<int *>(base + L.off_ctrl) + static_cast<size_t>(c) * kCtrlInts;
+    }
+    return v;
+}
+
+std::vector<uint16_t> wg_table(const Layout &L)
+{
+    std::vector<uint16_t> t(L.total_wgs);
+    for (int c = 0; c < L.nchips; ++c)
+        for (int g = 0; g < L.chips[c].wgs; ++g) t[L.chips[c].wg_base + g] = static_cast<uint16_t>(c);
+    return t;
+}
+
+// Kernel launch context of one batch call.
+struct Ctx {
+    const Layout *L;
+    const ChipDev *cds;
+    const uint16_t *tab;
+    hipStream_t st;
+};
 
 template <class T, int NB>
-bko_status launch_block_kernel(Step which, const Workspace &ws, int s, int init, hipStream_t st)
+bko_status launch_row_kernels(int which, const Ctx &x, int init)
 {
-    const int64_t ldw = ws.ldw;
-    const unsigned grid = grid_for(ldw);
-    const bool f64 = sizeof(T) == 8;
-    T *Dv = static_cast<T *>(ws.Dv), *Q = static_cast<T *>(ws.Q), *P = static_cast<T *>(ws.P);
-    T *AP = static_cast<T *>(ws.AP), *W = static_cast<T *>(ws.W);
-    const T *M1 = f64 ? reinterpret_cast<const T *>(ws.sm.M1) : reinterpret_cast<const T *>(ws.sm.M1f);
-    const T *M2 = f64 ? reinterpret_cast<const T *>(ws.sm.M2) : reinterpret_cast<const T *>(ws.sm.M2f);
-    const T *M3 = f64 ? reinterpret_cast<const T *>(ws.sm.M3) : reinterpret_cast<const T *>(ws.sm.M3f);
-    const T *M4 = f64 ? reinterpret_cast<const T *>(ws.sm.M4) : reinterpret_cast<const T *>(ws.sm.M4f);
-    const int sp = 16 * NB;
-    const size_t mbytes = sizeof(T) * sp * (sp + 1);
-    if (which == kStepGram) {
-        TimedLaunch tl(kGram, st);
-        hipLaunchKernelGGL((gram_kernel<T, NB>), dim3(grid), dim3(kThreads), 0, st, P, AP, ldw, s, ws.parts, ws.ctrl);
-    } else if (which == kStepW) {
-        TimedLaunch tl(kUpdate, st);
-        hipLaunchKernelGGL((update_w_kernel<T, NB>), dim3(grid), dim3(kThreads), 0, st, Q, AP, W, M2, ldw, s, ws.parts,
-                           ws.ctrl, init);
+    const int s = x.L->s;
+    const dim3 grid(static_cast<unsigned>(x.L->total_wgs)), block(kThreads);
+    if (which == 0) {
+        TimedLaunch tl(kSpmm, x.st);
+        hipLaunchKernelGGL((spmm_gram_kernel<T, NB>), grid, block, (spmm_gram_lds<T, NB>()), x.st, x.cds, x.tab, s);
+    } else if (which == 1) {
+        TimedLaunch tl(kUpdate, x.st);
+        hipLaunchKernelGGL((update_w_kernel<T, NB>), grid, block, 0, x.st, x.cds, x.tab, s, init);
     } else {
-        TimedLaunch tl(::bko::kUpdateDQP, st);
-        hipLaunchKernelGGL((update_dqp_kernel<T, NB>), dim3(grid), dim3(kThreads), 3 * mbytes, st, Dv, P, Q, W, M1, M3,
-                           M4, ldw, s, ws.ctrl);
+        TimedLaunch tl(::bko::kUpdateDQP, x.st);
+        const size_t sp = 16 * NB;
+        hipLaunchKernelGGL((update_dqp_kernel<T, NB>), grid, block, 3 * sizeof(T) * sp * (sp + 1), x.st, x.cds, x.tab,
+                           s);
     }
     BKO_HIP(hipGetLastError());
     return BKO_OK;
 }
 
 template <class T>
-bko_status launch_block(Step which, const Workspace &ws, int s, int init, hipStream_t st)
+bko_status launch_row(int which, const Ctx &x, int init)
 {
-    switch (nb_for(s)) {
-    case 1: return launch_block_kernel<T, 1>(which, ws, s, init, st);
-    case 2: return launch_block_kernel<T, 2>(which, ws, s, init, st);
-    case 3: return launch_block_kernel<T, 3>(which, ws, s, init, st);
-    default: return launch_block_kernel<T, 4>(which, ws, s, init, st);
+    switch (nb_for(x.L->s)) {
+    case 1: return launch_row_kernels<T, 1>(which, x, init);
+    case 2: return launch_row_kernels<T, 2>(which, x, init);
+    case 3: return launch_row_kernels<T, 3>(which, x, init);
+    default: return launch_row_kernels<T, 4>(which, x, init);
     }
 }
 
-// reduce the partials of the last Gram step, then factor (mode as factor_kernel)
-bko_status launch_reduce_factor(const Workspace &ws, int s, double rel_thr, int mode, hipStream_t st)
+// Largest LDS request of the row kernels at this s and precision.
+size_t row_kernel_lds(int s, bko_dtype compute)
 {
-    const int ss = s * s;
-    const unsigned nparts = grid_for(ws.ldw);
+    const int nb = nb_for(s);
+    const size_t sp = 16 * nb;
+    const size_t vsz = compute == BKO_F64 ? 8 : 4;
+    size_t g;
+    if (compute == BKO_F64) g = nb == 1 ? spmm_gram_lds<double, 1>() : nb == 2 ? spmm_gram_lds<double, 2>()
+                                : nb == 3 ? spmm_gram_lds<double, 3>() : spmm_gram_lds<double, 4>();
+    else g = nb == 1 ? spmm_gram_lds<float, 1>() : nb == 2 ? spmm_gram_lds<float, 2>()
+             : nb == 3 ? spmm_gram_lds<float, 3>() : spmm_gram_lds<float, 4>();
+    const size_t w = 2 * vsz * sp * (sp + 1) + sizeof(double) * kMaxS * kMaxS;
+    const size_t dqp = 3 * vsz * sp * (sp + 1);
+    return std::max(g, std::max(w, dqp));
+}
+
+// reduce the partials of the last Gram step of every chip, then factor
+bko_status launch_reduce_factor(const Ctx &x, double rel_thr, int mode)
+{
+    const int s = x.L->s, ss = s * s;
+    TimedLaunch tl(kSmall, x.st);
     const unsigned rblocks = static_cast<unsigned>(std::min(kRedBlocks, ss));
-    {
-        TimedLaunch tl(kSmall, st);
-        hipLaunchKernelGGL(gram_reduce_kernel, dim3(rblocks), dim3(kThreads), 0, st, ws.parts, static_cast<int>(nparts),
-                           ss, ws.gram, ws.ctrl);
-        BKO_HIP(hipGetLastError());
-        // A, G, C (each padded by E <= 32), two pivot rows (padded) and columns
-        const size_t lds = sizeof(double) * (4 * ss + 3 * 32 + 2 * (2 * s + 32) + 2 * s);
-#define BKO_FACTOR(E, SP)                                                                                   \
-    hipLaunchKernelGGL((factor_kernel<E, SP>), dim3(1), dim3(kFacThreads), lds, st, ws.gram, s, rel_thr, ws.sm, \
-                       ws.ctrl, mode)
-        const int e = factor_segment(s);
-        if (s <= 8) BKO_FACTOR(1, 8);
-        else if (s <= 16 && e == 1) BKO_FACTOR(1, 16);
-        else if (s <= 16) BKO_FACTOR(2, 16);
-        else if (s <= 32 && e == 4) BKO_FACTOR(4, 32);
-        else if (s <= 32) BKO_FACTOR(8, 32);
-        else if (e == 16) BKO_FACTOR(16, 0);
-        else BKO_FACTOR(32, 0);
-#undef BKO_FACTOR
-        BKO_HIP(hipGetLastError());
-    }
-    return BKO_OK;
-}
-
-// Column norms of an FP64 n x s block, returned on the host.
-bko_status host_colnorms(const double *A, int64_t lda, int64_t n, int s, double *colparts, std::vector<double> &out,
-                         hipStream_t st)
-{
-    const int chunks = static_cast<int>(std::min<int64_t>(128, (n + 4095) / 4096));
-    const int64_t rows = (n + chunks - 1) / chunks;
-    hipLaunchKernelGGL(colnorm_kernel, dim3(chunks, s), dim3(256), 0, st, A, lda, n, s, rows, colparts);
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(rblocks, static_cast<unsigned>(x.L->nchips)), dim3(kThreads), 0, x.st,
+                       x.cds, ss);
     BKO_HIP(hipGetLastError());
-    std::vector<double> h(static_cast<size_t>(chunks) * s);
-    BKO_HIP(hipMemcpyAsync(h.data(), colparts, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
-    BKO_HIP(hipStreamSynchronize(st));
-    out.assign(s, 0.0);
-    for (int c = 0; c < chunks; ++c)
-        for (int j = 0; j < s; ++j) out[j] += h[static_cast<size_t>(c) * s + j];
-    for (int j = 0; j < s; ++j) out[j] = std::sqrt(out[j]);
+    // A, G, C (each padded by E <= 32), two pivot rows (padded) and columns
+    const size_t lds = sizeof(double) * (4 * ss + 3 * 32 + 2 * (2 * s + 32) + 2 * s);
+    const dim3 grid(static_cast<unsigned>(x.L->nchips));
+#define BKO_FACTOR(E, SP) \
+    hipLaunchKernelGGL((factor_kernel<E, SP>), grid, dim3(kFacThreads), lds, x.st, x.cds, s, rel_thr, mode)
+    const int e = factor_segment(s);
+    if (s <= 8) BKO_FACTOR(1, 8);
+    else if (s <= 16 && e == 1) BKO_FACTOR(1, 16);
+    else if (s <= 16) BKO_FACTOR(2, 16);
+    else if (s <= 32 && e == 4) BKO_FACTOR(4, 32);
+    else if (s <= 32) BKO_FACTOR(8, 32);
+    else if (e == 16) BKO_FACTOR(16, 0);
+    else BKO_FACTOR(32, 0);
+#undef BKO_FACTOR
+    BKO_HIP(hipGetLastError());
     return BKO_OK;
 }
 
-// Inner block iteration on A D = R (R = ws.R64, FP64), storage type T.
-// th: per-column absolute residual targets.
+// One block iteration for every chip of the batch.
 template <class T>
-bko_status inner_solve(const Operator &op, int s, const Workspace &ws, const std::vector<double> &th, int budget,
-                       int &iters_out, int &deflated_out, bool &all_deflated, hipStream_t st)
+bko_status iteration(const Ctx &x, double rel_thr)
 {
-    const int64_t n = op.n, ldw = ws.ldw;
+    bko_status rc;
+    if ((rc = launch_row<T>(0, x, 0)) != BKO_OK) return rc;
+    if ((rc = launch_reduce_factor(x, rel_thr, 0)) != BKO_OK) return rc;
+    if ((rc = launch_row<T>(1, x, 0)) != BKO_OK) return rc;
+    if ((rc = launch_reduce_factor(x, rel_thr, 1)) != BKO_OK) return rc;
+    return launch_row<T>(2, x, 0);
+}
+
+template <class T>
+bko_status run_chunk(const Ctx &x, double rel_thr, int len, GraphCache *gc, void *work)
+{
+    const bool graph = gc != nullptr && x.st != nullptr && !timing_active();
+    if (!graph) {
+        for (int it = 0; it < len; ++it) {
+            bko_status rc = iteration<T>(x, rel_thr);
+            if (rc != BKO_OK) return rc;
+        }
+        return BKO_OK;
+    }
+    if (gc->work != work) gc->clear();
+    gc->work = work;
+    auto found = gc->execs.find(len);
+    if (found == gc->execs.end()) {
+        BKO_HIP(hipStreamBeginCapture(x.st, hipStreamCaptureModeThreadLocal));
+        bko_status rc = BKO_OK;
+        for (int it = 0; it < len && rc == BKO_OK; ++it) rc = iteration<T>(x, rel_thr);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(x.st, &g);
+        if (rc != BKO_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return hip_fail(ei, "hipGraphInstantiate");
+        found = gc->execs.emplace(len, ex).first;
+    }
+    BKO_HIP(hipGraphLaunch(found->second, x.st));
+    return BKO_OK;
+}
+
+struct ChipState {
+    bko_solve_info info{};
+    double prev_rel = HUGE_VAL;
+    int stagnant = 0;
+    bool done = false;
+    std::vector<double> bnorm, rnorm;
+};
+
+// Squared column norms of B (which = 0) or of the active chips' residuals
+// (which = 1) into each chip's norms slot.
+bko_status host_norms(const Ctx &x, int which)
+{
+    const Layout &L = *x.L;
+    hipLaunchKernelGGL(colsq_kernel, dim3(static_cast<unsigned>(L.total_wgs)), dim3(kThreads), 0, x.st, x.cds, x.tab, L.s,
+                       which);
+    BKO_HIP(hipGetLastError());
+    hipLaunchKernelGGL(colsq_reduce_kernel, dim3(static_cast<unsigned>(L.nchips)), dim3(kThreads), 0, x.st, x.cds, L.s,
+                       which);
+    BKO_HIP(hipGetLastError());
+    return BKO_OK;
+}
+
+template <class T>
+bko_status batch_solve_t(const Layout &L, void *work, const double *const *B, const int64_t *ldb, double *const *X,
+                         const int64_t *ldx, const double *const *X0, const int64_t *ldx0, double tol, int max_iter,
+                         bko_solve_info *infos, hipStream_t st, GraphCache *gc)
+{
+    const int s = L.s, nc = L.nchips;
+    char *base = static_cast<char *>(work);
     const bool f64 = sizeof(T) == 8;
     const double rel_thr = f64 ? 1e-13 : 1e-12;
-    const size_t blkv = sizeof(T) * static_cast<size_t>(ldw) * s;
-    const size_t ss = static_cast<size_t>(s) * s;
-    bko_status rc;
-
-    // fresh state: blocks zero (padding rows stay zero), C = I, M1 = 0
-    for (void *b : {ws.Dv, ws.Q, ws.P, ws.AP, ws.W})
-        if ((rc = launch_zero(b, blkv, st)) != BKO_OK) return rc;
-    if ((rc = launch_zero(ws.ctrl, sizeof(int) * 64, st)) != BKO_OK) return rc;
-    if ((rc = launch_zero(ws.sm.M1, sizeof(double) * ss, st)) != BKO_OK) return rc;
-    if ((rc = launch_zero(ws.sm.M1f, sizeof(float) * ss, st)) != BKO_OK) return rc;
-    hipLaunchKernelGGL(set_identity_kernel, dim3(1), dim3(256), 0, st, ws.sm.C, s);
-    BKO_HIP(hipGetLastError());
-    std::vector<double> thp(kMaxS, 0.0);
-    std::copy(th.begin(), th.end(), thp.begin());
-    BKO_HIP(hipMemcpyAsync(ws.sm.th, thp.data(), sizeof(double) * kMaxS, hipMemcpyHostToDevice, st));
-    const unsigned rblocks = static_cast<unsigned>((n + 255) / 256);
-    hipLaunchKernelGGL((cast_in_kernel<T>), dim3(rblocks), dim3(256), 0, st, ws.R64, ldw, static_cast<T *>(ws.W), ldw,
-                       n, s);
-    BKO_HIP(hipGetLastError());
-    // first QR of the residual, then Q = W S^+, P = Q (P is zero), D = 0 (M1 = 0)
-    if ((rc = launch_block<T>(kStepW, ws, s, 1, st)) != BKO_OK) return rc;
-    if ((rc = launch_reduce_factor(ws, s, rel_thr, 2, st)) != BKO_OK) return rc;
-    if ((rc = launch_block<T>(kStepDQP, ws, s, 0, st)) != BKO_OK) return rc;
-
-    const bko_dtype vt = f64 ? BKO_F64 : BKO_F32;
-    int h_ctrl[8] = {0};
-    int launched = 0;
-    int chunk = 4;
-    while (true) {
-        const int todo = std::min(chunk, budget - launched);
-        for (int it = 0; it < todo; ++it) {
-            {
-                TimedLaunch tl(kSpmm, st);
-                if ((rc = launch_stencil(op, s, ws.P, ldw, vt, ws.AP, ldw, vt, vt, nullptr, 0, st, ws.ctrl + kConverged,
-                                         ws.ctrl + kStop)) != BKO_OK)
-                    return rc;
-            }
-            if ((rc = launch_block<T>(kStepGram, ws, s, 0, st)) != BKO_OK) return rc;
-            if ((rc = launch_reduce_factor(ws, s, rel_thr, 0, st)) != BKO_OK) return rc;
-            if ((rc = launch_block<T>(kStepW, ws, s, 0, st)) != BKO_OK) return rc;
-            if ((rc = launch_reduce_factor(ws, s, rel_thr, 1, st)) != BKO_OK) return rc;
-            if ((rc = launch_block<T>(kStepDQP, ws, s, 0, st)) != BKO_OK) return rc;
-        }
-        launched += todo;
-        BKO_HIP(hipMemcpyAsync(h_ctrl, ws.ctrl, sizeof(h_ctrl), hipMemcpyDeviceToHost, st));
-        BKO_HIP(hipStreamSynchronize(st));
-        if (h_ctrl[kConverged] || launched >= budget) break;
-        chunk = std::min(chunk * 2, 64);
+    const double inner_rel_f32 = 1e-5;
+    if (row_kernel_lds(s, L.compute) > device_max_lds()) {
+        set_error("s = %d needs %zu bytes of LDS per workgroup in this precision; the device grants %zu", s,
+                  row_kernel_lds(s, L.compute), device_max_lds());
+        return BKO_EINVAL;
     }
-    iters_out = h_ctrl[kIters];
-    deflated_out = h_ctrl[kDeflated];
-    all_deflated = h_ctrl[kAllDeflated] != 0;
-    return BKO_OK;
+    // chip records and the workgroup table (host copies live until the final synchronisation)
+    const std::vector<ChipDev> recs = chip_records(L, work, B, ldb, X, ldx, X0, ldx0);
+    const std::vector<uint16_t> tabh = wg_table(L);
+    std::vector<int> ctrlh(static_cast<size_t>(kCtrlInts) * nc, 0);
+    std::vector<double> thh(static_cast<size_t>(kMaxS) * nc, 0.0), nh(static_cast<size_t>(kMaxS) * nc, 0.0);
+    Ctx x{&L, reinterpret_cast<const ChipDev *>(base + L.off_cds), reinterpret_cast<const uint16_t *>(base + L.off_tab), st};
+    int *ctrl_d = reinterpret_cast<int *>(base + L.off_ctrl);
+    double *th_d = reinterpret_cast<double *>(base + L.off_th);
+    double *norms_d = reinterpret_cast<double *>(base + L.off_norms);
+    BKO_HIP(hipMemcpyAsync(base + L.off_cds, recs.data(), sizeof(ChipDev) * nc, hipMemcpyHostToDevice, st));
+    BKO_HIP(hipMemcpyAsync(base + L.off_tab, tabh.data(), sizeof(uint16_t) * tabh.size(), hipMemcpyHostToDevice, st));
+    // every chip active for the start: ||b_j||, X = X0 or 0
+    for (int c = 0; c < nc; ++c) ctrlh[static_cast<size_t>(c) * kCtrlInts + kActive] = 1;
+    BKO_HIP(hipMemcpyAsync(ctrl_d, ctrlh.data(), sizeof(int) * ctrlh.size(), hipMemcpyHostToDevice, st));
+    bko_status rc;
+    if ((rc = host_norms(x, 0)) != BKO_OK) return rc;
+    std::vector<double> bn(static_cast<size_t>(kMaxS) * nc);
+    BKO_HIP(hipMemcpyAsync(bn.data(), norms_d, sizeof(double) * bn.size(), hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(start_x_kernel, dim3(static_cast<unsigned>(L.total_wgs)), dim3(kThreads), 0, st, x.cds, x.tab, s);
+    BKO_HIP(hipGetLastError());
+    BKO_HIP(hipStreamSynchronize(st));
+    std::vector<ChipState> cs(nc);
+    for (int c = 0; c < nc; ++c) {
+        cs[c].info.status = BKO_ENOCONV;
+        cs[c].bnorm.resize(s);
+        for (int j = 0; j < s; ++j) cs[c].bnorm[j] = std::sqrt(bn[static_cast<size_t>(c) * kMaxS + j]);
+        for (int j = 0; j < s; ++j)
+            if (!std::isfinite(cs[c].bnorm[j])) {
+                set_error("right-hand side column %d of chip %d is not finite", j, c);
+                return BKO_EINVAL;
+            }
+    }
+
+    for (int outer = 0; outer < 100; ++outer) {
+        // R = B - A X in FP64 and its column norms, for the chips still running
+        {
+            TimedLaunch tl(kResid, st);
+            hipLaunchKernelGGL(residual_kernel, dim3(static_cast<unsigned>(L.total_wgs)), dim3(kThreads), 0, st, x.cds,
+                               x.tab, s);
+            BKO_HIP(hipGetLastError());
+        }
+        if ((rc = host_norms(x, 1)) != BKO_OK) return rc;
+        BKO_HIP(hipMemcpyAsync(nh.data(), norms_d, sizeof(double) * nh.size(), hipMemcpyDeviceToHost, st));
+        BKO_HIP(hipStreamSynchronize(st));
+        int active = 0;
+        for (int c = 0; c < nc; ++c) {
+            ChipState &k = cs[c];
+            int *ch = &ctrlh[static_cast<size_t>(c) * kCtrlInts];
+            std::fill(ch, ch + kCtrlInts, 0);
+            if (k.done) {
+                ch[kConverged] = ch[kStop] = 1;
+                continue;
+            }
+            k.rnorm.resize(s);
+            double rel = 0.0;
+            bool finite = true;
+            for (int j = 0; j < s; ++j) {
+                k.rnorm[j] = std::sqrt(nh[static_cast<size_t>(c) * kMaxS + j]);
+                finite = finite && std::isfinite(k.rnorm[j]);
+                const double bj = k.bnorm[j];
+                rel = std::max(rel, bj > 0 ? k.rnorm[j] / bj : (k.rnorm[j] > 0 ? HUGE_VAL : 0.0));
+            }
+            k.info.max_rel_res = rel;
+            int status = -1;
+            if (!finite) status = BKO_EINVAL;
+            else if (rel <= tol) status = BKO_OK;
+            else if (k.info.iters >= max_iter) status = BKO_ENOCONV;
+            else if (rel > 0.5 * k.prev_rel && ++k.stagnant >= 3) status = BKO_EBREAKDOWN;
+            if (status < 0 && rel <= 0.5 * k.prev_rel) k.stagnant = 0;
+            if (status >= 0) {
+                k.info.status = status;
+                k.done = true;
+                ch[kConverged] = ch[kStop] = 1;
+                continue;
+            }
+            k.prev_rel = rel;
+            ch[kActive] = 1;
+            ++active;
+            for (int j = 0; j < s; ++j) {
+                const double target = 0.5 * tol * k.bnorm[j];
+                thh[static_cast<size_t>(c) * kMaxS + j] = f64 ? target : std::max(target, inner_rel_f32 * k.rnorm[j]);
+            }
+        }
+        if (active == 0) break;
+        BKO_HIP(hipMemcpyAsync(th_d, thh.data(), sizeof(double) * thh.size(), hipMemcpyHostToDevice, st));
+        BKO_HIP(hipMemcpyAsync(ctrl_d, ctrlh.data(), sizeof(int) * ctrlh.size(), hipMemcpyHostToDevice, st));
+        // inner solve on A D = R: W = R, first QR, Q = W S^+, P = Q, D = 0
+        hipLaunchKernelGGL((inner_start_kernel<T>), dim3(static_cast<unsigned>(L.total_wgs)), dim3(kThreads), 0, st, x.cds,
+                           x.tab, s);
+        BKO_HIP(hipGetLastError());
+        if ((rc = launch_row<T>(1, x, 1)) != BKO_OK) return rc;
+        if ((rc = launch_reduce_factor(x, rel_thr, 2)) != BKO_OK) return rc;
+        if ((rc = launch_row<T>(2, x, 0)) != BKO_OK) return rc;
+        int budget = 0;
+        for (int c = 0; c < nc; ++c)
+            if (!cs[c].done) budget = std::max(budget, max_iter - cs[c].info.iters);
+        int launched = 0, chunk = 4;
+        std::vector<int> hc(ctrlh.size());
+        while (true) {
+            const int todo = std::min(chunk, budget - launched);
+            if ((rc = run_chunk<T>(x, rel_thr, todo, gc, work)) != BKO_OK) return rc;
+            launched += todo;
+            BKO_HIP(hipMemcpyAsync(hc.data(), ctrl_d, sizeof(int) * hc.size(), hipMemcpyDeviceToHost, st));
+            BKO_HIP(hipStreamSynchronize(st));
+            bool all = true, capped = false;
+            for (int c = 0; c < nc; ++c) {
+                if (cs[c].done) continue;
+                const int *h = &hc[static_cast<size_t>(c) * kCtrlInts];
+                if (!h[kConverged]) {
+                    all = false;
+                    // a chip at its own iteration limit is stopped here
+                    if (cs[c].info.iters + h[kIters] >= max_iter) {
+                        const int stop[2] = {1, 1};
+                        BKO_HIP(hipMemcpyAsync(ctrl_d + static_cast<size_t>(c) * kCtrlInts + kConverged, stop,
+                                               sizeof(stop), hipMemcpyHostToDevice, st));
+                        capped = true;
+                    }
+                }
+            }
+            if (capped) BKO_HIP(hipStreamSynchronize(st));
+            if (all || launched >= budget) break;
+            chunk = std::min(chunk * 2, 64);
+        }
+        for (int c = 0; c < nc; ++c) {
+            if (cs[c].done) continue;
+            const int *h = &hc[static_cast<size_t>(c) * kCtrlInts];
+            cs[c].info.iters += h[kIters];
+            cs[c].info.refinements += 1;
+            cs[c].info.deflated = std::max(cs[c].info.deflated, h[kDeflated]);
+        }
+        hipLaunchKernelGGL((add_out_kernel<T>), dim3(static_cast<unsigned>(L.total_wgs)), dim3(kThreads), 0, st, x.cds,
+                           x.tab, s);
+        BKO_HIP(hipGetLastError());
+    }
+    BKO_HIP(hipStreamSynchronize(st));
+    bko_status worst = BKO_OK;
+    for (int c = 0; c < nc; ++c) {
+        if (!cs[c].done) cs[c].info.status = BKO_ENOCONV;
+        if (infos) infos[c] = cs[c].info;
+        if (cs[c].info.status != BKO_OK && worst == BKO_OK) worst = static_cast<bko_status>(cs[c].info.status);
+    }
+    if (worst == BKO_ENOCONV) set_error("no convergence within %d iterations", max_iter);
+    if (worst == BKO_EBREAKDOWN) set_error("block iteration stagnated");
+    if (worst == BKO_EINVAL) set_error("residual is not finite (initial guess or operator invalid)");
+    return worst;
 }
 
 }  // namespace
 
+// ------------------------------------------------------------------ public entry points
+
 size_t solve_workspace_bytes(int64_t n, int s, bko_dtype compute)
 {
-    return carve(nullptr, n, s, compute).bytes;
+    Operator op{};
+    op.n = n;
+    const Operator *ops[1] = {&op};
+    return make_layout(ops, 1, s, compute, kMaxWgs).bytes;
 }
 
 bko_status block_solve(const Operator &op, int s, const double *B, int64_t ldb, double *X, int64_t ldx,
@@ -902,105 +1418,112 @@ bko_status block_solve(const Operator &op, int s, const double *B, int64_t ldb, 
                        size_t work_bytes, bko_solve_info *info, hipStream_t st)
 {
     (void)work_bytes;
-    const Workspace ws = carve(work, op.n, s, compute);
-    const int64_t n = op.n;
-    const unsigned rblocks = static_cast<unsigned>((n + 255) / 256);
+    const Operator *ops[1] = {&op};
+    const Layout L = make_layout(ops, 1, s, compute, kMaxWgs);
+    const double *Bs[1] = {B};
+    double *Xs[1] = {X};
+    const double *X0s[1] = {X0};
+    const int64_t lb[1] = {ldb}, lx[1] = {ldx}, lx0[1] = {ldx0};
+    if (compute == BKO_F64)
+        return batch_solve_t<double>(L, work, Bs, lb, Xs, lx, X0s, lx0, tol, max_iter, info, st, nullptr);
+    return batch_solve_t<float>(L, work, Bs, lb, Xs, lx, X0s, lx0, tol, max_iter, info, st, nullptr);
+}
+
+size_t batch_workspace_bytes(const BatchPlan &p)
+{
+    return make_layout(p.ops.data(), static_cast<int>(p.ops.size()), p.s, p.compute, kMaxWgs).bytes;
+}
+
+namespace {
+
+// Time the partial-producing row kernels (stencil + Gram, and the W^T W
+// Gram) of the whole batch at one workgroup cap; milliseconds per pass.
+template <class T>
+bko_status time_cap(const BatchPlan &p, int cap, void *work, hipStream_t st, float &ms)
+{
+    const int nc = static_cast<int>(p.ops.size());
+    const Layout L = make_layout(p.ops.data(), nc, p.s, p.compute, cap);
+    char *base = static_cast<char *>(work);
+    const std::vector<ChipDev> recs = chip_records(L, work, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    const std::vector<uint16_t> tabh = wg_table(L);
+    BKO_HIP(hipMemcpyAsync(base + L.off_cds, recs.data(), sizeof(ChipDev) * nc, hipMemcpyHostToDevice, st));
+    BKO_HIP(hipMemcpyAsync(base + L.off_tab, tabh.data(), sizeof(uint16_t) * tabh.size(), hipMemcpyHostToDevice, st));
+    Ctx x{&L, reinterpret_cast<const ChipDev *>(base + L.off_cds), reinterpret_cast<const uint16_t *>(base + L.off_tab), st};
     bko_status rc;
-    // LDS needed by the FP64 update kernel at this s
-    {
-        const size_t sp = 16 * static_cast<size_t>(nb_for(s));
-        const size_t need = 3 * (compute == BKO_F64 ? 8 : 4) * sp * (sp + 1);
-        const size_t cap = device_max_lds();
-        if (need > cap || sizeof(double) * 4 * s * s > cap) {
-            set_error("s = %d needs %zu bytes of LDS per workgroup in this precision; the device grants %zu", s, need,
-                      cap);
-            return BKO_EINVAL;
-        }
+    auto pass = [&]() -> bko_status {
+        bko_status r;
+        if ((r = launch_row<T>(0, x, 0)) != BKO_OK) return r;
+        return launch_row<T>(1, x, 1);
+    };
+    if ((rc = pass()) != BKO_OK) return rc;
+    hipEvent_t a = nullptr, b = nullptr;
+    BKO_HIP(hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return hip_fail(hipErrorOutOfMemory, "hipEventCreate");
     }
-    std::vector<double> bnorm, rnorm;
-    if ((rc = host_colnorms(B, ldb, n, s, ws.colparts, bnorm, st)) != BKO_OK) return rc;
-    for (int j = 0; j < s; ++j)
-        if (!std::isfinite(bnorm[j])) {
-            set_error("right-hand side column %d is not finite", j);
-            return BKO_EINVAL;
-        }
-    // X = X0 or 0
-    if (X0 == nullptr) {
-        for (int j = 0; j < s; ++j)
-            if ((rc = launch_zero(X + j * ldx, sizeof(double) * n, st)) != BKO_OK) return rc;
-    } else if (X0 != X) {
-        hipLaunchKernelGGL(copy_block_kernel, dim3(rblocks), dim3(256), 0, st, X0, ldx0, X, ldx, n, s);
-        BKO_HIP(hipGetLastError());
+    constexpr int kReps = 5;
+    (void)hipEventRecord(a, st);
+    for (int r = 0; r < kReps && rc == BKO_OK; ++r) rc = pass();
+    (void)hipEventRecord(b, st);
+    const hipError_t e = hipEventSynchronize(b);
+    float t = 0.f;
+    if (e == hipSuccess) (void)hipEventElapsedTime(&t, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc != BKO_OK) return rc;
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    ms = t / kReps;
+    return BKO_OK;
+}
+
+}  // namespace
+
+// Autotuner: choose the per-chip workgroup cap of the row kernels (how many
+// tiles each workgroup walks, and how many Gram partials each reduction
+// sums) by timing every candidate on this batch and workspace.  The
+// workspace contents are scratch here (control words cleared: every chip
+// runs).
+bko_status batch_tune(BatchPlan &p, void *work, hipStream_t st)
+{
+    const int nc = static_cast<int>(p.ops.size());
+    const Layout L0 = make_layout(p.ops.data(), nc, p.s, p.compute, kMaxWgs);
+    if (row_kernel_lds(p.s, p.compute) > device_max_lds()) {
+        set_error("s = %d needs %zu bytes of LDS per workgroup in this precision; the device grants %zu", p.s,
+                  row_kernel_lds(p.s, p.compute), device_max_lds());
+        return BKO_EINVAL;
     }
-    bko_solve_info inf{};
-    inf.status = BKO_ENOCONV;
-    double prev_rel = HUGE_VAL;
-    int stagnant = 0;
-    const double inner_rel_f32 = 1e-5;
-    for (int outer = 0; outer < 100; ++outer) {
-        // R = B - A X in FP64 (the cast into the inner blocks reads rows < n)
-        {
-            TimedLaunch tl(kResid, st);
-            if ((rc = launch_stencil(op, s, X, ldx, BKO_F64, ws.R64, ws.ldw, BKO_F64, BKO_F64, B, ldb, st)) != BKO_OK)
-                return rc;
-        }
-        if ((rc = host_colnorms(ws.R64, ws.ldw, n, s, ws.colparts, rnorm, st)) != BKO_OK) return rc;
-        double rel = 0.0;
-        bool finite = true;
-        for (int j = 0; j < s; ++j) {
-            finite = finite && std::isfinite(rnorm[j]);
-            rel = std::max(rel, bnorm[j] > 0 ? rnorm[j] / bnorm[j] : (rnorm[j] > 0 ? HUGE_VAL : 0.0));
-        }
-        inf.max_rel_res = rel;
-        if (!finite) {
-            set_error("residual is not finite (initial guess or operator invalid)");
-            inf.status = BKO_EINVAL;
-            break;
-        }
-        if (rel <= tol) {
-            inf.status = BKO_OK;
-            break;
-        }
-        if (inf.iters >= max_iter) {
-            inf.status = BKO_ENOCONV;
-            break;
-        }
-        if (rel > 0.5 * prev_rel) {
-            if (++stagnant >= 3) {
-                inf.status = BKO_EBREAKDOWN;
-                break;
-            }
-        } else {
-            stagnant = 0;
-        }
-        prev_rel = rel;
-        std::vector<double> th(s);
-        for (int j = 0; j < s; ++j) {
-            const double target = 0.5 * tol * bnorm[j];
-            th[j] = compute == BKO_F64 ? target : std::max(target, inner_rel_f32 * rnorm[j]);
-        }
-        int it = 0, defl = 0;
-        bool alldefl = false;
-        const int budget = max_iter - inf.iters;
-        if (compute == BKO_F64) rc = inner_solve<double>(op, s, ws, th, budget, it, defl, alldefl, st);
-        else rc = inner_solve<float>(op, s, ws, th, budget, it, defl, alldefl, st);
+    bko_status rc;
+    // finite, defined contents for the timed kernels
+    if ((rc = launch_zero(work, L0.bytes, st)) != BKO_OK) return rc;
+    p.tune_ms.clear();
+    float best = 0.f;
+    int best_cap = kMaxWgs;
+    for (int cap : {64, 128, 256, 512}) {
+        float ms = 0.f;
+        rc = p.compute == BKO_F64 ? time_cap<double>(p, cap, work, st, ms) : time_cap<float>(p, cap, work, st, ms);
         if (rc != BKO_OK) return rc;
-        inf.iters += it;
-        inf.refinements += 1;
-        inf.deflated = std::max(inf.deflated, defl);
-        if (compute == BKO_F64)
-            hipLaunchKernelGGL((add_out_kernel<double>), dim3(rblocks), dim3(256), 0, st, X, ldx,
-                               static_cast<const double *>(ws.Dv), ws.ldw, n, s);
-        else
-            hipLaunchKernelGGL((add_out_kernel<float>), dim3(rblocks), dim3(256), 0, st, X, ldx,
-                               static_cast<const float *>(ws.Dv), ws.ldw, n, s);
-        BKO_HIP(hipGetLastError());
+        p.tune_ms.push_back({cap, ms});
+        if (best_cap == kMaxWgs && p.tune_ms.size() == 1) best = ms, best_cap = cap;
+        else if (ms < best) best = ms, best_cap = cap;
     }
-    BKO_HIP(hipStreamSynchronize(st));
-    if (info) *info = inf;
-    if (inf.status == BKO_ENOCONV) set_error("no convergence within %d iterations (rel res %.3e)", max_iter, inf.max_rel_res);
-    if (inf.status == BKO_EBREAKDOWN) set_error("block iteration stagnated at rel res %.3e", inf.max_rel_res);
-    return static_cast<bko_status>(inf.status);
+    p.wg_cap = best_cap;
+    p.tuned = true;
+    p.graphs.clear();
+    return BKO_OK;
+}
+
+bko_status batch_solve(BatchPlan &p, const double *const *B, const int64_t *ldb, double *const *X, const int64_t *ldx,
+                       const double *const *X0, const int64_t *ldx0, double tol, int max_iter, void *work,
+                       bko_solve_info *infos, hipStream_t st)
+{
+    bko_status rc;
+    if (!p.tuned && (rc = batch_tune(p, work, st)) != BKO_OK) return rc;
+    const int nc = static_cast<int>(p.ops.size());
+    const Layout L = make_layout(p.ops.data(), nc, p.s, p.compute, p.wg_cap);
+    if (p.compute == BKO_F64)
+        return batch_solve_t<double>(L, work, B, ldb, X, ldx, X0, ldx0, tol, max_iter, infos, st, &p.graphs);
+    return batch_solve_t<float>(L, work, B, ldb, X, ldx, X0, ldx0, tol, max_iter, infos, st, &p.graphs);
 }
 
 }  // namespace bko

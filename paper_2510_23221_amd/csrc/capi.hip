@@ -97,6 +97,8 @@ bko_status drain(TimingState &t)
 }
 }  // namespace
 
+bool timing_active() { return timing().mask != 0; }
+
 TimedLaunch::TimedLaunch(int fam, hipStream_t s) : family(fam), stream(s), ev0(nullptr)
 {
     TimingState &t = timing();
@@ -448,6 +450,96 @@ bko_status bko_cg_solve(bko_op A, int m, const double *B, int ldb, double *X, in
         return BKO_ENOMEM;
     }
     return cg_solve(op, m, B, ldb, X, ldx, tol, max_iter, work, iters, info, static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+bko_status bko_batch_plan_create(int nchips, const bko_op *ops, int s, bko_dtype compute, bko_batch *out)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(out != nullptr && ops != nullptr, "NULL argument");
+    *out = nullptr;
+    BKO_CHECK(nchips >= 1 && nchips <= 65535, "nchips = %d outside [1, 65535]", nchips);
+    BKO_CHECK(s >= 1 && s <= 64, "s = %d outside [1, 64]", s);
+    BKO_CHECK(compute == BKO_F64 || compute == BKO_F32, "compute must be BKO_F64 or BKO_F32");
+    for (int c = 0; c < nchips; ++c) BKO_CHECK(ops[c] != nullptr, "operator %d is NULL", c);
+    BatchPlan *p = new BatchPlan();
+    p->s = s;
+    p->compute = compute;
+    for (int c = 0; c < nchips; ++c) p->ops.push_back(reinterpret_cast<const Operator *>(ops[c]));
+    *out = reinterpret_cast<bko_batch>(p);
+    return BKO_OK;
+    BKO_GUARD_END
+}
+
+bko_status bko_batch_plan_destroy(bko_batch plan)
+{
+    delete reinterpret_cast<BatchPlan *>(plan);
+    return BKO_OK;
+}
+
+bko_status bko_batch_workspace_bytes(bko_batch plan, size_t *bytes)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(plan != nullptr && bytes != nullptr, "NULL argument");
+    *bytes = batch_workspace_bytes(*reinterpret_cast<BatchPlan *>(plan));
+    return BKO_OK;
+    BKO_GUARD_END
+}
+
+static bko_status check_batch_work(const BatchPlan &p, void *work, size_t work_bytes)
+{
+    BKO_CHECK(work != nullptr, "NULL workspace");
+    BKO_CHECK(reinterpret_cast<uintptr_t>(work) % 256 == 0, "workspace must be 256-byte aligned");
+    const size_t need = batch_workspace_bytes(p);
+    if (work_bytes < need) {
+        set_error("workspace has %zu bytes, need %zu", work_bytes, need);
+        return BKO_ENOMEM;
+    }
+    return BKO_OK;
+}
+
+bko_status bko_batch_tune(bko_batch plan, void *work, size_t work_bytes, int *wg_cap, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(plan != nullptr, "NULL plan");
+    BatchPlan &p = *reinterpret_cast<BatchPlan *>(plan);
+    bko_status rc = check_batch_work(p, work, work_bytes);
+    if (rc != BKO_OK) return rc;
+    rc = batch_tune(p, work, static_cast<hipStream_t>(stream));
+    if (rc == BKO_OK && wg_cap) *wg_cap = p.wg_cap;
+    return rc;
+    BKO_GUARD_END
+}
+
+bko_status bko_batch_solve(bko_batch plan, const double *const *B, const int *ldb, double *const *X, const int *ldx,
+                           const double *const *X0, const int *ldx0, double tol, int max_iter, void *work,
+                           size_t work_bytes, bko_solve_info *infos, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(plan != nullptr, "NULL plan");
+    BatchPlan &p = *reinterpret_cast<BatchPlan *>(plan);
+    const int nc = static_cast<int>(p.ops.size());
+    BKO_CHECK(B && ldb && X && ldx, "NULL array table");
+    BKO_CHECK(X0 == nullptr || ldx0 != nullptr, "X0 given without ldx0");
+    BKO_CHECK(tol > 0.0 && std::isfinite(tol), "tol must be positive");
+    BKO_CHECK(max_iter >= 1, "max_iter must be >= 1");
+    std::vector<int64_t> lb(nc), lx(nc), lx0(nc, 0);
+    for (int c = 0; c < nc; ++c) {
+        const int64_t n = p.ops[c]->n;
+        BKO_CHECK(B[c] && X[c], "NULL array of chip %d", c);
+        BKO_CHECK(ldb[c] >= n && ldx[c] >= n, "leading dimensions of chip %d must be >= n", c);
+        lb[c] = ldb[c];
+        lx[c] = ldx[c];
+        if (X0 && X0[c]) {
+            BKO_CHECK(ldx0[c] >= n, "ldx0 of chip %d must be >= n", c);
+            if (X0[c] == X[c]) BKO_CHECK(ldx0[c] == ldx[c], "X0 of chip %d aliases X with another ld", c);
+            lx0[c] = ldx0[c];
+        }
+    }
+    bko_status rc = check_batch_work(p, work, work_bytes);
+    if (rc != BKO_OK) return rc;
+    return batch_solve(p, B, lb.data(), X, lx.data(), X0, lx0.data(), tol, max_iter, work, infos,
+                       static_cast<hipStream_t>(stream));
     BKO_GUARD_END
 }
 

@@ -163,6 +163,10 @@ enum TimingFamily {
     kNumFamilies = 8
 };
 
+// True while any timing family is selected (launches then carry events and
+// are not captured into graphs).
+bool timing_active();
+
 struct TimedLaunch {
     TimedLaunch(int family, hipStream_t s);
     ~TimedLaunch();

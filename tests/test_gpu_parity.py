@@ -395,3 +395,79 @@ def test_block_beats_per_sample_cg_iterations(dev):
     _, info_b = capi.block_krylov_solve(G, B, w.tol)
     _, iters, _ = capi.cg_solve(G, B, w.tol)
     assert info_b["iters"] < iters.mean()
+
+
+# ------------------------------------------------------------------ batches of chips
+
+def _batch_chips():
+    """Uneven grids (several tiles, ragged tails, 2-D and stacked, all face kinds)."""
+    rng = np.random.default_rng(21)
+    chips = [_chip("ragged"), _chip("2d"), synth.chip_stack(rng, 24, 20, 5), _chip("line"),
+             synth.chip_stack(rng, 48, 48, 4)]
+    return chips
+
+
+@pytest.mark.parametrize("compute,use_stream", [(capi.F64, True), (capi.F32, True), (capi.F64, False)])
+def test_batch_solve_matches_oracle(dev, compute, use_stream):
+    chips = _batch_chips()
+    As = [oracle.assemble_chip(c) for c in chips]
+    Gs = [capi.HeatOperator.from_chip(c, dev) for c in chips]
+    rng = np.random.default_rng(22)
+    s = 8
+    Bs = [rng.standard_normal((s, A.n)) for A in As]
+    plan = capi.BatchPlan(Gs, s, compute)
+    stream = torch.cuda.Stream() if use_stream else None
+    tol = 1e-10 if compute == capi.F64 else 1e-8
+    with torch.cuda.stream(stream) if stream is not None else torch.cuda.stream(torch.cuda.current_stream()):
+        cap = plan.tune(dev, stream=stream)
+        assert cap in (64, 128, 256, 512)
+        Xs, infos = plan.solve([torch.as_tensor(B, device=dev) for B in Bs], tol, stream=stream)
+        # a second call replays the captured iteration chunks
+        Xs2, infos2 = plan.solve([torch.as_tensor(B, device=dev) for B in Bs], tol, stream=stream)
+    torch.cuda.synchronize()
+    for k, (A, B, X, info) in enumerate(zip(As, Bs, Xs, infos)):
+        X = to_np(X)
+        R = B - oracle.apply_many(A, X)
+        rel = np.linalg.norm(R, axis=1) / np.linalg.norm(B, axis=1)
+        floor = 8 * U64 * np.linalg.norm(oracle.apply_many(abs_csr(A), np.abs(X)) + np.abs(B), axis=1) \
+            / np.linalg.norm(B, axis=1)
+        assert info["status"] == capi.OK, (k, info)
+        assert (rel <= tol * 1.0001 + floor).all(), (k, rel.max(), info)
+        assert abs(info["max_rel_res"] - rel.max()) <= 1e-3 * tol + 0.01 * rel.max() + floor.max()
+        X_ref, _, _ = oracle.cg_many(A, B, 1e-13)
+        if compute == capi.F64 and chips[k].nx != 300:
+            assert rel_fro(X, X_ref) <= 1e-7, (k, rel_fro(X, X_ref))
+        # the replayed solve reproduces the first one exactly (same kernels, same order)
+        assert np.array_equal(X, to_np(Xs2[k])) and infos2[k]["iters"] == info["iters"]
+
+
+def test_batch_matches_single_chip_solves(dev):
+    """Each chip of a batch converges like its own single-chip solve."""
+    chips = _batch_chips()[:3]
+    Gs = [capi.HeatOperator.from_chip(c, dev) for c in chips]
+    rng = np.random.default_rng(23)
+    Bs = [torch.as_tensor(rng.standard_normal((5, c.n)), device=dev) for c in chips]
+    plan = capi.BatchPlan(Gs, 5, capi.F64)
+    Xs, infos = plan.solve(Bs, 1e-10)
+    for G, B, X, info in zip(Gs, Bs, Xs, infos):
+        X1, info1 = capi.block_krylov_solve(G, B, 1e-10)
+        assert abs(info["iters"] - info1["iters"]) <= 2
+        assert rel_fro(to_np(X), to_np(X1)) <= 1e-8
+
+
+def test_batch_initial_guess_and_zero_chip(dev):
+    """A chip started at its solution takes no iteration and a chip with zero
+    right-hand sides stays zero, while the other chips of the batch iterate."""
+    chips = _batch_chips()[:3]
+    As = [oracle.assemble_chip(c) for c in chips]
+    Gs = [capi.HeatOperator.from_chip(c, dev) for c in chips]
+    rng = np.random.default_rng(24)
+    Bs = [rng.standard_normal((4, A.n)) for A in As]
+    Bs[2][:] = 0.0
+    X_ref, _, _ = oracle.cg_many(As[0], Bs[0], 1e-13)
+    plan = capi.BatchPlan(Gs, 4, capi.F64)
+    X0s = [torch.as_tensor(X_ref, device=dev), None, None]
+    Xs, infos = plan.solve([torch.as_tensor(B, device=dev) for B in Bs], 1e-10, X0s=X0s)
+    assert infos[0]["iters"] == 0 and infos[1]["iters"] > 0
+    assert infos[2]["iters"] == 0 and np.abs(to_np(Xs[2])).max() == 0.0
+    assert all(i["status"] == capi.OK for i in infos)
