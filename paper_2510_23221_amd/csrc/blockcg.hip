@@ -81,6 +81,9 @@ struct Small {
     float *M1f, *M2f, *M3f, *M4f;
 };
 
+// Device view of Small with global-memory pointers.
+struct SmallG;
+
 // What a grouped kernel knows about one chip.
 struct ChipDev {
     // operator: coefficients in the block precision, and in FP64
@@ -125,6 +128,21 @@ __device__ inline d4 mma64(double a, double b, d4 c) { return __builtin_amdgcn_m
 // index of the (a, b) upper block, a <= b < NB
 template <int NB> __device__ constexpr int ublock(int a, int b) { return a * NB - a * (a - 1) / 2 + (b - a); }
 
+// Pointers read from the chip records are generic to the compiler; marking
+// them as global memory lets it emit global (not flat) loads and stores.
+template <class T> using gptr = T __attribute__((address_space(1))) *;
+template <class T> __device__ __forceinline__ gptr<T> glb(T *p) { return (gptr<T>)p; }
+
+struct SmallG {
+    gptr<double> C, M1, M2, M3, M4, th;
+    gptr<float> M1f, M2f, M3f, M4f;
+    __device__ explicit SmallG(const Small &m)
+        : C(glb(m.C)), M1(glb(m.M1)), M2(glb(m.M2)), M3(glb(m.M3)), M4(glb(m.M4)), th(glb(m.th)), M1f(glb(m.M1f)),
+          M2f(glb(m.M2f)), M3f(glb(m.M3f)), M4f(glb(m.M4f))
+    {
+    }
+};
+
 // Chip of this workgroup and the workgroup's index within the chip.
 __device__ inline const ChipDev &chip_of(const ChipDev *cds, const uint16_t *tab, int &local)
 {
@@ -139,7 +157,7 @@ __device__ inline const ChipDev &chip_of(const ChipDev *cds, const uint16_t *tab
 // at least s * s doubles) and write it to out.  kSym: only upper blocks were
 // formed.
 template <int NB, bool kSym, int NBLK>
-__device__ void publish_partial(const d4 (&g)[NBLK], int s, double *lds, double *out)
+__device__ void publish_partial(const d4 (&g)[NBLK], int s, double *lds, gptr<double> out)
 {
     const int ss = s * s;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -196,7 +214,8 @@ __global__ __launch_bounds__(kThreads) void spmm_gram_kernel(const ChipDev *__re
     constexpr int CSTEP = kThreads / TR;  // column classes
     int local;
     const ChipDev &cd = chip_of(cds, tab, local);
-    int *ctrl = cd.ctrl;
+    const int wgs = cd.wgs;
+    gptr<int> ctrl = glb(cd.ctrl);
     if (ctrl[kConverged]) {
         // the iteration before this one converged: tell the later kernels
         if (local == 0 && threadIdx.x == 0) ctrl[kStop] = 1;
@@ -213,12 +232,12 @@ __global__ __launch_bounds__(kThreads) void spmm_gram_kernel(const ChipDev *__re
         Ps[e] = T(0);
         APs[e] = T(0);
     }
-    const T *__restrict__ P = static_cast<const T *>(cd.P);
-    T *__restrict__ AP = static_cast<T *>(cd.AP);
-    const T *__restrict__ cdiag = static_cast<const T *>(cd.cdiag);
-    const T *__restrict__ cwx = static_cast<const T *>(cd.cwx);
-    const T *__restrict__ cwy = static_cast<const T *>(cd.cwy);
-    const T *__restrict__ cwz = static_cast<const T *>(cd.cwz);
+    const gptr<const T> __restrict__ P = glb(static_cast<const T *>(cd.P));
+    const gptr<T> __restrict__ AP = glb(static_cast<T *>(cd.AP));
+    const gptr<const T> __restrict__ cdiag = glb(static_cast<const T *>(cd.cdiag));
+    const gptr<const T> __restrict__ cwx = glb(static_cast<const T *>(cd.cwx));
+    const gptr<const T> __restrict__ cwy = glb(static_cast<const T *>(cd.cwy));
+    const gptr<const T> __restrict__ cwz = glb(static_cast<const T *>(cd.cwz));
     const int nx = cd.nx, ny = cd.ny, nz = cd.nz;
     const int64_t n = cd.n, ldw = cd.ldw;
     const int64_t plane = static_cast<int64_t>(nx) * ny;
@@ -228,7 +247,7 @@ __global__ __launch_bounds__(kThreads) void spmm_gram_kernel(const ChipDev *__re
 #pragma unroll
     for (int q = 0; q < NB * NB; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
     const int64_t ntiles = ldw / kTileRows;
-    for (int64_t tile = local; tile < ntiles; tile += cd.wgs) {
+    for (int64_t tile = local; tile < ntiles; tile += wgs) {
         for (int half = 0; half < kTileRows / TR; ++half) {
             const int64_t a = tile * kTileRows + half * TR + cell;
             if (a < n) {
@@ -246,7 +265,7 @@ __global__ __launch_bounds__(kThreads) void spmm_gram_kernel(const ChipDev *__re
                 const T czp = cwz[a], czm = l > 0 ? cwz[a - plane] : T(0);
 #pragma unroll 4
                 for (int c = cls; c < s; c += CSTEP) {
-                    const T *x = P + c * ldw + a;
+                    const gptr<const T> x = P + c * ldw + a;
                     const T xc = x[0];
                     const T nb = cxm * x[oxm] + cxp * x[oxp] + cym * x[oym] + cyp * x[oyp] + czm * x[ozm] + czp * x[ozp];
                     const T y = d * xc - nb;
@@ -288,7 +307,7 @@ __global__ __launch_bounds__(kThreads) void spmm_gram_kernel(const ChipDev *__re
             __syncthreads();
         }
     }
-    publish_partial<NB, false>(acc, s, reinterpret_cast<double *>(smem), cd.parts + static_cast<size_t>(local) * s * s);
+    publish_partial<NB, false>(acc, s, reinterpret_cast<double *>(smem), glb(cd.parts) + static_cast<size_t>(local) * s * s);
 }
 
 // gram = sum over the chip's partials, entry by entry in index order
@@ -296,8 +315,8 @@ __global__ __launch_bounds__(kThreads) void spmm_gram_kernel(const ChipDev *__re
 __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(const ChipDev *__restrict__ cds, int ss)
 {
     const ChipDev &cd = cds[blockIdx.y];
-    if (cd.ctrl[kConverged]) return;
-    const double *__restrict__ parts = cd.parts;
+    if (glb(cd.ctrl)[kConverged]) return;
+    const gptr<const double> __restrict__ parts = glb(static_cast<const double *>(cd.parts));
     const int nparts = cd.wgs;
     __shared__ double sh[kThreads];
     const int per = (ss + gridDim.x - 1) / gridDim.x;  // entries of this workgroup (<= 64)
@@ -324,7 +343,7 @@ __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(const ChipDev *__
     if (sl == 0 && e < ss) {
         double tot = 0.0;
         for (int q = 0; q < slices; ++q) tot += sh[q * per + le];
-        cd.gram[e] = tot;
+        glb(cd.gram)[e] = tot;
     }
 }
 
@@ -338,14 +357,25 @@ __device__ __forceinline__ double readlane_f64(double v, int lane)
     return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
 }
 
+// 1 / p from the hardware reciprocal estimate and two Newton steps (each
+// squares the relative error), for the pivots on the elimination's serial
+// path; within an ulp or two of the correctly rounded quotient for the
+// normal, positive pivots it is used on.
+__device__ __forceinline__ double recip(double p)
+{
+    double r = __builtin_amdgcn_rcp(p);
+    r = fma(r, fma(-p, r, 1.0), r);
+    return fma(r, fma(-p, r, 1.0), r);
+}
+
 // Masked LDL^T elimination of [G | I] by one wavefront, for s <= SP <= 32:
 // lane c holds column c of the 2 SP columns in registers; each pivot row of
 // the column is broadcast with readlane, so no LDS traffic or barrier per
 // pivot.  Indices s <= i < SP are decoupled padding with pivot gmax.
 // Writes the result (A[i][j], j < 2s: left half U, right half E) to LDS.
 template <int SP>
-__device__ __forceinline__ void wave_eliminate(const double *__restrict__ gram, int s, double rel_thr, double *A,
-                                               int *active)
+__device__ __forceinline__ void wave_eliminate(const gptr<const double> __restrict__ gram, int s, double rel_thr,
+                                               double *A, int *active)
 {
     const int lane = threadIdx.x & 63;
     const int w = 2 * s;
@@ -366,7 +396,7 @@ __device__ __forceinline__ void wave_eliminate(const double *__restrict__ gram, 
         const double p = readlane_f64(a[k], k);
         const bool act = p > thr && isfinite(p);
         // this column's pivot-row entry, scaled; zero when the pivot is inactive
-        const double m = act ? -a[k] * (1.0 / p) : 0.0;
+        const double m = act ? -a[k] * recip(p) : 0.0;
 #pragma unroll
         for (int i = k + 1; i < SP; ++i) a[i] = fma(readlane_f64(a[i], k), m, a[i]);
         if (lane == 0 && k < s) active[k] = act ? 1 : 0;
@@ -417,10 +447,10 @@ __global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__re
                                                              int mode)
 {
     const ChipDev &cd = cds[blockIdx.x];  // one workgroup per chip
-    int *ctrl = cd.ctrl;
+    const gptr<int> ctrl = glb(cd.ctrl);
     if (ctrl[kConverged]) return;
-    const double *__restrict__ gram = cd.gram;
-    const Small sm = cd.sm;
+    const gptr<const double> __restrict__ gram = glb(static_cast<const double *>(cd.gram));
+    const SmallG sm(cd.sm);
     constexpr int E2 = E > 1 ? E / 2 : 1;
     constexpr int EA = SP > 0 ? 1 : E;  // register row segment of the LDS elimination
     extern __shared__ __align__(16) double lds[];
@@ -445,7 +475,16 @@ __global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__re
         rowbuf[w + e] = 0.0;
         rowbuf[2 * w + E + e] = 0.0;
     }
-    for (int e = tid; e < ss; e += kFacThreads) Cl[e] = sm.C[e];
+    {
+        // all loads of C in flight before the LDS stores
+        constexpr int IT = kMaxS * kMaxS / kFacThreads;
+        double cv[IT];
+#pragma unroll
+        for (int i = 0; i < IT; ++i) cv[i] = tid + i * kFacThreads < ss ? sm.C[tid + i * kFacThreads] : 0.0;
+#pragma unroll
+        for (int i = 0; i < IT; ++i)
+            if (tid + i * kFacThreads < ss) Cl[tid + i * kFacThreads] = cv[i];
+    }
     if (tid == 0) notconv = 0;
     if constexpr (SP > 0) {
         if (tid < 64) wave_eliminate<SP>(gram, s, rel_thr, A, active);
@@ -609,15 +648,32 @@ inline int factor_segment(int s)
 
 // ------------------------------------------------------------------ block updates
 
-// Stage an s x s FP64 matrix (row-major, ld s) as a padded SP x MST tile of T
-// in LDS, optionally negated; entries outside s x s are zero.
-template <class T, int SP, int MST>
-__device__ inline void stage_small(T *dst, const T *src, int s, bool neg)
+// Stage NM s x s matrices (row-major, ld s) as padded SP x MST tiles of T in
+// LDS; entries outside s x s are zero and neg[q] negates matrix q.  The
+// loads of every matrix are issued in groups before their LDS stores, so a
+// workgroup pays a few memory latencies here, not one per element it stages.
+template <class T, int SP, int MST, int NM>
+__device__ inline void stage_small(T *const (&dst)[NM], const gptr<const T> (&src)[NM], int s, const bool (&neg)[NM])
 {
-    for (int e = threadIdx.x; e < SP * MST; e += kThreads) {
-        const int k = e / MST, j = e % MST;
-        const T v = (k < s && j < s) ? src[k * s + j] : T(0);
-        dst[e] = neg ? -v : v;
+    constexpr int IT = (SP * MST + kThreads - 1) / kThreads;
+    constexpr int CH = IT < 6 ? IT : 6;
+    for (int i0 = 0; i0 < IT; i0 += CH) {
+        T v[NM][CH];
+#pragma unroll
+        for (int q = 0; q < NM; ++q)
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const int e = threadIdx.x + (i0 + i) * kThreads;
+                const int k = e / MST, j = e % MST;
+                v[q][i] = (i0 + i < IT && e < SP * MST && k < s && j < s) ? src[q][k * s + j] : T(0);
+            }
+#pragma unroll
+        for (int q = 0; q < NM; ++q)
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const int e = threadIdx.x + (i0 + i) * kThreads;
+                if (i0 + i < IT && e < SP * MST) dst[q][e] = neg[q] ? -v[q][i] : v[q][i];
+            }
     }
 }
 
@@ -632,7 +688,8 @@ __global__ __launch_bounds__(kThreads) void update_w_kernel(const ChipDev *__res
 {
     int local;
     const ChipDev &cd = chip_of(cds, tab, local);
-    if (cd.ctrl[kConverged]) return;
+    const int wgs = cd.wgs;
+    if (glb(cd.ctrl)[kConverged]) return;
     using V = typename MF<T>::V;
     constexpr bool kF64 = MF<T>::kF64;
     constexpr int KS = 4 * NB;  // k steps of 4 over the padded width 16 NB
@@ -643,14 +700,15 @@ __global__ __launch_bounds__(kThreads) void update_w_kernel(const ChipDev *__res
     __shared__ double lds[kMaxS * kMaxS];
     const bool f64 = sizeof(T) == 8;
     if (!init) {
-        stage_small<T, SP, MST>(M3s, f64 ? reinterpret_cast<const T *>(cd.sm.M3) : reinterpret_cast<const T *>(cd.sm.M3f),
-                                s, false);
-        stage_small<T, SP, MST>(M2s, f64 ? reinterpret_cast<const T *>(cd.sm.M2) : reinterpret_cast<const T *>(cd.sm.M2f),
-                                s, true);
+        T *const dst[2] = {M3s, M2s};
+        const gptr<const T> src[2] = {glb(f64 ? reinterpret_cast<const T *>(cd.sm.M3) : reinterpret_cast<const T *>(cd.sm.M3f)),
+                                      glb(f64 ? reinterpret_cast<const T *>(cd.sm.M2) : reinterpret_cast<const T *>(cd.sm.M2f))};
+        const bool neg[2] = {false, true};
+        stage_small<T, SP, MST, 2>(dst, src, s, neg);
         __syncthreads();
     }
-    T *__restrict__ W = static_cast<T *>(cd.W);
-    const T *__restrict__ AP = static_cast<const T *>(cd.AP);
+    const gptr<T> __restrict__ W = glb(static_cast<T *>(cd.W));
+    const gptr<const T> __restrict__ AP = glb(static_cast<const T *>(cd.AP));
     const int64_t ldw = cd.ldw;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
@@ -658,7 +716,7 @@ __global__ __launch_bounds__(kThreads) void update_w_kernel(const ChipDev *__res
 #pragma unroll
     for (int q = 0; q < NB * (NB + 1) / 2; ++q) g[q] = d4{0.0, 0.0, 0.0, 0.0};
     const int64_t ntiles = ldw / kTileRows;
-    for (int64_t tile = local; tile < ntiles; tile += cd.wgs) {
+    for (int64_t tile = local; tile < ntiles; tile += wgs) {
         for (int rb = 0; rb < 4; ++rb) {
             const int64_t r0 = tile * kTileRows + wave * 64 + rb * 16;
             V wv[NB];
@@ -712,7 +770,7 @@ __global__ __launch_bounds__(kThreads) void update_w_kernel(const ChipDev *__res
                                                       g[ublock<NB>(ab, bb)]);
         }
     }
-    publish_partial<NB, true>(g, s, lds, cd.parts + static_cast<size_t>(local) * s * s);
+    publish_partial<NB, true>(g, s, lds, glb(cd.parts) + static_cast<size_t>(local) * s * s);
 }
 
 // D += P M1 ;  P = W M3 + P M4   (matrix cores, storage precision; Q = W M3)
@@ -722,7 +780,8 @@ __global__ __launch_bounds__(kThreads) void update_dqp_kernel(const ChipDev *__r
 {
     int local;
     const ChipDev &cd = chip_of(cds, tab, local);
-    if (cd.ctrl[kStop]) return;
+    const int wgs = cd.wgs;
+    if (glb(cd.ctrl)[kStop]) return;
     using V = typename MF<T>::V;
     constexpr bool kF64 = MF<T>::kF64;
     constexpr int KS = 4 * NB;
@@ -733,21 +792,24 @@ __global__ __launch_bounds__(kThreads) void update_dqp_kernel(const ChipDev *__r
     T *M3 = M1 + SP * MST;
     T *M4 = M3 + SP * MST;
     const bool f64 = sizeof(T) == 8;
-    stage_small<T, SP, MST>(M1, f64 ? reinterpret_cast<const T *>(cd.sm.M1) : reinterpret_cast<const T *>(cd.sm.M1f), s,
-                            false);
-    stage_small<T, SP, MST>(M3, f64 ? reinterpret_cast<const T *>(cd.sm.M3) : reinterpret_cast<const T *>(cd.sm.M3f), s,
-                            false);
-    stage_small<T, SP, MST>(M4, f64 ? reinterpret_cast<const T *>(cd.sm.M4) : reinterpret_cast<const T *>(cd.sm.M4f), s,
-                            false);
+    {
+        T *const dst[3] = {M1, M3, M4};
+        const gptr<const T> src[3] = {
+            glb(f64 ? reinterpret_cast<const T *>(cd.sm.M1) : reinterpret_cast<const T *>(cd.sm.M1f)),
+            glb(f64 ? reinterpret_cast<const T *>(cd.sm.M3) : reinterpret_cast<const T *>(cd.sm.M3f)),
+            glb(f64 ? reinterpret_cast<const T *>(cd.sm.M4) : reinterpret_cast<const T *>(cd.sm.M4f))};
+        const bool neg[3] = {false, false, false};
+        stage_small<T, SP, MST, 3>(dst, src, s, neg);
+    }
     __syncthreads();
-    T *__restrict__ D = static_cast<T *>(cd.Dv);
-    T *__restrict__ P = static_cast<T *>(cd.P);
-    const T *__restrict__ W = static_cast<const T *>(cd.W);
+    const gptr<T> __restrict__ D = glb(static_cast<T *>(cd.Dv));
+    const gptr<T> __restrict__ P = glb(static_cast<T *>(cd.P));
+    const gptr<const T> __restrict__ W = glb(static_cast<const T *>(cd.W));
     const int64_t ldw = cd.ldw;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int64_t ntiles = ldw / kTileRows;
-    for (int64_t tile = local; tile < ntiles; tile += cd.wgs) {
+    for (int64_t tile = local; tile < ntiles; tile += wgs) {
         for (int rb = 0; rb < 4; ++rb) {
             const int64_t r0 = tile * kTileRows + wave * 64 + rb * 16;
             T pa[KS], wa[KS];
@@ -757,34 +819,31 @@ __global__ __launch_bounds__(kThreads) void update_dqp_kernel(const ChipDev *__r
                 pa[t] = col < s ? P[col * ldw + r0 + li] : T(0);
                 wa[t] = col < s ? W[col * ldw + r0 + li] : T(0);
             }
-            V ad[NB], ap[NB];
+            // pa holds this wave's rows of every column of P, so the new rows
+            // can be written column block by column block
 #pragma unroll
             for (int jb = 0; jb < NB; ++jb) {
                 const int colj = jb * 16 + li;
+                V ad, ap;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    ad[jb][r] = colj < s ? D[colj * ldw + r0 + mfma_row<kF64>(lg, r)] : T(0);
-                    ap[jb][r] = T(0);
+                    ad[r] = colj < s ? D[colj * ldw + r0 + mfma_row<kF64>(lg, r)] : T(0);
+                    ap[r] = T(0);
                 }
 #pragma unroll
                 for (int t = 0; t < KS; ++t) {
                     const int k = 4 * t + lg;
-                    ad[jb] = MF<T>::mma(pa[t], M1[k * MST + colj], ad[jb]);
-                    ap[jb] = MF<T>::mma(wa[t], M3[k * MST + colj], ap[jb]);
+                    ad = MF<T>::mma(pa[t], M1[k * MST + colj], ad);
+                    ap = MF<T>::mma(wa[t], M3[k * MST + colj], ap);
                 }
 #pragma unroll
-                for (int t = 0; t < KS; ++t) ap[jb] = MF<T>::mma(pa[t], M4[(4 * t + lg) * MST + colj], ap[jb]);
-            }
-            // every lane has read its rows of P: write the new blocks
-#pragma unroll
-            for (int jb = 0; jb < NB; ++jb) {
-                const int colj = jb * 16 + li;
+                for (int t = 0; t < KS; ++t) ap = MF<T>::mma(pa[t], M4[(4 * t + lg) * MST + colj], ap);
                 if (colj < s) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int64_t idx = colj * ldw + r0 + mfma_row<kF64>(lg, r);
-                        D[idx] = ad[jb][r];
-                        P[idx] = ap[jb][r];
+                        D[idx] = ad[r];
+                        P[idx] = ap[r];
                     }
                 }
             }
@@ -800,11 +859,12 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const ChipDev *__res
 {
     int local;
     const ChipDev &cd = chip_of(cds, tab, local);
+    const int wgs = cd.wgs;
     if (!cd.ctrl[kActive]) return;
     const int nx = cd.nx, ny = cd.ny, nz = cd.nz;
     const int64_t n = cd.n, ldw = cd.ldw, plane = static_cast<int64_t>(nx) * ny;
     const int64_t ntiles = ldw / kTileRows;
-    for (int64_t tile = local; tile < ntiles; tile += cd.wgs) {
+    for (int64_t tile = local; tile < ntiles; tile += wgs) {
         const int64_t a = tile * kTileRows + threadIdx.x;
         if (a >= n) {
             for (int c = 0; c < s; ++c) cd.R64[c * ldw + a] = 0.0;
@@ -836,6 +896,7 @@ __global__ __launch_bounds__(kThreads) void colsq_kernel(const ChipDev *__restri
 {
     int local;
     const ChipDev &cd = chip_of(cds, tab, local);
+    const int wgs = cd.wgs;
     if (which == 1 && !cd.ctrl[kActive]) return;
     __shared__ double sh[kThreads / 64][kMaxS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -844,7 +905,7 @@ __global__ __launch_bounds__(kThreads) void colsq_kernel(const ChipDev *__restri
     const int64_t ntiles = cd.ldw / kTileRows;
     for (int c = 0; c < s; ++c) {
         double acc = 0.0;
-        for (int64_t tile = local; tile < ntiles; tile += cd.wgs) {
+        for (int64_t tile = local; tile < ntiles; tile += wgs) {
             const int64_t a = tile * kTileRows + threadIdx.x;
             if (a < cd.n) {
                 const double v = src[c * ld + a];
@@ -884,10 +945,11 @@ __global__ __launch_bounds__(kThreads) void inner_start_kernel(const ChipDev *__
 {
     int local;
     const ChipDev &cd = chip_of(cds, tab, local);
+    const int wgs = cd.wgs;
     if (!cd.ctrl[kActive]) return;
     const int64_t ldw = cd.ldw, ntiles = ldw / kTileRows;
     T *W = static_cast<T *>(cd.W), *D = static_cast<T *>(cd.Dv), *P = static_cast<T *>(cd.P), *AP = static_cast<T *>(cd.AP);
-    for (int64_t tile = local; tile < ntiles; tile += cd.wgs) {
+    for (int64_t tile = local; tile < ntiles; tile += wgs) {
         const int64_t a = tile * kTileRows + threadIdx.x;
         for (int c = 0; c < s; ++c) {
             const int64_t e = c * ldw + a;
@@ -912,8 +974,9 @@ __global__ __launch_bounds__(kThreads) void start_x_kernel(const ChipDev *__rest
 {
     int local;
     const ChipDev &cd = chip_of(cds, tab, local);
+    const int wgs = cd.wgs;
     const int64_t ntiles = cd.ldw / kTileRows;
-    for (int64_t tile = local; tile < ntiles; tile += cd.wgs) {
+    for (int64_t tile = local; tile < ntiles; tile += wgs) {
         const int64_t a = tile * kTileRows + threadIdx.x;
         if (a >= cd.n) continue;
         for (int c = 0; c < s; ++c) cd.X[c * cd.ldx + a] = cd.X0 ? cd.X0[c * cd.ldx0 + a] : 0.0;
@@ -927,10 +990,11 @@ __global__ __launch_bounds__(kThreads) void add_out_kernel(const ChipDev *__rest
 {
     int local;
     const ChipDev &cd = chip_of(cds, tab, local);
+    const int wgs = cd.wgs;
     if (!cd.ctrl[kActive]) return;
     const T *D = static_cast<const T *>(cd.Dv);
     const int64_t ntiles = cd.ldw / kTileRows;
-    for (int64_t tile = local; tile < ntiles; tile += cd.wgs) {
+    for (int64_t tile = local; tile < ntiles; tile += wgs) {
         const int64_t a = tile * kTileRows + threadIdx.x;
         if (a >= cd.n) continue;
         for (int c = 0; c < s; ++c) cd.X[c * cd.ldx + a] += static_cast<double>(D[c * cd.ldw + a]);
