@@ -266,6 +266,86 @@ bko_status bko_apply_operator(bko_op A, int m, const void *T, int ldt, bko_dtype
 bko_status bko_residual(bko_op A, int m, const double *B, int ldb, const double *X, int ldx,
                         double *R, int ldr, void *stream);
 
+/* ------------------------------------------------ learned initial guess */
+
+/*
+ * A 4-level convolutional encoder-decoder that predicts the basis solutions
+ * of a chip from its power maps, conductivity and film coefficient; its
+ * output is the X0 argument of the block solve (Sec. III-A starts the block
+ * iteration from any initial block; zero start is the fallback).  Not part
+ * of the paper.  Tensors are FP32, layout (N, C, H, W), device memory.
+ *
+ * Layers (3 x 3 "same" convolutions, bias, ReLU, except the last):
+ *   0,1 Cin->w1->w1 at H | 2,3 pool: w1->w2->w2 at H/2 | 4,5 pool: w2->w3->w3
+ *   at H/4 | 6,7 pool: w3->w4->w4 at H/8 | 8,9 [up(7), out 5]: w4+w3->w3->w3
+ *   | 10,11 [up(9), out 3]: w3+w2->w2->w2 | 12,13 [up(11), out 1]:
+ *   w2+w1->w1->w1 | 14 1 x 1 w1->Cout, no ReLU;
+ * w1 = base, w2 = 2 base, w3 = w4 = 4 base; pool = 2 x 2 average, up =
+ * nearest 2x, [a, b] = channel concatenation.  Flat parameters: per layer in
+ * this order, filter (Cout, Cin, K, K) row-major then bias (Cout).
+ *
+ * State buffer (caller-owned, 256-byte aligned, bko_unet_sizes bytes):
+ * FP32 parameters [nparams], FP32 gradients [nparams], Adam first and
+ * second moments [nparams each], then the BF16 copy of the parameters that
+ * every convolution reads (FP32 accumulation).  The workspace holds the
+ * activations of up to max_batch samples.
+ */
+typedef struct bko_unet *bko_net;
+
+bko_status bko_unet_create(int cin, int cout, int base, int height, int width, int max_batch, bko_net *out);
+bko_status bko_unet_destroy(bko_net net);
+bko_status bko_unet_sizes(bko_net net, int64_t *nparams, size_t *state_bytes, size_t *work_bytes);
+
+/* Load FP32 parameters (device, nparams), clear the Adam state and step count. */
+bko_status bko_unet_set_params(bko_net net, void *state, const float *params, void *stream);
+
+/* y (n, Cout, H, W) = network(x (n, Cin, H, W)), 1 <= n <= max_batch. Asynchronous. */
+bko_status bko_unet_forward(bko_net net, void *state, void *work, const float *x, int n, float *y, void *stream);
+
+/*
+ * Forward pass, loss = mean over all n Cout H W outputs of (y - target)^2,
+ * and its gradient with respect to every parameter into the state's gradient
+ * block.  loss (host, may be NULL) receives the loss and then the call
+ * synchronises the stream; with NULL it is asynchronous.
+ */
+bko_status bko_unet_gradient(bko_net net, void *state, void *work, const float *x, const float *target, int n,
+                             float *loss, void *stream);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected) on the state's
+ * gradients; refreshes the BF16 copy.  Asynchronous. */
+bko_status bko_unet_adam_step(bko_net net, void *state, float lr, void *stream);
+
+/*
+ * Building blocks, exposed for tests: one convolution (mode 0 reads A (N,
+ * Ca, H, W); mode 1 the 2 x 2 average of A (N, Ca, 2H, 2W); mode 2 the
+ * concatenation of A (N, Ca, H/2, W/2) upsampled and B (N, Cb, H, W)), with
+ * BF16 filters wgt (Co, Ca + Cb, K, K), or with transposed != 0 the flipped,
+ * transposed filters of a layer (Ca + Cb, Co, K, K) (the input gradient);
+ * bias may be NULL.  And the filter / bias gradient of such a convolution
+ * for output gradient g (N, Co, H, W) into gw (Co, Ca + Cb, K, K) and gb
+ * (Co), with a work buffer of bko_nn_wgrad_work_floats floats.
+ */
+bko_status bko_nn_conv2d(const float *A, int Ca, const float *B, int Cb, int mode, int N, int H, int W, int Co, int K,
+                         const uint16_t *wgt, int transposed, const float *bias, float *out, int relu, void *stream);
+size_t bko_nn_wgrad_work_floats(int N, int H, int W, int Ci, int Co, int K);
+bko_status bko_nn_conv2d_wgrad(const float *A, int Ca, const float *B, int Cb, int mode, const float *g, int N, int H,
+                               int W, int Co, int K, float *work, float *gw, float *gb, void *stream);
+
+/*
+ * Network input of m fields of one chip: channels [0, nz) = F[:, j] /
+ * ||F[:, j]|| as nz planes of ny x nx (the field layout itself), [nz, 2 nz) =
+ * (log k - kmu) / ksig per layer, 2 nz = hval everywhere; scale[j] =
+ * ||F[:, j]|| (FP64).  x is (m, 2 nz + 1, ny, nx).
+ */
+bko_status bko_lstart_pack(int nx, int ny, int nz, const double *F, int ldf, int m, const double *k_cell, float kmu,
+                           float ksig, float hval, double *scale, float *x, void *stream);
+/* Training target t (m, n) = T[:, j] / (scale[j] gain). */
+bko_status bko_lstart_pack_target(int n, const double *T, int ldt, int m, const double *scale, double gain, float *t,
+                                  void *stream);
+/* X0[:, j] = y (m, n)[j] * scale[j] * gain (FP64 initial guess). */
+bko_status bko_lstart_unpack(int n, const float *y, int m, const double *scale, double gain, double *X0, int ldx,
+                             void *stream);
+
 /* ---------------------------------------------------- kernel timing hooks */
 
 /*

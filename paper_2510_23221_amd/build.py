@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libblockoa.so")
-SOURCES = ["capi.hip", "stencil.hip", "combine.hip", "blockcg.hip", "cg.hip"]
+SOURCES = ["capi.hip", "stencil.hip", "combine.hip", "blockcg.hip", "cg.hip", "nn.hip"]
 ARCH = "gfx950"
 
 

@@ -35,7 +35,10 @@ EXPORTED = ("bko_version", "bko_last_error", "bko_operator_bytes", "bko_assemble
             "bko_block_krylov_solve", "bko_combine", "bko_apply_operator", "bko_residual",
             "bko_timing_enable", "bko_timing_query", "bko_timing_reset", "bko_cg_workspace_bytes",
             "bko_cg_solve", "bko_batch_plan_create", "bko_batch_plan_destroy", "bko_batch_workspace_bytes",
-            "bko_batch_tune", "bko_batch_solve")
+            "bko_batch_tune", "bko_batch_solve", "bko_nn_conv2d", "bko_nn_wgrad_work_floats",
+            "bko_nn_conv2d_wgrad", "bko_unet_create", "bko_unet_destroy", "bko_unet_sizes", "bko_unet_set_params",
+            "bko_unet_forward", "bko_unet_gradient", "bko_unet_adam_step", "bko_lstart_pack",
+            "bko_lstart_pack_target", "bko_lstart_unpack")
 
 
 class BlockoaError(RuntimeError):
@@ -85,6 +88,20 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bko_cg_workspace_bytes": (i32, [vp, i32, ctypes.POINTER(sz)]),
         "bko_batch_plan_create": (i32, [i32, ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp)]),
         "bko_batch_plan_destroy": (i32, [vp]),
+        "bko_nn_conv2d": (i32, [vp, i32, vp, i32, i32, i32, i32, i32, i32, i32, vp, i32, vp, vp, i32, vp]),
+        "bko_nn_wgrad_work_floats": (sz, [i32, i32, i32, i32, i32, i32]),
+        "bko_nn_conv2d_wgrad": (i32, [vp, i32, vp, i32, i32, vp, i32, i32, i32, i32, i32, vp, vp, vp, vp]),
+        "bko_unet_create": (i32, [i32, i32, i32, i32, i32, i32, ctypes.POINTER(vp)]),
+        "bko_unet_destroy": (i32, [vp]),
+        "bko_unet_sizes": (i32, [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(sz), ctypes.POINTER(sz)]),
+        "bko_unet_set_params": (i32, [vp, vp, vp, vp]),
+        "bko_unet_forward": (i32, [vp, vp, vp, vp, i32, vp, vp]),
+        "bko_unet_gradient": (i32, [vp, vp, vp, vp, vp, i32, ctypes.POINTER(ctypes.c_float), vp]),
+        "bko_unet_adam_step": (i32, [vp, vp, ctypes.c_float, vp]),
+        "bko_lstart_pack": (i32, [i32, i32, i32, vp, i32, i32, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                  vp, vp, vp]),
+        "bko_lstart_pack_target": (i32, [i32, vp, i32, i32, vp, dbl, vp, vp]),
+        "bko_lstart_unpack": (i32, [i32, vp, i32, vp, dbl, vp, i32, vp]),
         "bko_batch_workspace_bytes": (i32, [vp, ctypes.POINTER(sz)]),
         "bko_batch_tune": (i32, [vp, vp, sz, ctypes.POINTER(i32), vp]),
         "bko_batch_solve": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(vp),
@@ -326,6 +343,153 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def _f32(t, name):
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 tensor on the GPU")
+    return _ptr(t)
+
+
+def nn_conv2d(A, w_bf16, bias=None, B=None, mode=0, relu=False, transposed=False, out_channels=None):
+    """One convolution of the learned-start network (see include/blockoa.h).
+    A: (N, Ca, h, w) with (h, w) = (H, W), (2H, 2W) or (H/2, W/2) for modes 0,
+    1, 2; B: (N, Cb, H, W) for mode 2.  w_bf16: int16 tensor of BF16 bits."""
+    N, Ca = A.shape[0], A.shape[1]
+    if mode == 0:
+        H, W = A.shape[2], A.shape[3]
+    elif mode == 1:
+        H, W = A.shape[2] // 2, A.shape[3] // 2
+    else:
+        H, W = B.shape[2], B.shape[3]
+    Cb = 0 if B is None else B.shape[1]
+    K = w_bf16.shape[-1]
+    Co = out_channels if out_channels is not None else (w_bf16.shape[1] if transposed else w_bf16.shape[0])
+    out = torch.empty((N, Co, H, W), dtype=torch.float32, device=A.device)
+    _check(load_library().bko_nn_conv2d(_f32(A, "A"), Ca, None if B is None else _f32(B, "B"), Cb, mode, N, H, W, Co,
+                                        K, _ptr(w_bf16), int(transposed), None if bias is None else _f32(bias, "bias"),
+                                        _ptr(out), int(relu), _stream()))
+    return out
+
+
+def nn_conv2d_wgrad(A, g, K, B=None, mode=0):
+    """Filter and bias gradients of nn_conv2d for output gradient g (N, Co, H, W)."""
+    N, Co, H, W = g.shape
+    Ca = A.shape[1]
+    Cb = 0 if B is None else B.shape[1]
+    lib = load_library()
+    nw = lib.bko_nn_wgrad_work_floats(N, H, W, Ca + Cb, Co, K)
+    work = torch.empty(max(nw, 1), dtype=torch.float32, device=A.device)
+    gw = torch.empty((Co, Ca + Cb, K, K), dtype=torch.float32, device=A.device)
+    gb = torch.empty(Co, dtype=torch.float32, device=A.device)
+    _check(lib.bko_nn_conv2d_wgrad(_f32(A, "A"), Ca, None if B is None else _f32(B, "B"), Cb, mode, _f32(g, "g"), N, H,
+                                   W, Co, K, _ptr(work), _ptr(gw), _ptr(gb), _stream()))
+    return gw, gb
+
+
+def to_bf16_bits(t: torch.Tensor) -> torch.Tensor:
+    """float32 tensor -> int16 tensor of its BF16 bits (round to nearest even)."""
+    return t.to(torch.bfloat16).view(torch.int16)
+
+
+class UNet:
+    """The learned-start encoder-decoder (layer table in include/blockoa.h);
+    parameters, gradients and Adam state live in one device buffer."""
+
+    def __init__(self, cin: int, cout: int, base: int, height: int, width: int, max_batch: int, device="cuda"):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.bko_unet_create(cin, cout, base, height, width, max_batch, ctypes.byref(h)))
+        self.handle = h
+        self.cin, self.cout, self.base, self.height, self.width, self.max_batch = cin, cout, base, height, width, max_batch
+        npar, sb, wb = ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib.bko_unet_sizes(h, ctypes.byref(npar), ctypes.byref(sb), ctypes.byref(wb)))
+        self.nparams = npar.value
+        self._state, self._state_ptr = _aligned_workspace(sb.value, device)
+        self._work, self._work_ptr = _aligned_workspace(wb.value, device)
+
+    def _view(self, k):
+        off = self._state_ptr - self._state.data_ptr()
+        return self._state[off + 4 * k * self.nparams: off + 4 * (k + 1) * self.nparams].view(torch.float32)
+
+    @property
+    def params(self) -> torch.Tensor:
+        return self._view(0)
+
+    @property
+    def grads(self) -> torch.Tensor:
+        return self._view(1)
+
+    def set_params(self, p: torch.Tensor):
+        p = p.to(device=self._state.device, dtype=torch.float32).contiguous()
+        if p.numel() != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters")
+        _check(load_library().bko_unet_set_params(self.handle, ctypes.c_void_p(self._state_ptr), _ptr(p), _stream()))
+        torch.cuda.current_stream().synchronize()
+
+    def forward(self, x: torch.Tensor, y: Optional[torch.Tensor] = None) -> torch.Tensor:
+        n = x.shape[0]
+        if y is None:
+            y = torch.empty((n, self.cout, self.height, self.width), dtype=torch.float32, device=x.device)
+        _check(load_library().bko_unet_forward(self.handle, ctypes.c_void_p(self._state_ptr),
+                                               ctypes.c_void_p(self._work_ptr), _f32(x, "x"), n, _f32(y, "y"),
+                                               _stream()))
+        return y
+
+    def gradient(self, x: torch.Tensor, target: torch.Tensor, want_loss: bool = True):
+        loss = ctypes.c_float()
+        _check(load_library().bko_unet_gradient(self.handle, ctypes.c_void_p(self._state_ptr),
+                                                ctypes.c_void_p(self._work_ptr), _f32(x, "x"), _f32(target, "target"),
+                                                x.shape[0], ctypes.byref(loss) if want_loss else None, _stream()))
+        return loss.value if want_loss else None
+
+    def adam_step(self, lr: float):
+        _check(load_library().bko_unet_adam_step(self.handle, ctypes.c_void_p(self._state_ptr), lr, _stream()))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load_library().bko_unet_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lstart_pack(chip_dims, F: torch.Tensor, k_cell: torch.Tensor, kmu: float, ksig: float, hval: float):
+    """Network input of the fields F ((m, N) FP64, one field per row) of one
+    chip.  Returns (x (m, 2 nz + 1, ny, nx) float32, scale (m,) float64)."""
+    nx, ny, nz = chip_dims
+    m = F.shape[0]
+    fp, ldf, ft = _block(F, "F")
+    if ft != F64:
+        raise ValueError("F must be float64")
+    x = torch.empty((m, 2 * nz + 1, ny, nx), dtype=torch.float32, device=F.device)
+    scale = torch.empty(m, dtype=torch.float64, device=F.device)
+    k = k_cell.to(dtype=torch.float64).contiguous()
+    _check(load_library().bko_lstart_pack(nx, ny, nz, fp, ldf, m, _ptr(k), kmu, ksig, hval, _ptr(scale), _ptr(x),
+                                          _stream()))
+    return x, scale
+
+
+def lstart_pack_target(T: torch.Tensor, scale: torch.Tensor, gain: float) -> torch.Tensor:
+    m, n = T.shape
+    tp, ldt, tt = _block(T, "T")
+    t = torch.empty((m, n), dtype=torch.float32, device=T.device)
+    _check(load_library().bko_lstart_pack_target(n, tp, ldt, m, _ptr(scale), gain, _ptr(t), _stream()))
+    return t
+
+
+def lstart_unpack(y: torch.Tensor, scale: torch.Tensor, gain: float, X0: Optional[torch.Tensor] = None):
+    m = y.shape[0]
+    n = y[0].numel()
+    if X0 is None:
+        X0 = torch.empty((m, n), dtype=torch.float64, device=y.device)
+    xp, ldx, _ = _block(X0, "X0")
+    _check(load_library().bko_lstart_unpack(n, _f32(y, "y"), m, _ptr(scale), gain, xp, ldx, _stream()))
+    return X0
 
 
 def cg_workspace_bytes(A: HeatOperator, m: int) -> int:

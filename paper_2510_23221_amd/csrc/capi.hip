@@ -543,6 +543,145 @@ bko_status bko_batch_solve(bko_batch plan, const double *const *B, const int *ld
     BKO_GUARD_END
 }
 
+// ------------------------------------------------------------------ learned start
+
+bko_status bko_nn_conv2d(const float *A, int Ca, const float *B, int Cb, int mode, int N, int H, int W, int Co, int K,
+                         const uint16_t *wgt, int transposed, const float *bias, float *out, int relu, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(A && wgt && out, "NULL array");
+    BKO_CHECK(N >= 1 && H >= 1 && W >= 1 && Ca >= 1 && Co >= 1, "bad sizes");
+    BKO_CHECK(K == 1 || K == 3, "K must be 1 or 3");
+    BKO_CHECK(mode >= 0 && mode <= 2, "mode must be 0, 1 or 2");
+    BKO_CHECK(mode == 2 ? (B != nullptr && Cb >= 1 && H % 2 == 0 && W % 2 == 0) : Cb == 0, "bad concatenation input");
+    return nn_conv(A, Ca, B, Cb, mode, N, H, W, Co, K, wgt, transposed, bias, out, relu,
+                   static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+size_t bko_nn_wgrad_work_floats(int N, int H, int W, int Ci, int Co, int K)
+{
+    if (N < 1 || H < 1 || W < 1 || Ci < 1 || Co < 1 || (K != 1 && K != 3)) return 0;
+    return nn_wgrad_part_floats(N, H, W, Ci, Co, K);
+}
+
+bko_status bko_nn_conv2d_wgrad(const float *A, int Ca, const float *B, int Cb, int mode, const float *g, int N, int H,
+                               int W, int Co, int K, float *work, float *gw, float *gb, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(A && g && work && gw && gb, "NULL array");
+    BKO_CHECK(N >= 1 && H >= 1 && W >= 1 && Ca >= 1 && Co >= 1, "bad sizes");
+    BKO_CHECK(K == 1 || K == 3, "K must be 1 or 3");
+    BKO_CHECK(mode >= 0 && mode <= 2, "mode must be 0, 1 or 2");
+    BKO_CHECK(mode == 2 ? (B != nullptr && Cb >= 1 && H % 2 == 0 && W % 2 == 0) : Cb == 0, "bad concatenation input");
+    return nn_wgrad(A, Ca, B, Cb, mode, g, N, H, W, Co, K, work, gw, gb, static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+bko_status bko_unet_create(int cin, int cout, int base, int height, int width, int max_batch, bko_net *out)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(out != nullptr, "NULL argument");
+    *out = nullptr;
+    BKO_CHECK(cin >= 1 && cout >= 1 && base >= 1 && max_batch >= 1, "bad sizes");
+    BKO_CHECK(height >= 8 && width >= 8 && height % 8 == 0 && width % 8 == 0,
+              "height and width must be positive multiples of 8 (three 2x poolings)");
+    *out = reinterpret_cast<bko_net>(new UNet(cin, cout, base, height, width, max_batch));
+    return BKO_OK;
+    BKO_GUARD_END
+}
+
+bko_status bko_unet_destroy(bko_net net)
+{
+    delete reinterpret_cast<UNet *>(net);
+    return BKO_OK;
+}
+
+bko_status bko_unet_sizes(bko_net net, int64_t *nparams, size_t *state_bytes, size_t *work_bytes)
+{
+    BKO_CHECK(net != nullptr, "NULL network");
+    const UNet &u = *reinterpret_cast<UNet *>(net);
+    if (nparams) *nparams = u.nparams;
+    if (state_bytes) *state_bytes = u.state_bytes();
+    if (work_bytes) *work_bytes = u.work_floats * sizeof(float);
+    return BKO_OK;
+}
+
+bko_status bko_unet_set_params(bko_net net, void *state, const float *params, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(net && state && params, "NULL argument");
+    BKO_CHECK(reinterpret_cast<uintptr_t>(state) % 256 == 0, "state must be 256-byte aligned");
+    return reinterpret_cast<UNet *>(net)->set_params(state, params, static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+bko_status bko_unet_forward(bko_net net, void *state, void *work, const float *x, int n, float *y, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(net && state && work && x && y, "NULL argument");
+    const UNet &u = *reinterpret_cast<UNet *>(net);
+    BKO_CHECK(n >= 1 && n <= u.batch, "n = %d outside [1, %d]", n, u.batch);
+    BKO_CHECK(reinterpret_cast<uintptr_t>(state) % 256 == 0 && reinterpret_cast<uintptr_t>(work) % 256 == 0,
+              "state and work must be 256-byte aligned");
+    return u.forward(state, work, x, n, y, static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+bko_status bko_unet_gradient(bko_net net, void *state, void *work, const float *x, const float *target, int n,
+                             float *loss, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(net && state && work && x && target, "NULL argument");
+    const UNet &u = *reinterpret_cast<UNet *>(net);
+    BKO_CHECK(n >= 1 && n <= u.batch, "n = %d outside [1, %d]", n, u.batch);
+    BKO_CHECK(reinterpret_cast<uintptr_t>(state) % 256 == 0 && reinterpret_cast<uintptr_t>(work) % 256 == 0,
+              "state and work must be 256-byte aligned");
+    return u.gradient(state, work, x, target, n, loss, static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+bko_status bko_unet_adam_step(bko_net net, void *state, float lr, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(net && state, "NULL argument");
+    BKO_CHECK(lr > 0.0f && std::isfinite(lr), "lr must be positive");
+    return reinterpret_cast<UNet *>(net)->adam(state, lr, static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+bko_status bko_lstart_pack(int nx, int ny, int nz, const double *F, int ldf, int m, const double *k_cell, float kmu,
+                           float ksig, float hval, double *scale, float *x, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(F && k_cell && scale && x, "NULL argument");
+    BKO_CHECK(nx >= 1 && ny >= 1 && nz >= 1 && m >= 1, "bad sizes");
+    BKO_CHECK(static_cast<int64_t>(ldf) >= static_cast<int64_t>(nx) * ny * nz, "ldf must be >= n");
+    BKO_CHECK(ksig > 0.0f, "ksig must be positive");
+    return lstart_pack(nx, ny, nz, F, ldf, m, k_cell, kmu, ksig, hval, scale, x, static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+bko_status bko_lstart_pack_target(int n, const double *T, int ldt, int m, const double *scale, double gain, float *t,
+                                  void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(T && scale && t, "NULL argument");
+    BKO_CHECK(n >= 1 && m >= 1 && ldt >= n && gain > 0.0, "bad sizes");
+    return lstart_pack_target(n, T, ldt, m, scale, gain, t, static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+bko_status bko_lstart_unpack(int n, const float *y, int m, const double *scale, double gain, double *X0, int ldx,
+                             void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(y && scale && X0, "NULL argument");
+    BKO_CHECK(n >= 1 && m >= 1 && ldx >= n && gain > 0.0, "bad sizes");
+    return lstart_unpack(n, y, m, scale, gain, X0, ldx, static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
 bko_status bko_timing_enable(int enable)
 {
     TimingState &t = timing();

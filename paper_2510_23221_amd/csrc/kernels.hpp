@@ -61,6 +61,56 @@ bko_status batch_solve(BatchPlan &p, const double *const *B, const int64_t *ldb,
                        const int64_t *ldx, const double *const *X0, const int64_t *ldx0, double tol,
                        int max_iter, void *work, bko_solve_info *infos, hipStream_t stream);
 
+// ---- learned start (convolutional encoder-decoder)
+bko_status nn_conv(const float *A, int Ca, const float *B, int Cb, int mode, int N, int H, int W, int Co, int K,
+                   const uint16_t *wgt, int transposed, const float *bias, float *out, int relu, hipStream_t st);
+size_t nn_wgrad_part_floats(int N, int H, int W, int Ci, int Co, int K);
+bko_status nn_wgrad(const float *A, int Ca, const float *B, int Cb, int mode, const float *g, int N, int H, int W,
+                    int Co, int K, float *part, float *gw, float *gb, hipStream_t st);
+bko_status nn_relu_bwd(float *g, const float *y, int64_t n, hipStream_t st);
+bko_status nn_pool_bwd(const float *g, int NC, int H, int W, const float *add, float *gA, hipStream_t st);
+bko_status nn_upcat_bwd(const float *g, int N, int Ca, int Cb, int H, int W, float *gA, float *gB, hipStream_t st);
+int nn_mse_blocks(int64_t n);
+bko_status nn_mse(const float *pred, const float *target, int64_t n, float *grad, float *lpart, hipStream_t st);
+bko_status nn_adam(float *p, const float *g, float *m, float *v, uint16_t *pb, int64_t n, float lr, int t,
+                   hipStream_t st);
+bko_status nn_to_bf16(const float *p, uint16_t *pb, int64_t n, hipStream_t st);
+bko_status lstart_pack(int nx, int ny, int nz, const double *F, int64_t ldf, int m, const double *kc, float kmu,
+                       float ksig, float hval, double *scale, float *x, hipStream_t st);
+bko_status lstart_pack_target(int64_t n, const double *T, int64_t ldt, int m, const double *scale, double gain,
+                              float *t, hipStream_t st);
+bko_status lstart_unpack(int64_t n, const float *y, int m, const double *scale, double gain, double *X0, int64_t ldx,
+                         hipStream_t st);
+
+// The 4-level encoder-decoder (layer table in nn.hip).  Host metadata; the
+// caller owns the state buffer (parameters, gradients, Adam moments, BF16
+// copy) and the activation workspace.
+struct UNet {
+    struct Layer {
+        int ci, co, k, relu, h, w;
+        int64_t woff, boff;
+        size_t act, grad;  // workspace offsets (floats)
+    };
+    struct State {
+        float *params, *grads, *m, *v;
+        uint16_t *pb;
+    };
+    int cin, cout, base, H, W, batch;
+    Layer L[15];
+    int64_t nparams = 0;
+    size_t scratch_off = 0, skip_off[3] = {0, 0, 0}, part_off = 0, lpart_off = 0, work_floats = 0;
+    int step = 0;
+
+    UNet(int cin, int cout, int base, int H, int W, int batch);
+    size_t state_bytes() const;
+    State state(void *p) const;
+    bko_status set_params(void *state, const float *params, hipStream_t st);
+    bko_status forward(void *state, void *work, const float *x, int n, float *y, hipStream_t st) const;
+    bko_status gradient(void *state, void *work, const float *x, const float *target, int n, float *loss,
+                        hipStream_t st) const;
+    bko_status adam(void *state, float lr, hipStream_t st);
+};
+
 size_t cg_workspace_bytes(int64_t n, int m);
 
 bko_status cg_solve(const Operator &op, int m, const double *B, int64_t ldb, double *X, int64_t ldx, double tol,
