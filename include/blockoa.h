@@ -71,6 +71,7 @@ typedef struct {
     int deflated;       /* search directions dropped as linearly dependent   */
     int status;         /* bko_status of the solve                           */
     double max_rel_res; /* max_j ||b_j - A x_j||_2 / ||b_j||_2, FP64, at exit */
+    int x0_rejected;    /* initial-guess columns replaced by zero (fallback)  */
 } bko_solve_info;
 
 /* ------------------------------------------------------------------ build */
@@ -149,7 +150,9 @@ bko_status bko_block_krylov_workspace_bytes(bko_op A, int s, bko_dtype compute, 
  *                       iterative refinement).
  *   B (n x s, ldb >= n) FP64 device, X (n x s, ldx >= n) FP64 device output.
  *   X0 (ldx0 >= n) optional FP64 initial guess (e.g. a learned start); NULL
- *   means X0 = 0.  X0 may alias X (ldx0 == ldx).
+ *   means X0 = 0.  X0 may alias X (ldx0 == ldx).  A column whose initial
+ *   residual is larger than ||b_j|| (a start worse than zero) or not finite
+ *   falls back to the zero start; info->x0_rejected counts such columns.
  *   tol > 0, max_iter >= 1 caps the total inner iterations.
  *   work / work_bytes: caller workspace (bko_block_krylov_workspace_bytes),
  *   256-byte aligned, contents need not be initialised.
@@ -333,12 +336,22 @@ bko_status bko_nn_conv2d_wgrad(const float *A, int Ca, const float *B, int Cb, i
 
 /*
  * Network input of m fields of one chip: channels [0, nz) = F[:, j] /
- * ||F[:, j]|| as nz planes of ny x nx (the field layout itself), [nz, 2 nz) =
+ * scale[j] as nz planes of ny x nx (the field layout itself), [nz, 2 nz) =
  * (log k - kmu) / ksig per layer, 2 nz = hval everywhere; scale[j] =
- * ||F[:, j]|| (FP64).  x is (m, 2 nz + 1, ny, nx).
+ * ||F[:, j]||_2 / sqrt(n), the RMS value (FP64; 0 gives zero planes).  x is
+ * (m, 2 nz + 1, ny, nx).
  */
 bko_status bko_lstart_pack(int nx, int ny, int nz, const double *F, int ldf, int m, const double *k_cell, float kmu,
                            float ksig, float hval, double *scale, float *x, void *stream);
+/*
+ * sweeps damped Jacobi sweeps X <- X + omega (B - A X) / diag(A) (FP64, m
+ * columns, 0 < omega < 2): damps the high-frequency error of an initial
+ * guess (a learned X0 is accurate in its smooth part, and the block solve
+ * converges on the rest).  work: n x m FP64 scratch (ldw >= n).  Asynchronous.
+ */
+bko_status bko_jacobi_smooth(bko_op A, int m, const double *B, int ldb, double *X, int ldx, double *work, int ldw,
+                             int sweeps, double omega, void *stream);
+
 /* Training target t (m, n) = T[:, j] / (scale[j] gain). */
 bko_status bko_lstart_pack_target(int n, const double *T, int ldt, int m, const double *scale, double gain, float *t,
                                   void *stream);

@@ -38,7 +38,7 @@ EXPORTED = ("bko_version", "bko_last_error", "bko_operator_bytes", "bko_assemble
             "bko_batch_tune", "bko_batch_solve", "bko_nn_conv2d", "bko_nn_wgrad_work_floats",
             "bko_nn_conv2d_wgrad", "bko_unet_create", "bko_unet_destroy", "bko_unet_sizes", "bko_unet_set_params",
             "bko_unet_forward", "bko_unet_gradient", "bko_unet_adam_step", "bko_lstart_pack",
-            "bko_lstart_pack_target", "bko_lstart_unpack")
+            "bko_lstart_pack_target", "bko_lstart_unpack", "bko_jacobi_smooth")
 
 
 class BlockoaError(RuntimeError):
@@ -49,7 +49,7 @@ class BlockoaError(RuntimeError):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("refinements", ctypes.c_int), ("deflated", ctypes.c_int),
-                ("status", ctypes.c_int), ("max_rel_res", ctypes.c_double)]
+                ("status", ctypes.c_int), ("max_rel_res", ctypes.c_double), ("x0_rejected", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -102,6 +102,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                   vp, vp, vp]),
         "bko_lstart_pack_target": (i32, [i32, vp, i32, i32, vp, dbl, vp, vp]),
         "bko_lstart_unpack": (i32, [i32, vp, i32, vp, dbl, vp, i32, vp]),
+        "bko_jacobi_smooth": (i32, [vp, i32, vp, i32, vp, i32, vp, i32, i32, dbl, vp]),
         "bko_batch_workspace_bytes": (i32, [vp, ctypes.POINTER(sz)]),
         "bko_batch_tune": (i32, [vp, vp, sz, ctypes.POINTER(i32), vp]),
         "bko_batch_solve": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(vp),
@@ -480,6 +481,18 @@ def lstart_pack_target(T: torch.Tensor, scale: torch.Tensor, gain: float) -> tor
     t = torch.empty((m, n), dtype=torch.float32, device=T.device)
     _check(load_library().bko_lstart_pack_target(n, tp, ldt, m, _ptr(scale), gain, _ptr(t), _stream()))
     return t
+
+
+def jacobi_smooth(A: HeatOperator, B: torch.Tensor, X: torch.Tensor, sweeps: int, omega: float = 0.6,
+                  stream=None) -> torch.Tensor:
+    """In-place damped Jacobi sweeps on X ((m, N) FP64) for right-hand sides B."""
+    m = B.shape[0]
+    bp, ldb, _ = _block(B, "B")
+    xp, ldx, _ = _block(X, "X")
+    work = torch.empty_like(X)
+    _check(load_library().bko_jacobi_smooth(A.handle, m, bp, ldb, xp, ldx, _ptr(work), X.shape[1], sweeps, omega,
+                                            _stream(stream)))
+    return X
 
 
 def lstart_unpack(y: torch.Tensor, scale: torch.Tensor, gain: float, X0: Optional[torch.Tensor] = None):

@@ -983,6 +983,24 @@ __global__ __launch_bounds__(kThreads) void start_x_kernel(const ChipDev *__rest
     }
 }
 
+// X[:, c] = 0 for the columns with mask[chip * kMaxS + c] != 0.
+__global__ __launch_bounds__(kThreads) void zero_cols_kernel(const ChipDev *__restrict__ cds,
+                                                             const uint16_t *__restrict__ tab, int s,
+                                                             const int *__restrict__ mask)
+{
+    int local;
+    const ChipDev &cd = chip_of(cds, tab, local);
+    const int wgs = cd.wgs;
+    const int *mk = mask + static_cast<size_t>(tab[blockIdx.x]) * kMaxS;
+    const int64_t ntiles = cd.ldw / kTileRows;
+    for (int64_t tile = local; tile < ntiles; tile += wgs) {
+        const int64_t a = tile * kTileRows + threadIdx.x;
+        if (a >= cd.n) continue;
+        for (int c = 0; c < s; ++c)
+            if (mk[c]) cd.X[c * cd.ldx + a] = 0.0;
+    }
+}
+
 // X (FP64) += D (type T) for active chips.
 template <class T>
 __global__ __launch_bounds__(kThreads) void add_out_kernel(const ChipDev *__restrict__ cds,
@@ -1017,7 +1035,7 @@ struct ChipHost {
 struct Layout {
     int nchips = 0, s = 0, total_wgs = 0, wg_cap = 0;
     bko_dtype compute = BKO_F64;
-    size_t off_cds = 0, off_tab = 0, off_th = 0, off_ctrl = 0, off_norms = 0, bytes = 0;
+    size_t off_cds = 0, off_tab = 0, off_th = 0, off_ctrl = 0, off_norms = 0, off_mask = 0, bytes = 0;
     std::vector<ChipHost> chips;
 };
 
@@ -1076,6 +1094,7 @@ Layout make_layout(const Operator *const *ops, int nchips, int s, bko_dtype comp
     L.off_th = take(sizeof(double) * kMaxS * nchips);
     L.off_ctrl = take(sizeof(int) * kCtrlInts * nchips);
     L.off_norms = take(sizeof(double) * kMaxS * nchips);
+    L.off_mask = take(sizeof(int) * kMaxS * nchips);
     for (int c = 0; c < nchips; ++c) L.chips[c].off = take(chip_region_bytes(L.chips[c].ldw, s, compute, nullptr));
     L.bytes = o;
     return L;
@@ -1349,6 +1368,39 @@ bko_status batch_solve_t(const Layout &L, void *work, const double *const *B, co
                 set_error("right-hand side column %d of chip %d is not finite", j, c);
                 return BKO_EINVAL;
             }
+    }
+    // fallback: a column of an initial guess whose residual is not smaller
+    // than the zero start's (||b_j - A x0_j|| > ||b_j||, or not finite) starts
+    // from zero instead
+    bool any_x0 = false;
+    for (int c = 0; c < nc; ++c) any_x0 = any_x0 || recs[c].X0 != nullptr;
+    if (any_x0) {
+        hipLaunchKernelGGL(residual_kernel, dim3(static_cast<unsigned>(L.total_wgs)), dim3(kThreads), 0, st, x.cds, x.tab,
+                           s);
+        BKO_HIP(hipGetLastError());
+        if ((rc = host_norms(x, 1)) != BKO_OK) return rc;
+        BKO_HIP(hipMemcpyAsync(nh.data(), norms_d, sizeof(double) * nh.size(), hipMemcpyDeviceToHost, st));
+        BKO_HIP(hipStreamSynchronize(st));
+        std::vector<int> mask(static_cast<size_t>(kMaxS) * nc, 0);
+        bool any = false;
+        for (int c = 0; c < nc; ++c) {
+            if (!recs[c].X0) continue;
+            for (int j = 0; j < s; ++j) {
+                const double r = std::sqrt(nh[static_cast<size_t>(c) * kMaxS + j]);
+                if (!(r <= cs[c].bnorm[j])) {
+                    mask[static_cast<size_t>(c) * kMaxS + j] = 1;
+                    cs[c].info.x0_rejected += 1;
+                    any = true;
+                }
+            }
+        }
+        if (any) {
+            BKO_HIP(hipMemcpyAsync(base + L.off_mask, mask.data(), sizeof(int) * mask.size(), hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(zero_cols_kernel, dim3(static_cast<unsigned>(L.total_wgs)), dim3(kThreads), 0, st, x.cds,
+                               x.tab, s, reinterpret_cast<const int *>(base + L.off_mask));
+            BKO_HIP(hipGetLastError());
+            BKO_HIP(hipStreamSynchronize(st));
+        }
     }
 
     for (int outer = 0; outer < 100; ++outer) {

@@ -682,6 +682,20 @@ bko_status bko_lstart_unpack(int n, const float *y, int m, const double *scale, 
     BKO_GUARD_END
 }
 
+bko_status bko_jacobi_smooth(bko_op A, int m, const double *B, int ldb, double *X, int ldx, double *work, int ldw,
+                             int sweeps, double omega, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(A != nullptr, "operator handle is NULL");
+    const Operator &op = *reinterpret_cast<const Operator *>(A);
+    BKO_CHECK(m >= 1 && B && X && work, "bad arguments");
+    BKO_CHECK(ldb >= op.n && ldx >= op.n && ldw >= op.n, "leading dimensions must be >= n");
+    BKO_CHECK(sweeps >= 0 && sweeps <= 10000, "sweeps outside [0, 10000]");
+    BKO_CHECK(omega > 0.0 && omega < 2.0, "omega must be in (0, 2)");
+    return launch_jacobi(op, m, B, ldb, X, ldx, work, ldw, sweeps, omega, static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
 bko_status bko_timing_enable(int enable)
 {
     TimingState &t = timing();

@@ -16,6 +16,11 @@ bko_status launch_stencil(const Operator &op, int m, const void *X, int64_t ldx,
                           const double *Bres, int64_t ldb, hipStream_t stream, const int *skip = nullptr,
                           int *stop = nullptr);
 
+// `sweeps` damped Jacobi sweeps X <- X + omega (B - A X) / diag(A) in FP64
+// over m columns; work is an n x m FP64 block (ldw >= n).
+bko_status launch_jacobi(const Operator &op, int m, const double *B, int64_t ldb, double *X, int64_t ldx,
+                         double *work, int64_t ldw, int sweeps, double omega, hipStream_t stream);
+
 bko_status launch_combine(int64_t n, int s, int64_t m, const void *X, int64_t ldx, bko_dtype x_t,
                           const void *C, int64_t ldc, bko_dtype c_t, void *T, int64_t ldt,
                           bko_dtype t_t, bko_dtype compute, hipStream_t stream);

@@ -461,7 +461,7 @@ namespace bko {
 
 namespace {
 
-// scale[j] = ||F[:, j]||_2 (one workgroup per column, FP64)
+// scale[j] = ||F[:, j]||_2 / sqrt(n), the RMS value (one workgroup per column, FP64)
 __global__ __launch_bounds__(kNT) void colnorm64_kernel(const double *__restrict__ F, int64_t ldf, int64_t n,
                                                         double *__restrict__ scale)
 {
@@ -478,7 +478,7 @@ __global__ __launch_bounds__(kNT) void colnorm64_kernel(const double *__restrict
         if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) scale[j] = sqrt(sh[0]);
+    if (threadIdx.x == 0) scale[j] = sqrt(sh[0] / static_cast<double>(n));
 }
 
 // Network input of field j: channels [0, nz) = F[:, j] / scale[j] as nz

@@ -267,6 +267,18 @@ def workload(config_index: int, *, m: Optional[int] = None, s: Optional[int] = N
     raise ValueError(f"unknown configuration index {config_index}")
 
 
+def learned_start_test_chips(n: int, grid: Tuple[int, int, int] = (128, 128, 8), s: int = 16):
+    """Unseen chips for the learned start: the training generator with seeds
+    disjoint from the training chips'.  Returns (chips, power maps)."""
+    chips, Bs = [], []
+    for i in range(n):
+        rng = np.random.default_rng(seed_for(4, 50000 + i))
+        chip = chip_stack(rng, *grid)
+        chips.append(chip)
+        Bs.append(power_blocky(rng, chip, s))
+    return chips, Bs
+
+
 def random_block(rng: np.random.Generator, s: int, n: int) -> np.ndarray:
     """Standard-normal (s, N) block, for probes and parity tests."""
     return rng.standard_normal(size=(s, n))

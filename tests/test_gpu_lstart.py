@@ -11,7 +11,7 @@ import pytest
 import torch
 
 from oracle import conv_ref as cr
-from paper_2510_23221_amd import capi
+from paper_2510_23221_amd import capi, synth
 from tests.gpu_util import rel_fro
 
 pytestmark = pytest.mark.gpu
@@ -191,7 +191,7 @@ def test_lstart_pack_and_unpack(dev):
     x, scale = capi.lstart_pack((nx, ny, nz), torch.as_tensor(F, device="cuda"), torch.as_tensor(k, device="cuda"),
                                 2.0, 1.5, 0.25)
     xs, sc = _np(x), scale.cpu().numpy()
-    assert np.allclose(sc, np.linalg.norm(F, axis=1), rtol=1e-14)
+    assert np.allclose(sc, np.linalg.norm(F, axis=1) / np.sqrt(n), rtol=1e-14)
     for j in range(m):
         fj = F[j] / sc[j] if sc[j] > 0 else np.zeros(n)
         assert np.allclose(xs[j, :nz].reshape(-1), fj, rtol=1e-6, atol=1e-7)
@@ -202,3 +202,42 @@ def test_lstart_pack_and_unpack(dev):
     X0 = capi.lstart_unpack(t.reshape(m, nz, ny, nx), scale, 3.0)
     back = np.where(sc[:, None] > 0, T, 0.0)
     assert np.allclose(_np(X0), back, rtol=1e-6, atol=1e-12)
+
+
+def test_jacobi_smooth_matches_oracle(dev):
+    import oracle
+    rng = np.random.default_rng(800)
+    chip = synth.chip_stack(rng, 24, 16, 5)
+    A = oracle.assemble_chip(chip)
+    G = capi.HeatOperator.from_chip(chip, dev)
+    B = rng.standard_normal((3, A.n))
+    X = rng.standard_normal((3, A.n))
+    diag = np.array([A.val[A.rowptr[i]:A.rowptr[i + 1]][A.col[A.rowptr[i]:A.rowptr[i + 1]] == i][0] for i in range(A.n)])
+    ref = X.copy()
+    for _ in range(3):  # odd count: the result comes back from the work block
+        ref = ref + 0.6 * (B - oracle.apply_many(A, ref)) / diag
+    Xd = torch.as_tensor(X, device=dev)
+    capi.jacobi_smooth(G, torch.as_tensor(B, device=dev), Xd, 3, 0.6)
+    assert rel_fro(_np(Xd), ref) <= 1e-13
+
+
+@pytest.mark.parametrize("compute", [capi.F64, capi.F32])
+def test_learned_start_cuts_block_iterations(dev, compute):
+    """Train the network on pairs the pipeline generates for a few chips and
+    start the block solve of unseen chips from its (smoothed) prediction:
+    fewer block iterations than the zero start with the same smoothing, at
+    the same FP64 residual target."""
+    from paper_2510_23221_amd import lstart
+    w = synth.workload(4, grid=(32, 32, 4), nchips=6, m=256, s=8)
+    data = lstart.generate_pairs(w.chips, w.B, w.C, 1e-10, compute=capi.F64)
+    norm = lstart.fit_normalizer(data)
+    net = lstart.make_net(w.chips[0], base=8, max_batch=16, seed=0)
+    log = lstart.train(net, data, norm, steps=2000, batch=16, lr=2e-3, seed=1, log_every=500)
+    assert log[-1][1] < 0.05 * log[0][1], log
+    chips, Bs = synth.learned_start_test_chips(4, (32, 32, 4), 8)
+    recs = lstart.evaluate(net, norm, chips, Bs, 1e-8, compute=compute, smooth=20)
+    zero = sum(r["zero_smooth_iters"] for r in recs)
+    learned = sum(r["learned_iters"] for r in recs)
+    assert all(r["learned_res"] <= 1e-8 and r["zero_smooth_res"] <= 1e-8 for r in recs)
+    assert all(r["rejected"] == 0 for r in recs)
+    assert learned < zero, [(r["zero_iters"], r["zero_smooth_iters"], r["learned_iters"]) for r in recs]

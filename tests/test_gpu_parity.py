@@ -471,3 +471,25 @@ def test_batch_initial_guess_and_zero_chip(dev):
     assert infos[0]["iters"] == 0 and infos[1]["iters"] > 0
     assert infos[2]["iters"] == 0 and np.abs(to_np(Xs[2])).max() == 0.0
     assert all(i["status"] == capi.OK for i in infos)
+
+
+def test_initial_guess_fallback_to_zero_start(ops, dev):
+    """Columns of X0 that start worse than zero are replaced by the zero start
+    (the plain block CG fallback of the learned start); good columns are kept."""
+    chip, A, G = ops["2d"]
+    rng = np.random.default_rng(31)
+    B = rng.standard_normal((6, A.n))
+    Bg = torch.as_tensor(B, device=dev)
+    X_zero, info_zero = capi.block_krylov_solve(G, Bg, 1e-10)
+    bad = torch.as_tensor(1e6 * rng.standard_normal((6, A.n)), device=dev)
+    X_bad, info_bad = capi.block_krylov_solve(G, Bg, 1e-10, X0=bad)
+    assert info_bad["x0_rejected"] == 6
+    assert info_bad["iters"] == info_zero["iters"]
+    assert torch.equal(X_bad, X_zero)
+    X_ref, _, _ = oracle.cg_many(A, B, 1e-13)
+    mixed = bad.clone()
+    mixed[:3] = torch.as_tensor(X_ref[:3], device=dev)
+    _, info_mixed = capi.block_krylov_solve(G, Bg, 1e-10, X0=mixed)
+    assert info_mixed["x0_rejected"] == 3 and info_mixed["status"] == capi.OK
+    _, info_none = capi.block_krylov_solve(G, Bg, 1e-10)
+    assert info_none["x0_rejected"] == 0
