@@ -39,7 +39,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=1, help="workload index (0..3)")
+    ap.add_argument("--config", type=int, default=1, help="single-chip workload index (0, 1, 3)")
+    ap.add_argument("--workload", choices=["single", "batched", "learned"], default="single",
+                    help="single chip (default), batch of uneven chips, or learned start")
+    ap.add_argument("--nchips", type=int, default=None)
+    ap.add_argument("--train-epochs", type=float, default=2.0)
+    ap.add_argument("--test-chips", type=int, default=64)
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cg-columns", type=int, default=512, help="columns of the per-sample CG baseline (0: skip)")
@@ -97,6 +102,10 @@ def main():
     from paper_2510_23221_amd import capi, synth
 
     dev = torch.device("cuda:0")
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "learned":
+        return bench_learned(args)
     w = synth.workload(args.config, m=args.m)
     chip = w.chips[0]
     s, m, n = w.s, w.m, chip.n
@@ -209,6 +218,108 @@ def main():
         res["per_sample_cg"] = per_sample_cg(G, B, C, w, args.cg_columns, value)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(res), flush=True)
+
+
+def bench_batched(args):
+    """Batch of uneven chips (64 stacks, 32^2..256^2 x 4..12 layers, s = 16,
+    M = 500 each): one batch plan solves every chip with grouped launches
+    and graph-captured iteration chunks on a side stream, then each chip's
+    combination and operator action.  value = all pairs / step time."""
+    import torch
+
+    from paper_2510_23221_amd import capi, synth
+
+    dev = torch.device("cuda:0")
+    w = synth.workload(2, m=args.m, nchips=args.nchips)
+    Gs = [capi.HeatOperator.from_chip(c, dev) for c in w.chips]
+    Bs = [torch.as_tensor(B, device=dev) for B in w.B]
+    Cs = [torch.as_tensor(C, device=dev) for C in w.C]
+    Xs = [torch.empty_like(B) for B in Bs]
+    nmax = max(c.n for c in w.chips)
+    T = torch.empty((w.m, nmax), dtype=torch.float64, device=dev)
+    F = torch.empty((w.m, nmax), dtype=torch.float64, device=dev)
+    plan = capi.BatchPlan(Gs, w.s, capi.F32)
+    stream = torch.cuda.Stream()
+    infos = []
+    with torch.cuda.stream(stream):
+        tpw = plan.tune(dev, stream=stream)
+
+        def step():
+            _, inf = plan.solve(Bs, w.tol, Xs=Xs, stream=stream)
+            for G, X, C in zip(Gs, Xs, Cs):
+                n = G.n
+                capi.combine(X, C, T=T[:, :n], stream=stream)
+                capi.apply_operator(G, T[:, :n], F=F[:, :n], stream=stream)
+            infos.append(inf)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    pairs = w.m * len(w.chips)
+    last = infos[-1]
+    res = {"metric": "data pairs/s at rel residual <=1e-8, batch of uneven chips", "value": round(pairs / (ms * 1e-3), 1),
+           "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": w.name, "nchips": len(w.chips), "cells_total": int(sum(c.n for c in w.chips)),
+                      "s": w.s, "M_per_chip": w.m, "tol": w.tol, "scheme": "mixed", "T_F_dtype": "float64"},
+           "autotuned_tiles_per_workgroup": tpw,
+           "iters": {"min": min(i["iters"] for i in last), "max": max(i["iters"] for i in last),
+                     "mean": sum(i["iters"] for i in last) / len(last)},
+           "max_rel_res": max(i["max_rel_res"] for i in last),
+           "all_ok": all(i["status"] == capi.OK for i in last)}
+    print(json.dumps(res), flush=True)
+
+
+def bench_learned(args):
+    """Learned start: generate the training pairs with BlocKOA (40 chips at
+    128 x 128 x 8, 500 pairs each), train the encoder-decoder with the
+    library's kernels, then solve unseen chips (s = 16) from the zero start,
+    the smoothed zero start and the smoothed learned start."""
+    import numpy as np
+    import torch
+
+    from paper_2510_23221_amd import capi, lstart, synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    w = synth.workload(4, m=args.m, nchips=args.nchips)
+    data = lstart.generate_pairs(w.chips, w.B, w.C, 1e-10, compute=capi.F32)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    norm = lstart.fit_normalizer(data)
+    batch = 16
+    net = lstart.make_net(w.chips[0], base=32, max_batch=batch, seed=0)
+    steps = max(1, int(args.train_epochs * len(w.chips) * w.m / batch))
+    t0 = time.perf_counter()
+    log = lstart.train(net, data, norm, steps=steps, batch=batch, lr=5e-4, seed=1, log_every=max(1, steps // 10))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    chips, Bs = synth.learned_start_test_chips(args.test_chips, w.chips[0].dims, w.s)
+    recs = lstart.evaluate(net, norm, chips, Bs, w.tol, compute=capi.F32, smooth=20)
+    z = np.array([r["zero_iters"] for r in recs])
+    zs = np.array([r["zero_smooth_iters"] for r in recs])
+    ln = np.array([r["learned_iters"] for r in recs])
+    t_zero = sum(r["zero_s"] for r in recs)
+    t_learn = sum(r["learned_s"] + r["infer_s"] for r in recs)
+    res = {"metric": "block iterations and solve throughput, learned vs zero start", "unit": "basis solves/s",
+           "value": round(len(recs) / t_learn, 2), "zero_start_value": round(len(recs) / t_zero, 2),
+           "n_gpus": 1, "data": "synthetic", "dtype": "bf16 weights, f32 activations; f32+f64 solve",
+           "config": {"workload": "learned-start-128x128x8", "train_chips": len(w.chips), "pairs": len(w.chips) * w.m,
+                      "s": w.s, "test_chips": len(recs), "tol": w.tol, "params": net.nparams, "epochs": args.train_epochs,
+                      "smoothing_sweeps": 20},
+           "seconds": {"generate_pairs": round(t_gen, 2), "train": round(t_train, 2)},
+           "train_loss": [(a, round(b, 6)) for a, b in log],
+           "iters": {"zero": float(z.mean()), "zero_smoothed": float(zs.mean()), "learned": float(ln.mean())},
+           "learned_fewer_than_zero_smoothed": int((ln < zs).sum()),
+           "rejected_columns": int(sum(r["rejected"] for r in recs)),
+           "max_rel_res": {"zero": max(r["zero_res"] for r in recs), "learned": max(r["learned_res"] for r in recs)}}
     print(json.dumps(res), flush=True)
 
 

@@ -71,7 +71,7 @@ typedef struct {
     int deflated;       /* search directions dropped as linearly dependent   */
     int status;         /* bko_status of the solve                           */
     double max_rel_res; /* max_j ||b_j - A x_j||_2 / ||b_j||_2, FP64, at exit */
-    int x0_rejected;    /* initial-guess columns replaced by zero (fallback)  */
+    int x0_rejected;    /* initial-guess columns that fell back to zero       */
 } bko_solve_info;
 
 /* ------------------------------------------------------------------ build */
@@ -150,9 +150,11 @@ bko_status bko_block_krylov_workspace_bytes(bko_op A, int s, bko_dtype compute, 
  *                       iterative refinement).
  *   B (n x s, ldb >= n) FP64 device, X (n x s, ldx >= n) FP64 device output.
  *   X0 (ldx0 >= n) optional FP64 initial guess (e.g. a learned start); NULL
- *   means X0 = 0.  X0 may alias X (ldx0 == ldx).  A column whose initial
- *   residual is larger than ||b_j|| (a start worse than zero) or not finite
- *   falls back to the zero start; info->x0_rejected counts such columns.
+ *   means X0 = 0.  X0 may alias X (ldx0 == ldx).  Each column x0 is used as
+ *   alpha x0 with alpha = x0'b / x0'A x0, the multiple of x0 closest to the
+ *   solution in the A-norm (never further from it than the zero start); a
+ *   column with alpha <= 0 or not finite falls back to the zero start and is
+ *   counted in info->x0_rejected.
  *   tol > 0, max_iter >= 1 caps the total inner iterations.
  *   work / work_bytes: caller workspace (bko_block_krylov_workspace_bytes),
  *   256-byte aligned, contents need not be initialised.
@@ -189,14 +191,15 @@ bko_status bko_batch_plan_destroy(bko_batch plan);
 bko_status bko_batch_workspace_bytes(bko_batch plan, size_t *bytes);
 
 /*
- * Autotuner: times the row kernels of the whole batch for each candidate
- * per-chip workgroup count (64, 128, 256, 512: how many row tiles each
- * workgroup walks and how many Gram partials each reduction sums) and keeps
- * the fastest in the plan.  The workspace contents are overwritten.  wg_cap
- * (host, may be NULL) receives the choice.  bko_batch_solve tunes on its
- * first call if this was not called.  Synchronises the stream.
+ * Autotuner: times the row kernels for each candidate number of 256-row
+ * tiles per workgroup (1, 2, 4, 8: each chip then runs ceil(tiles / t)
+ * workgroups, and its Gram reductions sum as many partials), over the whole
+ * batch and over its largest chip alone (the tail of a batch solve), and
+ * keeps the fastest in the plan.  The workspace contents are overwritten.
+ * tiles_per_wg (host, may be NULL) receives the choice.  bko_batch_solve
+ * tunes on its first call if this was not called.  Synchronises the stream.
  */
-bko_status bko_batch_tune(bko_batch plan, void *work, size_t work_bytes, int *wg_cap, void *stream);
+bko_status bko_batch_tune(bko_batch plan, void *work, size_t work_bytes, int *tiles_per_wg, void *stream);
 
 /*
  * Solve A_c X_c = B_c for every chip c of the plan (semantics of

@@ -284,11 +284,12 @@ class BatchPlan:
         return self._work[1], self._work[2]
 
     def tune(self, device="cuda", stream=None) -> int:
+        """Run the autotuner; returns the chosen row tiles per workgroup."""
         ptr, nbytes = self._workspace(device)
-        cap = ctypes.c_int()
-        _check(load_library().bko_batch_tune(self.handle, ctypes.c_void_p(ptr), nbytes, ctypes.byref(cap),
+        tpw = ctypes.c_int()
+        _check(load_library().bko_batch_tune(self.handle, ctypes.c_void_p(ptr), nbytes, ctypes.byref(tpw),
                                              _stream(stream)))
-        return cap.value
+        return tpw.value
 
     def solve(self, Bs: Sequence[torch.Tensor], tol: float, max_iter: int = 100000, X0s=None, Xs=None,
               stream=None, check: bool = True):

@@ -103,7 +103,7 @@ struct ChipDev {
     void *Dv, *P, *AP, *W;
     double *R64;
     Small sm;
-    double *parts;  // [wgs][s][s] Gram partials, also [wgs][s] column sums
+    double *parts;  // [wgs][s][s] Gram partials, also [wgs][s] or [wgs][2 s] column sums
     double *gram;   // [s][s]
     double *norms;  // [kMaxS] squared column norms
     int *ctrl;      // kCtrlInts control words
@@ -983,21 +983,75 @@ __global__ __launch_bounds__(kThreads) void start_x_kernel(const ChipDev *__rest
     }
 }
 
-// X[:, c] = 0 for the columns with mask[chip * kMaxS + c] != 0.
-__global__ __launch_bounds__(kThreads) void zero_cols_kernel(const ChipDev *__restrict__ cds,
-                                                             const uint16_t *__restrict__ tab, int s,
-                                                             const int *__restrict__ mask)
+// Per-workgroup column sums of X0 . B and X0 . R64 (R64 = B - A X0) over
+// the chip's rows, into parts[local * 2s + c] and parts[local * 2s + s + c].
+__global__ __launch_bounds__(kThreads) void x0_dots_kernel(const ChipDev *__restrict__ cds,
+                                                           const uint16_t *__restrict__ tab, int s)
 {
     int local;
     const ChipDev &cd = chip_of(cds, tab, local);
     const int wgs = cd.wgs;
-    const int *mk = mask + static_cast<size_t>(tab[blockIdx.x]) * kMaxS;
+    if (!cd.X0) return;
+    __shared__ double sh[kThreads / 64][2 * kMaxS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t ntiles = cd.ldw / kTileRows;
+    for (int c = 0; c < s; ++c) {
+        double ab = 0.0, ar = 0.0;
+        for (int64_t tile = local; tile < ntiles; tile += wgs) {
+            const int64_t a = tile * kTileRows + threadIdx.x;
+            if (a < cd.n) {
+                const double x = cd.X[c * cd.ldx + a];
+                ab = fma(x, cd.B[c * cd.ldb + a], ab);
+                ar = fma(x, cd.R64[c * cd.ldw + a], ar);
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            ab += __shfl_xor(ab, off);
+            ar += __shfl_xor(ar, off);
+        }
+        if (lane == 0) {
+            sh[wave][c] = ab;
+            sh[wave][s + c] = ar;
+        }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < 2 * s; c += kThreads) {
+        double t = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) t += sh[w][c];
+        cd.parts[static_cast<size_t>(local) * 2 * s + c] = t;
+    }
+}
+
+// dots[chip * 2 kMaxS + c] = sum over the chip's workgroups, in order (one
+// workgroup per chip).
+__global__ __launch_bounds__(kThreads) void x0_dots_reduce_kernel(const ChipDev *__restrict__ cds, int s,
+                                                                  double *__restrict__ dots)
+{
+    const ChipDev &cd = cds[blockIdx.x];
+    if (!cd.X0) return;
+    for (int c = threadIdx.x; c < 2 * s; c += kThreads) {
+        double t = 0.0;
+        for (int p = 0; p < cd.wgs; ++p) t += cd.parts[static_cast<size_t>(p) * 2 * s + c];
+        dots[static_cast<size_t>(blockIdx.x) * 2 * kMaxS + c] = t;
+    }
+}
+
+// X[:, c] *= alpha[chip * kMaxS + c] for chips that were given an initial guess.
+__global__ __launch_bounds__(kThreads) void scale_cols_kernel(const ChipDev *__restrict__ cds,
+                                                              const uint16_t *__restrict__ tab, int s,
+                                                              const double *__restrict__ alpha)
+{
+    int local;
+    const ChipDev &cd = chip_of(cds, tab, local);
+    const int wgs = cd.wgs;
+    if (!cd.X0) return;
+    const double *al = alpha + static_cast<size_t>(tab[blockIdx.x]) * kMaxS;
     const int64_t ntiles = cd.ldw / kTileRows;
     for (int64_t tile = local; tile < ntiles; tile += wgs) {
         const int64_t a = tile * kTileRows + threadIdx.x;
         if (a >= cd.n) continue;
-        for (int c = 0; c < s; ++c)
-            if (mk[c]) cd.X[c * cd.ldx + a] = 0.0;
+        for (int c = 0; c < s; ++c) cd.X[c * cd.ldx + a] *= al[c];
     }
 }
 
@@ -1033,16 +1087,21 @@ struct ChipHost {
 };
 
 struct Layout {
-    int nchips = 0, s = 0, total_wgs = 0, wg_cap = 0;
+    int nchips = 0, s = 0, total_wgs = 0, tiles_per_wg = 1;
     bko_dtype compute = BKO_F64;
-    size_t off_cds = 0, off_tab = 0, off_th = 0, off_ctrl = 0, off_norms = 0, off_mask = 0, bytes = 0;
+    size_t off_cds = 0, off_tab = 0, off_th = 0, off_ctrl = 0, off_norms = 0, off_alpha = 0, off_dots = 0, bytes = 0;
     std::vector<ChipHost> chips;
 };
 
-constexpr int kMaxWgs = 512;  // partial producers per chip (upper bound of the tuned cap)
+// Gram partials a chip may produce per reduction: enough for one workgroup
+// per row tile of the chips in use, bounded so a chip's partials stay within
+// 32 MB at any s.
+inline int part_cap(int s) { return std::max(512, (1 << 22) / (s * s)); }
+inline int max_parts(int tiles, int s) { return std::min(tiles, part_cap(s)); }
 
 inline size_t chip_region_bytes(int64_t ldw, int s, bko_dtype compute, size_t *offs)
 {
+    const size_t nparts = static_cast<size_t>(max_parts(static_cast<int>(ldw / kTileRows), s));
     const size_t vsz = compute == BKO_F64 ? 8 : 4;
     const size_t ss = static_cast<size_t>(s) * s;
     const size_t sizes[] = {sizeof(double) * ldw * s,                     // R64
@@ -1051,7 +1110,7 @@ inline size_t chip_region_bytes(int64_t ldw, int s, bko_dtype compute, size_t *o
                             sizeof(double) * ss * 5,                      // C, M1..M4
                             sizeof(double) * kMaxS,                       // (unused slot)
                             sizeof(float) * ss * 4,                       // M1f..M4f
-                            sizeof(double) * ss * kMaxWgs,                // parts
+                            sizeof(double) * std::max<size_t>(ss, 2 * s) * nparts,  // parts (Gram, or 2 column sums)
                             sizeof(double) * ss};                         // gram
     size_t o = 0;
     for (size_t k = 0; k < sizeof(sizes) / sizeof(sizes[0]); ++k) {
@@ -1061,13 +1120,16 @@ inline size_t chip_region_bytes(int64_t ldw, int s, bko_dtype compute, size_t *o
     return o;
 }
 
-Layout make_layout(const Operator *const *ops, int nchips, int s, bko_dtype compute, int wg_cap)
+// tiles_per_wg: row tiles each workgroup of the row kernels walks (the
+// autotuned granularity); a chip gets ceil(tiles / tiles_per_wg) workgroups,
+// at most max_parts of them.
+Layout make_layout(const Operator *const *ops, int nchips, int s, bko_dtype compute, int tiles_per_wg)
 {
     Layout L;
     L.nchips = nchips;
     L.s = s;
     L.compute = compute;
-    L.wg_cap = wg_cap;
+    L.tiles_per_wg = tiles_per_wg;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t q = o;
@@ -1083,18 +1145,19 @@ Layout make_layout(const Operator *const *ops, int nchips, int s, bko_dtype comp
         h.n = ops[c]->n;
         h.ldw = static_cast<int64_t>(align_up(static_cast<size_t>(h.n), kTileRows));
         h.tiles = static_cast<int>(h.ldw / kTileRows);
-        h.wgs = std::min(h.tiles, wg_cap);
+        h.wgs = std::min((h.tiles + tiles_per_wg - 1) / tiles_per_wg, max_parts(h.tiles, s));
         h.wg_base = total;
         total += h.wgs;
     }
     L.total_wgs = total;
-    int table = 0;  // sized for the largest cap, so offsets do not depend on the cap
-    for (int c = 0; c < nchips; ++c) table += std::min(L.chips[c].tiles, kMaxWgs);
+    int table = 0;  // sized for one tile per workgroup, so offsets do not depend on the tuning
+    for (int c = 0; c < nchips; ++c) table += max_parts(L.chips[c].tiles, s);
     L.off_tab = take(sizeof(uint16_t) * table);
     L.off_th = take(sizeof(double) * kMaxS * nchips);
     L.off_ctrl = take(sizeof(int) * kCtrlInts * nchips);
     L.off_norms = take(sizeof(double) * kMaxS * nchips);
-    L.off_mask = take(sizeof(int) * kMaxS * nchips);
+    L.off_alpha = take(sizeof(double) * kMaxS * nchips);
+    L.off_dots = take(sizeof(double) * 2 * kMaxS * nchips);
     for (int c = 0; c < nchips; ++c) L.chips[c].off = take(chip_region_bytes(L.chips[c].ldw, s, compute, nullptr));
     L.bytes = o;
     return L;
@@ -1369,38 +1432,42 @@ bko_status batch_solve_t(const Layout &L, void *work, const double *const *B, co
                 return BKO_EINVAL;
             }
     }
-    // fallback: a column of an initial guess whose residual is not smaller
-    // than the zero start's (||b_j - A x0_j|| > ||b_j||, or not finite) starts
-    // from zero instead
+    // an initial guess column x0 is replaced by alpha x0 with alpha =
+    // x0'b / x0'A x0, the multiple of x0 closest to the solution in the A-norm
+    // (the norm block CG minimises), which is never further than the zero
+    // start; a column with alpha <= 0 or not finite starts from zero
     bool any_x0 = false;
     for (int c = 0; c < nc; ++c) any_x0 = any_x0 || recs[c].X0 != nullptr;
     if (any_x0) {
         hipLaunchKernelGGL(residual_kernel, dim3(static_cast<unsigned>(L.total_wgs)), dim3(kThreads), 0, st, x.cds, x.tab,
                            s);
         BKO_HIP(hipGetLastError());
-        if ((rc = host_norms(x, 1)) != BKO_OK) return rc;
-        BKO_HIP(hipMemcpyAsync(nh.data(), norms_d, sizeof(double) * nh.size(), hipMemcpyDeviceToHost, st));
+        double *dots_d = reinterpret_cast<double *>(base + L.off_dots);
+        hipLaunchKernelGGL(x0_dots_kernel, dim3(static_cast<unsigned>(L.total_wgs)), dim3(kThreads), 0, st, x.cds, x.tab,
+                           s);
+        BKO_HIP(hipGetLastError());
+        hipLaunchKernelGGL(x0_dots_reduce_kernel, dim3(static_cast<unsigned>(nc)), dim3(kThreads), 0, st, x.cds, s, dots_d);
+        BKO_HIP(hipGetLastError());
+        std::vector<double> dh(static_cast<size_t>(2 * kMaxS) * nc, 0.0), alpha(static_cast<size_t>(kMaxS) * nc, 1.0);
+        BKO_HIP(hipMemcpyAsync(dh.data(), dots_d, sizeof(double) * dh.size(), hipMemcpyDeviceToHost, st));
         BKO_HIP(hipStreamSynchronize(st));
-        std::vector<int> mask(static_cast<size_t>(kMaxS) * nc, 0);
-        bool any = false;
         for (int c = 0; c < nc; ++c) {
             if (!recs[c].X0) continue;
             for (int j = 0; j < s; ++j) {
-                const double r = std::sqrt(nh[static_cast<size_t>(c) * kMaxS + j]);
-                if (!(r <= cs[c].bnorm[j])) {
-                    mask[static_cast<size_t>(c) * kMaxS + j] = 1;
-                    cs[c].info.x0_rejected += 1;
-                    any = true;
-                }
+                const double xb = dh[static_cast<size_t>(c) * 2 * kMaxS + j];
+                const double xr = dh[static_cast<size_t>(c) * 2 * kMaxS + s + j];
+                const double xax = xb - xr;  // x0' A x0 = x0' (b - r0)
+                double a = (xb > 0.0 && xax > 0.0) ? xb / xax : 0.0;
+                if (!std::isfinite(a)) a = 0.0;
+                alpha[static_cast<size_t>(c) * kMaxS + j] = a;
+                if (a == 0.0) cs[c].info.x0_rejected += 1;
             }
         }
-        if (any) {
-            BKO_HIP(hipMemcpyAsync(base + L.off_mask, mask.data(), sizeof(int) * mask.size(), hipMemcpyHostToDevice, st));
-            hipLaunchKernelGGL(zero_cols_kernel, dim3(static_cast<unsigned>(L.total_wgs)), dim3(kThreads), 0, st, x.cds,
-                               x.tab, s, reinterpret_cast<const int *>(base + L.off_mask));
-            BKO_HIP(hipGetLastError());
-            BKO_HIP(hipStreamSynchronize(st));
-        }
+        BKO_HIP(hipMemcpyAsync(base + L.off_alpha, alpha.data(), sizeof(double) * alpha.size(), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(scale_cols_kernel, dim3(static_cast<unsigned>(L.total_wgs)), dim3(kThreads), 0, st, x.cds,
+                           x.tab, s, reinterpret_cast<const double *>(base + L.off_alpha));
+        BKO_HIP(hipGetLastError());
+        BKO_HIP(hipStreamSynchronize(st));
     }
 
     for (int outer = 0; outer < 100; ++outer) {
@@ -1526,7 +1593,7 @@ size_t solve_workspace_bytes(int64_t n, int s, bko_dtype compute)
     Operator op{};
     op.n = n;
     const Operator *ops[1] = {&op};
-    return make_layout(ops, 1, s, compute, kMaxWgs).bytes;
+    return make_layout(ops, 1, s, compute, 1).bytes;
 }
 
 bko_status block_solve(const Operator &op, int s, const double *B, int64_t ldb, double *X, int64_t ldx,
@@ -1535,7 +1602,7 @@ bko_status block_solve(const Operator &op, int s, const double *B, int64_t ldb, 
 {
     (void)work_bytes;
     const Operator *ops[1] = {&op};
-    const Layout L = make_layout(ops, 1, s, compute, kMaxWgs);
+    const Layout L = make_layout(ops, 1, s, compute, 1);
     const double *Bs[1] = {B};
     double *Xs[1] = {X};
     const double *X0s[1] = {X0};
@@ -1547,63 +1614,82 @@ bko_status block_solve(const Operator &op, int s, const double *B, int64_t ldb, 
 
 size_t batch_workspace_bytes(const BatchPlan &p)
 {
-    return make_layout(p.ops.data(), static_cast<int>(p.ops.size()), p.s, p.compute, kMaxWgs).bytes;
+    return make_layout(p.ops.data(), static_cast<int>(p.ops.size()), p.s, p.compute, 1).bytes;
 }
 
 namespace {
 
 // Time the partial-producing row kernels (stencil + Gram, and the W^T W
-// Gram) of the whole batch at one workgroup cap; milliseconds per pass.
+// Gram) at one granularity: a pass over the whole batch, plus a pass in
+// which only the largest chip runs (the tail of a batch solve, where the
+// slowest chips iterate alone).  Milliseconds per pass, summed.
 template <class T>
-bko_status time_cap(const BatchPlan &p, int cap, void *work, hipStream_t st, float &ms)
+bko_status time_granularity(const BatchPlan &p, int tpw, void *work, hipStream_t st, float &ms)
 {
     const int nc = static_cast<int>(p.ops.size());
-    const Layout L = make_layout(p.ops.data(), nc, p.s, p.compute, cap);
+    const Layout L = make_layout(p.ops.data(), nc, p.s, p.compute, tpw);
     char *base = static_cast<char *>(work);
     const std::vector<ChipDev> recs = chip_records(L, work, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     const std::vector<uint16_t> tabh = wg_table(L);
     BKO_HIP(hipMemcpyAsync(base + L.off_cds, recs.data(), sizeof(ChipDev) * nc, hipMemcpyHostToDevice, st));
     BKO_HIP(hipMemcpyAsync(base + L.off_tab, tabh.data(), sizeof(uint16_t) * tabh.size(), hipMemcpyHostToDevice, st));
     Ctx x{&L, reinterpret_cast<const ChipDev *>(base + L.off_cds), reinterpret_cast<const uint16_t *>(base + L.off_tab), st};
-    bko_status rc;
-    auto pass = [&]() -> bko_status {
-        bko_status r;
-        if ((r = launch_row<T>(0, x, 0)) != BKO_OK) return r;
-        return launch_row<T>(1, x, 1);
-    };
-    if ((rc = pass()) != BKO_OK) return rc;
+    int biggest = 0;
+    for (int c = 1; c < nc; ++c)
+        if (L.chips[c].tiles > L.chips[biggest].tiles) biggest = c;
+    std::vector<int> all(static_cast<size_t>(kCtrlInts) * nc, 0), tail(static_cast<size_t>(kCtrlInts) * nc, 0);
+    for (int c = 0; c < nc; ++c)
+        if (c != biggest) tail[static_cast<size_t>(c) * kCtrlInts + kConverged] = 1;
+    int *ctrl_d = reinterpret_cast<int *>(base + L.off_ctrl);
     hipEvent_t a = nullptr, b = nullptr;
     BKO_HIP(hipEventCreate(&a));
     if (hipEventCreate(&b) != hipSuccess) {
         (void)hipEventDestroy(a);
         return hip_fail(hipErrorOutOfMemory, "hipEventCreate");
     }
-    constexpr int kReps = 5;
-    (void)hipEventRecord(a, st);
-    for (int r = 0; r < kReps && rc == BKO_OK; ++r) rc = pass();
-    (void)hipEventRecord(b, st);
-    const hipError_t e = hipEventSynchronize(b);
-    float t = 0.f;
-    if (e == hipSuccess) (void)hipEventElapsedTime(&t, a, b);
+    bko_status rc = BKO_OK;
+    float total = 0.f;
+    for (const std::vector<int> *ctrl : {&all, &tail}) {
+        if (hipMemcpyAsync(ctrl_d, ctrl->data(), sizeof(int) * ctrl->size(), hipMemcpyHostToDevice, st) != hipSuccess) {
+            rc = hip_fail(hipErrorUnknown, "hipMemcpyAsync");
+            break;
+        }
+        auto pass = [&]() -> bko_status {
+            bko_status r;
+            if ((r = launch_row<T>(0, x, 0)) != BKO_OK) return r;
+            return launch_row<T>(1, x, 1);
+        };
+        if ((rc = pass()) != BKO_OK) break;
+        constexpr int kReps = 5;
+        (void)hipEventRecord(a, st);
+        for (int r = 0; r < kReps && rc == BKO_OK; ++r) rc = pass();
+        (void)hipEventRecord(b, st);
+        const hipError_t e = hipEventSynchronize(b);
+        if (rc != BKO_OK) break;
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "hipEventSynchronize");
+            break;
+        }
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, a, b);
+        total += t / kReps;
+    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    if (rc != BKO_OK) return rc;
-    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-    ms = t / kReps;
-    return BKO_OK;
+    ms = total;
+    return rc;
 }
 
 }  // namespace
 
-// Autotuner: choose the per-chip workgroup cap of the row kernels (how many
-// tiles each workgroup walks, and how many Gram partials each reduction
-// sums) by timing every candidate on this batch and workspace.  The
-// workspace contents are scratch here (control words cleared: every chip
-// runs).
+// Autotuner: choose how many row tiles each workgroup of the row kernels
+// walks (which sets each chip's workgroup count and Gram-partial count) by
+// timing every candidate on this batch and workspace, over the whole batch
+// and over its largest chip alone.  The workspace contents are scratch here.
 bko_status batch_tune(BatchPlan &p, void *work, hipStream_t st)
 {
     const int nc = static_cast<int>(p.ops.size());
-    const Layout L0 = make_layout(p.ops.data(), nc, p.s, p.compute, kMaxWgs);
+    const Layout L0 = make_layout(p.ops.data(), nc, p.s, p.compute, 1);
     if (row_kernel_lds(p.s, p.compute) > device_max_lds()) {
         set_error("s = %d needs %zu bytes of LDS per workgroup in this precision; the device grants %zu", p.s,
                   row_kernel_lds(p.s, p.compute), device_max_lds());
@@ -1614,16 +1700,19 @@ bko_status batch_tune(BatchPlan &p, void *work, hipStream_t st)
     if ((rc = launch_zero(work, L0.bytes, st)) != BKO_OK) return rc;
     p.tune_ms.clear();
     float best = 0.f;
-    int best_cap = kMaxWgs;
-    for (int cap : {64, 128, 256, 512}) {
+    int best_tpw = 1;
+    for (int tpw : {1, 2, 4, 8}) {
         float ms = 0.f;
-        rc = p.compute == BKO_F64 ? time_cap<double>(p, cap, work, st, ms) : time_cap<float>(p, cap, work, st, ms);
+        rc = p.compute == BKO_F64 ? time_granularity<double>(p, tpw, work, st, ms)
+                                  : time_granularity<float>(p, tpw, work, st, ms);
         if (rc != BKO_OK) return rc;
-        p.tune_ms.push_back({cap, ms});
-        if (best_cap == kMaxWgs && p.tune_ms.size() == 1) best = ms, best_cap = cap;
-        else if (ms < best) best = ms, best_cap = cap;
+        p.tune_ms.push_back({tpw, ms});
+        if (p.tune_ms.size() == 1 || ms < best) {
+            best = ms;
+            best_tpw = tpw;
+        }
     }
-    p.wg_cap = best_cap;
+    p.tiles_per_wg = best_tpw;
     p.tuned = true;
     p.graphs.clear();
     return BKO_OK;
@@ -1636,7 +1725,7 @@ bko_status batch_solve(BatchPlan &p, const double *const *B, const int64_t *ldb,
     bko_status rc;
     if (!p.tuned && (rc = batch_tune(p, work, st)) != BKO_OK) return rc;
     const int nc = static_cast<int>(p.ops.size());
-    const Layout L = make_layout(p.ops.data(), nc, p.s, p.compute, p.wg_cap);
+    const Layout L = make_layout(p.ops.data(), nc, p.s, p.compute, p.tiles_per_wg);
     if (p.compute == BKO_F64)
         return batch_solve_t<double>(L, work, B, ldb, X, ldx, X0, ldx0, tol, max_iter, infos, st, &p.graphs);
     return batch_solve_t<float>(L, work, B, ldb, X, ldx, X0, ldx0, tol, max_iter, infos, st, &p.graphs);

@@ -498,7 +498,7 @@ static bko_status check_batch_work(const BatchPlan &p, void *work, size_t work_b
     return BKO_OK;
 }
 
-bko_status bko_batch_tune(bko_batch plan, void *work, size_t work_bytes, int *wg_cap, void *stream)
+bko_status bko_batch_tune(bko_batch plan, void *work, size_t work_bytes, int *tiles_per_wg, void *stream)
 {
     BKO_GUARD_BEGIN
     BKO_CHECK(plan != nullptr, "NULL plan");
@@ -506,7 +506,7 @@ bko_status bko_batch_tune(bko_batch plan, void *work, size_t work_bytes, int *wg
     bko_status rc = check_batch_work(p, work, work_bytes);
     if (rc != BKO_OK) return rc;
     rc = batch_tune(p, work, static_cast<hipStream_t>(stream));
-    if (rc == BKO_OK && wg_cap) *wg_cap = p.wg_cap;
+    if (rc == BKO_OK && tiles_per_wg) *tiles_per_wg = p.tiles_per_wg;
     return rc;
     BKO_GUARD_END
 }

@@ -54,9 +54,9 @@ struct BatchPlan {
     std::vector<const Operator *> ops;
     int s = 0;
     bko_dtype compute = BKO_F64;
-    int wg_cap = 512;   // per-chip workgroups of the row kernels (autotuned)
+    int tiles_per_wg = 1;  // row tiles per workgroup of the row kernels (autotuned)
     bool tuned = false;
-    std::vector<std::pair<int, float>> tune_ms;  // (cap, ms per timed pass)
+    std::vector<std::pair<int, float>> tune_ms;  // (tiles per workgroup, ms of the timed passes)
     GraphCache graphs;
 };
 
