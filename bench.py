@@ -33,6 +33,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
+# HBM bytes per launch of the default workload's kernels: rocprofv3
+# FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads for a plain
+# device copy of known size (profiles/pmc_traffic_stack128x128x8.md).  Valid
+# only for the kernels as profiled there and the default workload.
+TRAFFIC_BYTES = {"apply": 26464.1e6, "combine": 7234.8e6, "spmm": 64.9e6, "update_w": 69.4e6,
+                 "update_dqp": 131.3e6}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -179,14 +186,17 @@ def main():
     it_total = sum(i["iters"] for i in infos[-args.steps:])
     ref_total = sum(i["refinements"] for i in infos[-args.steps:])
 
+    default_workload = args.config == 1 and args.m is None
+
     def roof(kind):
         launches, tot = fam[kind]
         if launches == 0 or kind not in per_launch_bytes:
             return None
         avg_ms = tot / launches
         gbs = per_launch_bytes[kind] / (avg_ms * 1e-3) / 1e9
+        traffic = TRAFFIC_BYTES.get(kind) if default_workload else None
         return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kind,
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kind,
                 "launches": launches, "avg_us": round(avg_ms * 1e3, 2),
                 "bytes_per_launch": int(per_launch_bytes[kind])}
 
