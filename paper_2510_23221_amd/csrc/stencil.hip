@@ -9,11 +9,14 @@
 //                        - wy_a x_{a+nx} - wy_{a-nx} x_{a-nx}
 //                        - wz_a x_{a+p} - wz_{a-p} x_{a-p},     p = nx*ny.
 //
-// Work decomposition: a workgroup owns kTile consecutive cells and a group of
-// columns; each thread loads its cell's seven coefficients once and reuses
-// them for every column of the group.  The workgroup order is remapped so
-// that each XCD walks a contiguous range of (column group, cell tile) pairs,
-// keeping the neighbouring tiles that supply the y / z halo in one L2.
+// Two kernels.  stencil_tile_kernel (the operator action over many fields):
+// full-width row tiles marched through z with the current plane in LDS and
+// 16-byte vector access; stencil_kernel (short tiles, unaligned views, the
+// FP64 residual): a workgroup owns 256 consecutive cells and a group of
+// columns, each thread loading its cell's seven coefficients once for every
+// column of the group.  Both remap the workgroup order so that each XCD walks
+// a contiguous range of work.  The damped Jacobi sweep that smooths an
+// initial guess is the per-cell form with an update.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -126,9 +129,10 @@ constexpr int kTileVecs = 4;  // 16-byte vectors per thread and plane
 // each side sits in LDS (double-buffered, so one barrier per plane); the
 // planes below and above are carried in registers.  Every global access of
 // the field is a 16-byte vector access of consecutive cells.  Workgroups are
-// ordered tile-fastest within a field and each XCD walks a contiguous range,
-// so the halo rows (read by the neighbouring tile of the same field) and the
-// coefficients of the tiles are served from that XCD's L2.
+// ordered field-fastest within a tile and each XCD walks a contiguous range,
+// so the coefficients of a tile (as many bytes per cell as the field itself,
+// or twice as many) are read from HBM about once and served from that XCD's
+// L2 to every field.
 template <class Tin, class Tout, class Tc, class Acc, bool kResidual>
 __global__ __launch_bounds__(kThreads) void stencil_tile_kernel(
     const Tc *__restrict__ diag, const Tc *__restrict__ wx, const Tc *__restrict__ wy, const Tc *__restrict__ wz,
@@ -143,8 +147,12 @@ __global__ __launch_bounds__(kThreads) void stencil_tile_kernel(
         return;
     }
     const uint32_t lb = remap_block(blockIdx.x, nblocks);
-    const int tile = static_cast<int>(lb % ntiles);
-    const int64_t field = lb / ntiles;
+    // fields fastest: the workgroups an XCD runs together share one tile's
+    // coefficients (reused from L2); the halo rows of neighbouring tiles are
+    // the only re-reads
+    const uint32_t nf = nblocks / static_cast<uint32_t>(ntiles);
+    const int tile = static_cast<int>(lb / nf);
+    const int64_t field = lb % nf;
     const int j0 = tile * TY;
     const int rows = min(TY, ny - j0);
     const int64_t plane = static_cast<int64_t>(nx) * ny;

@@ -509,3 +509,16 @@ def test_initial_guess_single_column(ops, dev):
                                       X0=torch.as_tensor(3.0 * x_ref, device=dev))
     assert info["iters"] == 0 and info["x0_rejected"] == 0
     assert rel_fro(to_np(X), x_ref) <= 1e-9
+
+
+@pytest.mark.parametrize("s,compute", [(48, capi.F64), (64, capi.F32), (64, capi.F64), (17, capi.F32)])
+def test_block_solve_wide_blocks(ops, dev, s, compute):
+    """Widths that take the three- and four-block register tiles and the
+    row-segment factorisation (s > 32), and a width one past a tile edge."""
+    chip, A, G = ops["stack"]
+    rng = np.random.default_rng(40 + s)
+    B = rng.standard_normal((s, A.n))
+    tol = 1e-10 if compute == capi.F64 else 1e-8
+    X, info, it_ref = _solve_check(A, G, B, tol, compute, dev, xerr=(1e-7 if compute == capi.F64 else None))
+    assert info["status"] == capi.OK
+    assert info["iters"] < it_ref.mean()
