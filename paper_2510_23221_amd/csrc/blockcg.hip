@@ -156,15 +156,15 @@ __device__ inline const ChipDev &chip_of(const ChipDev *cds, const uint16_t *tab
 // Sum the four waves' 16x16 FP64 blocks into an s x s partial in LDS (lds:
 // at least s * s doubles) and write it to out.  kSym: only upper blocks were
 // formed.
-template <int NB, bool kSym, int NBLK>
+template <int NB, bool kSym, int NBLK, int kNT = kThreads>
 __device__ void publish_partial(const d4 (&g)[NBLK], int s, double *lds, gptr<double> out)
 {
     const int ss = s * s;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    for (int e = threadIdx.x; e < ss; e += kThreads) lds[e] = 0.0;
+    for (int e = threadIdx.x; e < ss; e += kNT) lds[e] = 0.0;
     __syncthreads();
-    for (int wv = 0; wv < kThreads / 64; ++wv) {
+    for (int wv = 0; wv < kNT / 64; ++wv) {
         if (wave == wv) {
 #pragma unroll
             for (int a = 0; a < NB; ++a)
@@ -182,7 +182,7 @@ __device__ void publish_partial(const d4 (&g)[NBLK], int s, double *lds, gptr<do
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < ss; e += kThreads) out[e] = lds[e];
+    for (int e = threadIdx.x; e < ss; e += kNT) out[e] = lds[e];
 }
 
 // ------------------------------------------------------------------ stencil product + Gram
@@ -204,14 +204,17 @@ template <class T, int NB> __host__ __device__ constexpr size_t spmm_gram_lds()
 // product of its cell for every column of its class, writes AP, and stages
 // P and AP in LDS; Gram phase: each wave takes a quarter of the staged rows
 // on the FP64 matrix cores.
+constexpr int kSpThreads = 256;  // stencil + Gram kernel (eight-wave workgroups measured slower)
+
 template <class T, int NB>
-__global__ __launch_bounds__(kThreads) void spmm_gram_kernel(const ChipDev *__restrict__ cds,
-                                                             const uint16_t *__restrict__ tab, int s)
+__global__ __launch_bounds__(kSpThreads) void spmm_gram_kernel(const ChipDev *__restrict__ cds,
+                                                               const uint16_t *__restrict__ tab, int s)
 {
     constexpr int TR = stage_rows<T, NB>();
     constexpr int SP = 16 * NB;
     constexpr int LD = TR + 1;
-    constexpr int CSTEP = kThreads / TR;  // column classes
+    constexpr int CSTEP = kSpThreads / TR;  // column classes
+    constexpr int NW = kSpThreads / 64;     // waves
     int local;
     const ChipDev &cd = chip_of(cds, tab, local);
     const int wgs = cd.wgs;
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(kThreads) void spmm_gram_kernel(const ChipDev *__re
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
     // columns s .. SP of the staged tiles stay zero
-    for (int e = s * LD + tid; e < SP * LD; e += kThreads) {
+    for (int e = s * LD + tid; e < SP * LD; e += kSpThreads) {
         Ps[e] = T(0);
         APs[e] = T(0);
     }
@@ -283,10 +286,10 @@ __global__ __launch_bounds__(kThreads) void spmm_gram_kernel(const ChipDev *__re
             __syncthreads();
             // Gram phase: rows r + t feed MFMA step t for lane group lg (any
             // bijection of rows onto k slots works, since the product sums
-            // over rows)
+            // over rows); each wave takes TR / NW rows
 #pragma unroll
-            for (int rb = 0; rb < TR / 64; ++rb) {
-                const int r = wave * (TR / 4) + rb * 16 + lg * 4;
+            for (int rb = 0; rb < TR / (16 * NW); ++rb) {
+                const int r = wave * (TR / NW) + rb * 16 + lg * 4;
                 double u[NB][4], v[NB][4];
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
@@ -307,7 +310,8 @@ __global__ __launch_bounds__(kThreads) void spmm_gram_kernel(const ChipDev *__re
             __syncthreads();
         }
     }
-    publish_partial<NB, false>(acc, s, reinterpret_cast<double *>(smem), glb(cd.parts) + static_cast<size_t>(local) * s * s);
+    publish_partial<NB, false, NB * NB, kSpThreads>(acc, s, reinterpret_cast<double *>(smem),
+                                                    glb(cd.parts) + static_cast<size_t>(local) * s * s);
 }
 
 // gram = sum over the chip's partials, entry by entry in index order
@@ -430,6 +434,33 @@ __device__ __forceinline__ void publish_pivot(const double (&a)[E], int i, int j
     }
 }
 
+// out(i, j, sum_k fa(i, k) fb(k, j)) for an s x s product (s <= 64) on the
+// FP64 matrix cores: the factorisation kernel's waves take the 16 x 16 output
+// blocks in turn; operands outside s x s read as zero.
+template <class FA, class FB, class FO>
+__device__ __forceinline__ void small_gemm(int s, FA fa, FB fb, FO out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int nb = (s + 15) / 16;
+    for (int blk = wave; blk < nb * nb; blk += kFacThreads / 64) {
+        const int bi = blk / nb, bj = blk % nb;
+        const int i = bi * 16 + li, j = bj * 16 + li;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < s; k0 += 4) {
+            const int k = k0 + lg;
+            const double a = (i < s && k < s) ? fa(i, k) : 0.0;
+            const double b = (k < s && j < s) ? fb(k, j) : 0.0;
+            acc = mma64(a, b, acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int io = bi * 16 + mfma_row<true>(lg, r);
+            if (io < s && j < s) out(io, j, acc[r]);
+        }
+    }
+}
+
 // Factor the reduced Gram of the chip.  mode 0: delta -> M2 = delta^+, M1 = delta^+ C.
 // mode 1 / 2: W^T W -> S = D^{1/2} Lunit^T, Linv = D^{-1/2} E; C <- S C;
 // M3[k][j] = Linv[j][k] (Q = W S^+), M4[k][j] = S[j][k] (P = Q + P S^T);
@@ -439,8 +470,7 @@ __device__ __forceinline__ void publish_pivot(const double (&a)[E], int i, int j
 // Work layout: each of the 256 threads owns E consecutive entries of one row
 // of [G | I] in registers; per pivot the owners publish the pivot row (with
 // its reciprocal) and column into double-buffered LDS vectors, one barrier
-// per pivot.  The s x s products afterwards use the same row-segment
-// ownership with E / 2 outputs per thread.
+// per pivot.  The s x s products afterwards run on the FP64 matrix cores.
 // SP > 0 selects the one-wavefront elimination (s <= SP <= 32).
 template <int E, int SP>
 __global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__restrict__ cds, int s, double rel_thr,
@@ -451,7 +481,6 @@ __global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__re
     if (ctrl[kConverged]) return;
     const gptr<const double> __restrict__ gram = glb(static_cast<const double *>(cd.gram));
     const SmallG sm(cd.sm);
-    constexpr int E2 = E > 1 ? E / 2 : 1;
     constexpr int EA = SP > 0 ? 1 : E;  // register row segment of the LDS elimination
     extern __shared__ __align__(16) double lds[];
     const int ss = s * s, w = 2 * s;
@@ -544,68 +573,28 @@ __global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__re
     __syncthreads();
     int inactive = 0;
     for (int k = 0; k < s; ++k) inactive += active[k] ? 0 : 1;
-    // s x s outputs: thread owns row i2, columns j2 .. j2 + E2
-    const int tpr2 = (s + E2 - 1) / E2;
-    const int i2 = tid / tpr2, j2 = (tid % tpr2) * E2;
-    const bool live2 = i2 < s;
-    double acc[E2];
     if (mode == 0) {
-        // delta^+[i][j] = sum_{k >= max(i,j)} E[k][i] E[k][j] / d_k, E = right half
-#pragma unroll
-        for (int q = 0; q < E2; ++q) acc[q] = 0.0;
-        if (live2) {
-            for (int k = i2; k < s; ++k) {
-                const double c = A[k * w + s + i2] * dv[k];
-#pragma unroll
-                for (int q = 0; q < E2; ++q)
-                    acc[q] += c * A[k * w + s + j2 + q];  // columns >= s: padding, not stored
-            }
-#pragma unroll
-            for (int q = 0; q < E2; ++q) {
-                if (j2 + q < s) {
-                    const int e = i2 * s + j2 + q;
-                    G[e] = acc[q];
-                    sm.M2[e] = acc[q];
-                    sm.M2f[e] = static_cast<float>(acc[q]);
-                }
-            }
-        }
+        // delta^+ = E^T diag(dv) E (E = right half); M2 = delta^+, M1 = delta^+ C
+        small_gemm(
+            s, [&](int i, int k) { return A[k * w + s + i]; }, [&](int k, int j) { return dv[k] * A[k * w + s + j]; },
+            [&](int i, int j, double v) {
+                G[i * s + j] = v;
+                sm.M2[i * s + j] = v;
+                sm.M2f[i * s + j] = static_cast<float>(v);
+            });
         __syncthreads();
-        // M1 = delta^+ C
-#pragma unroll
-        for (int q = 0; q < E2; ++q) acc[q] = 0.0;
-        if (live2) {
-            for (int k = 0; k < s; ++k) {
-                const double c = G[i2 * s + k];
-#pragma unroll
-                for (int q = 0; q < E2; ++q)
-                    acc[q] += c * Cl[k * s + j2 + q];
-            }
-#pragma unroll
-            for (int q = 0; q < E2; ++q) {
-                if (j2 + q < s) {
-                    const int e = i2 * s + j2 + q;
-                    sm.M1[e] = acc[q];
-                    sm.M1f[e] = static_cast<float>(acc[q]);
-                }
-            }
-        }
+        small_gemm(
+            s, [&](int i, int k) { return G[i * s + k]; }, [&](int k, int j) { return Cl[k * s + j]; },
+            [&](int i, int j, double v) {
+                sm.M1[i * s + j] = v;
+                sm.M1f[i * s + j] = static_cast<float>(v);
+            });
         return;
     }
-    // S[i][k] = U[i][k] dv[i] (k >= i);  Cn = S C into G
-#pragma unroll
-    for (int q = 0; q < E2; ++q) acc[q] = 0.0;
-    if (live2) {
-        for (int k = i2; k < s; ++k) {
-            const double c = A[i2 * w + k];
-#pragma unroll
-            for (int q = 0; q < E2; ++q)
-                acc[q] += c * Cl[k * s + j2 + q];
-        }
-#pragma unroll
-        for (int q = 0; q < E2; ++q)
-            if (j2 + q < s) G[i2 * s + j2 + q] = acc[q] * dv[i2];
-    }
+    // Cn = S C into G, S[i][k] = U[i][k] dv[i] (k >= i)
+    small_gemm(
+        s, [&](int i, int k) { return k >= i ? A[i * w + k] * dv[i] : 0.0; },
+        [&](int k, int j) { return Cl[k * s + j]; }, [&](int i, int j, double v) { G[i * s + j] = v; });
     // M3[k][j] = Linv[j][k] = E[j][k] dv[j] (k <= j);  M4[k][j] = S[j][k] = U[j][k] dv[j] (k >= j)
     for (int e = tid; e < ss; e += kFacThreads) {
         const int k = e / s, j = e % s;
@@ -1248,7 +1237,8 @@ bko_status launch_row_kernels(int which, const Ctx &x, int init)
     const dim3 grid(static_cast<unsigned>(x.L->total_wgs)), block(kThreads);
     if (which == 0) {
         TimedLaunch tl(kSpmm, x.st);
-        hipLaunchKernelGGL((spmm_gram_kernel<T, NB>), grid, block, (spmm_gram_lds<T, NB>()), x.st, x.cds, x.tab, s);
+        hipLaunchKernelGGL((spmm_gram_kernel<T, NB>), grid, dim3(kSpThreads), (spmm_gram_lds<T, NB>()), x.st, x.cds,
+                           x.tab, s);
     } else if (which == 1) {
         TimedLaunch tl(kUpdate, x.st);
         hipLaunchKernelGGL((update_w_kernel<T, NB>), grid, block, 0, x.st, x.cds, x.tab, s, init);
