@@ -37,7 +37,7 @@ FP64_PEAK_TFLOPS = 78.6
 # FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads for a plain
 # device copy of known size (profiles/pmc_traffic_stack128x128x8.md).  Valid
 # only for the kernels as profiled there and the default workload.
-TRAFFIC_BYTES = {"combine": 7234.8e6, "update_w": 69.4e6, "update_dqp": 131.3e6}
+TRAFFIC_BYTES = {"combine": 7234.8e6}
 
 
 def parse():

@@ -66,7 +66,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 256;      // row kernels
 constexpr int kFacThreads = 256;   // factorisation kernel
 constexpr int kMaxS = 64;
-constexpr int kRedBlocks = 64;     // reducer workgroups per chip
+constexpr int kRedBlocks = 128;    // reducer workgroups per chip
 constexpr int kTileRows = 256;     // rows per tile of the row kernels (4 waves x 64)
 constexpr int kCtrlInts = 16;      // control words per chip
 
@@ -461,6 +461,30 @@ __device__ __forceinline__ void small_gemm(int s, FA fa, FB fb, FO out)
     }
 }
 
+// LDS of a workgroup that factors its chip's s x s Gram itself (s <= 32).
+struct FacScratch {
+    double A[2 * 32 * 32];  // [U | E] after the elimination, s x 2s
+    double G[32 * 32];
+    double Cl[32 * 32];
+    double dv[32];
+    int active[32];
+    int notconv;
+};
+
+// The calling workgroup factors gram (s <= SP <= 32): one wave eliminates
+// [G | I] into fs.A, then fs.dv = 1 / pivot (mode 0) or 1 / sqrt(pivot).
+// Every workgroup that calls this on the same Gram gets the same factors.
+template <int SP>
+__device__ void factor_small(gptr<const double> gram, int s, double rel_thr, int mode, FacScratch &fs)
+{
+    if (threadIdx.x < 64) wave_eliminate<SP>(gram, s, rel_thr, fs.A, fs.active);
+    __syncthreads();
+    const int w = 2 * s;
+    for (int k = threadIdx.x; k < s; k += kFacThreads)
+        fs.dv[k] = !fs.active[k] ? 0.0 : (mode == 0 ? 1.0 / fs.A[k * w + k] : 1.0 / sqrt(fs.A[k * w + k]));
+    __syncthreads();
+}
+
 // Factor the reduced Gram of the chip.  mode 0: delta -> M2 = delta^+, M1 = delta^+ C.
 // mode 1 / 2: W^T W -> S = D^{1/2} Lunit^T, Linv = D^{-1/2} E; C <- S C;
 // M3[k][j] = Linv[j][k] (Q = W S^+), M4[k][j] = S[j][k] (P = Q + P S^T);
@@ -827,6 +851,277 @@ __global__ __launch_bounds__(kThreads) void update_dqp_kernel(const ChipDev *__r
                 }
 #pragma unroll
                 for (int t = 0; t < KS; ++t) ap = MF<T>::mma(pa[t], M4[(4 * t + lg) * MST + colj], ap);
+                if (colj < s) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t idx = colj * ldw + r0 + mfma_row<kF64>(lg, r);
+                        D[idx] = ad[r];
+                        P[idx] = ap[r];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ fused factorisation + update (s <= 32)
+//
+// For s <= 32 the two s x s factorisations of an iteration run inside the
+// kernels that consume them: every workgroup factors the reduced Gram
+// itself (one wavefront, a few microseconds, identical results in every
+// workgroup), which removes two launches and their gaps from each iteration.
+// Workgroup 0 of the chip also publishes what later kernels need (M1 for the
+// D update, C, M3, the control words).
+
+// W <- W S^+ - AP delta^+ with delta^+ factored here (see update_w_kernel).
+template <class T, int NB>
+__global__ __launch_bounds__(kThreads) void update_w_fused_kernel(const ChipDev *__restrict__ cds,
+                                                                  const uint16_t *__restrict__ tab, int s,
+                                                                  double rel_thr)
+{
+    static_assert(NB <= 2, "fused factorisation is for s <= 32");
+    int local;
+    const ChipDev &cd = chip_of(cds, tab, local);
+    const int wgs = cd.wgs;
+    if (glb(cd.ctrl)[kConverged]) return;
+    using V = typename MF<T>::V;
+    constexpr bool kF64 = MF<T>::kF64;
+    constexpr int KS = 4 * NB;
+    constexpr int SP = 16 * NB;
+    constexpr int MST = SP + 1;
+    __shared__ T M3s[SP * MST];
+    __shared__ T M2s[SP * MST];  // -delta^+
+    __shared__ FacScratch fs;
+    const bool f64 = sizeof(T) == 8;
+    const SmallG sm(cd.sm);
+    {
+        T *const dst[1] = {M3s};
+        const gptr<const T> src[1] = {
+            glb(f64 ? reinterpret_cast<const T *>(cd.sm.M3) : reinterpret_cast<const T *>(cd.sm.M3f))};
+        const bool neg[1] = {false};
+        stage_small<T, SP, MST, 1>(dst, src, s, neg);
+        for (int e = threadIdx.x; e < SP * MST; e += kThreads) M2s[e] = T(0);
+    }
+    factor_small<SP>(glb(static_cast<const double *>(cd.gram)), s, rel_thr, 0, fs);
+    const int w = 2 * s;
+    // delta^+ = E^T diag(dv) E (E = right half of the eliminated [G | I])
+    small_gemm(
+        s, [&](int i, int k) { return fs.A[k * w + s + i]; }, [&](int k, int j) { return fs.dv[k] * fs.A[k * w + s + j]; },
+        [&](int i, int j, double v) {
+            M2s[i * MST + j] = static_cast<T>(-v);
+            fs.G[i * s + j] = v;
+        });
+    __syncthreads();
+    if (local == 0) {
+        // M1 = delta^+ C for this step's update of D
+        for (int e = threadIdx.x; e < s * s; e += kThreads) fs.Cl[e] = sm.C[e];
+        __syncthreads();
+        small_gemm(
+            s, [&](int i, int k) { return fs.G[i * s + k]; }, [&](int k, int j) { return fs.Cl[k * s + j]; },
+            [&](int i, int j, double v) {
+                sm.M1[i * s + j] = v;
+                sm.M1f[i * s + j] = static_cast<float>(v);
+            });
+        __syncthreads();
+    }
+    const gptr<T> __restrict__ W = glb(static_cast<T *>(cd.W));
+    const gptr<const T> __restrict__ AP = glb(static_cast<const T *>(cd.AP));
+    const int64_t ldw = cd.ldw;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    d4 g[NB * (NB + 1) / 2];
+#pragma unroll
+    for (int q = 0; q < NB * (NB + 1) / 2; ++q) g[q] = d4{0.0, 0.0, 0.0, 0.0};
+    const int64_t ntiles = ldw / kTileRows;
+    for (int64_t tile = local; tile < ntiles; tile += wgs) {
+        // FP32: the next 16-row block's operands load while this one computes
+        constexpr int NBUF = sizeof(T) == 4 ? 2 : 1;
+        T wa[NBUF][KS], aa[NBUF][KS];
+        auto load = [&](int rb, int b) {
+            const int64_t r0 = tile * kTileRows + wave * 64 + rb * 16;
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+                const int col = 4 * t + lg;
+                wa[b][t] = col < s ? W[col * ldw + r0 + li] : T(0);
+                aa[b][t] = col < s ? AP[col * ldw + r0 + li] : T(0);
+            }
+        };
+        if (NBUF == 2) load(0, 0);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            const int b = NBUF == 2 ? (rb & 1) : 0;
+            if (NBUF == 1) load(rb, 0);
+            else if (rb + 1 < 4) load(rb + 1, b ^ 1);
+            const int64_t r0 = tile * kTileRows + wave * 64 + rb * 16;
+            V wv[NB];
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+                const int colj = jb * 16 + li;
+                V acc;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] = T(0);
+#pragma unroll
+                for (int t = 0; t < KS; ++t) acc = MF<T>::mma(wa[b][t], M3s[(4 * t + lg) * MST + colj], acc);
+#pragma unroll
+                for (int t = 0; t < KS; ++t) acc = MF<T>::mma(aa[b][t], M2s[(4 * t + lg) * MST + colj], acc);
+                wv[jb] = acc;
+            }
+            // rows rb of W were read (this block's buffer); the next block's
+            // rows are different, so the new block can be written now
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+                const int colj = jb * 16 + li;
+                if (colj < s) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) W[colj * ldw + r0 + mfma_row<kF64>(lg, r)] = wv[jb][r];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int ab = 0; ab < NB; ++ab)
+#pragma unroll
+                    for (int bb = ab; bb < NB; ++bb)
+                        g[ublock<NB>(ab, bb)] = mma64(static_cast<double>(wv[ab][r]), static_cast<double>(wv[bb][r]),
+                                                      g[ublock<NB>(ab, bb)]);
+        }
+    }
+    // the factor scratch is dead here: it holds the partial's reduction
+    publish_partial<NB, true>(g, s, fs.A, glb(cd.parts) + static_cast<size_t>(local) * s * s);
+}
+
+// D += P M1; P = W S^+ + P S^T with W^T W = S^T S factored here (mode 1, or
+// 2 for the first QR of an inner solve, which is not counted as an
+// iteration); workgroup 0 updates C = S C, tests convergence on it and
+// publishes S^+ for the next step.
+template <class T, int NB>
+__global__ __launch_bounds__(kThreads) void update_dqp_fused_kernel(const ChipDev *__restrict__ cds,
+                                                                    const uint16_t *__restrict__ tab, int s,
+                                                                    double rel_thr, int mode)
+{
+    static_assert(NB <= 2, "fused factorisation is for s <= 32");
+    int local;
+    const ChipDev &cd = chip_of(cds, tab, local);
+    const int wgs = cd.wgs;
+    const gptr<int> ctrl = glb(cd.ctrl);
+    if (ctrl[kStop]) return;
+    using V = typename MF<T>::V;
+    constexpr bool kF64 = MF<T>::kF64;
+    constexpr int KS = 4 * NB;
+    constexpr int SP = 16 * NB;
+    constexpr int MST = SP + 1;
+    __shared__ T M1[SP * MST];
+    __shared__ T M3[SP * MST];
+    __shared__ T M4[SP * MST];
+    __shared__ FacScratch fs;
+    const bool f64 = sizeof(T) == 8;
+    const SmallG sm(cd.sm);
+    {
+        T *const dst[1] = {M1};
+        const gptr<const T> src[1] = {
+            glb(f64 ? reinterpret_cast<const T *>(cd.sm.M1) : reinterpret_cast<const T *>(cd.sm.M1f))};
+        const bool neg[1] = {false};
+        stage_small<T, SP, MST, 1>(dst, src, s, neg);
+    }
+    factor_small<SP>(glb(static_cast<const double *>(cd.gram)), s, rel_thr, mode, fs);
+    const int w = 2 * s;
+    // M3[k][j] = S^+[k][j] = E[j][k] dv[j] (k <= j);  M4[k][j] = S[j][k] = U[j][k] dv[j] (k >= j)
+    for (int e = threadIdx.x; e < SP * MST; e += kThreads) {
+        const int k = e / MST, j = e % MST;
+        const bool in = k < s && j < s;
+        const double m3 = (in && k <= j) ? fs.A[j * w + s + k] * fs.dv[j] : 0.0;
+        const double m4 = (in && k >= j) ? fs.A[j * w + k] * fs.dv[j] : 0.0;
+        M3[e] = static_cast<T>(m3);
+        M4[e] = static_cast<T>(m4);
+        if (local == 0 && in) {
+            sm.M3[k * s + j] = m3;
+            sm.M3f[k * s + j] = static_cast<float>(m3);
+            sm.M4[k * s + j] = m4;
+            sm.M4f[k * s + j] = static_cast<float>(m4);
+        }
+    }
+    if (local == 0) {
+        // C <- S C, S[i][k] = U[i][k] dv[i] (k >= i); convergence on ||C e_j||
+        for (int e = threadIdx.x; e < s * s; e += kThreads) fs.Cl[e] = sm.C[e];
+        if (threadIdx.x == 0) fs.notconv = 0;
+        __syncthreads();
+        small_gemm(
+            s, [&](int i, int k) { return k >= i ? fs.A[i * w + k] * fs.dv[i] : 0.0; },
+            [&](int k, int j) { return fs.Cl[k * s + j]; }, [&](int i, int j, double v) { fs.G[i * s + j] = v; });
+        __syncthreads();
+        for (int j = threadIdx.x; j < s; j += kThreads) {
+            double n0 = 0.0, n1 = 0.0;
+            int r = 0;
+            for (; r + 1 <= j; r += 2) {
+                n0 += fs.G[r * s + j] * fs.G[r * s + j];
+                n1 += fs.G[(r + 1) * s + j] * fs.G[(r + 1) * s + j];
+            }
+            if (r <= j) n0 += fs.G[r * s + j] * fs.G[r * s + j];
+            if (!(sqrt(n0 + n1) <= sm.th[j])) atomicAdd(&fs.notconv, 1);
+        }
+        for (int e = threadIdx.x; e < s * s; e += kThreads) sm.C[e] = fs.G[e];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int inactive = 0;
+            for (int k = 0; k < s; ++k) inactive += fs.active[k] ? 0 : 1;
+            ctrl[kIters] += mode == 1 ? 1 : 0;
+            ctrl[kDeflated] = inactive;
+            if (inactive == s) ctrl[kAllDeflated] = 1;
+            if (fs.notconv == 0 || inactive == s) ctrl[kConverged] = 1;
+        }
+    }
+    __syncthreads();
+    const gptr<T> __restrict__ D = glb(static_cast<T *>(cd.Dv));
+    const gptr<T> __restrict__ P = glb(static_cast<T *>(cd.P));
+    const gptr<const T> __restrict__ W = glb(static_cast<const T *>(cd.W));
+    const int64_t ldw = cd.ldw;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t ntiles = ldw / kTileRows;
+    for (int64_t tile = local; tile < ntiles; tile += wgs) {
+        // FP32: the next 16-row block's operands load while this one computes
+        // (FP64 keeps one buffer: two would halve the resident waves)
+        constexpr int NBUF = sizeof(T) == 4 ? 2 : 1;
+        T pa[NBUF][KS], wa[NBUF][KS], dd[NBUF][NB][4];
+        auto load = [&](int rb, int b) {
+            const int64_t r0 = tile * kTileRows + wave * 64 + rb * 16;
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+                const int col = 4 * t + lg;
+                pa[b][t] = col < s ? P[col * ldw + r0 + li] : T(0);
+                wa[b][t] = col < s ? W[col * ldw + r0 + li] : T(0);
+            }
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+                const int colj = jb * 16 + li;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) dd[b][jb][r] = colj < s ? D[colj * ldw + r0 + mfma_row<kF64>(lg, r)] : T(0);
+            }
+        };
+        if (NBUF == 2) load(0, 0);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            const int b = NBUF == 2 ? (rb & 1) : 0;
+            if (NBUF == 1) load(rb, 0);
+            else if (rb + 1 < 4) load(rb + 1, b ^ 1);
+            const int64_t r0 = tile * kTileRows + wave * 64 + rb * 16;
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+                const int colj = jb * 16 + li;
+                V ad, ap;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    ad[r] = dd[b][jb][r];
+                    ap[r] = T(0);
+                }
+#pragma unroll
+                for (int t = 0; t < KS; ++t) {
+                    const int k = 4 * t + lg;
+                    ad = MF<T>::mma(pa[b][t], M1[k * MST + colj], ad);
+                    ap = MF<T>::mma(wa[b][t], M3[k * MST + colj], ap);
+                }
+#pragma unroll
+                for (int t = 0; t < KS; ++t) ap = MF<T>::mma(pa[b][t], M4[(4 * t + lg) * MST + colj], ap);
                 if (colj < s) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
@@ -1306,12 +1601,57 @@ bko_status launch_reduce_factor(const Ctx &x, double rel_thr, int mode)
     return BKO_OK;
 }
 
+// s <= 32: the factorisations run inside the update kernels
+inline bool fused_factor(int s) { return s <= 32; }
+
+bko_status launch_reduce(const Ctx &x)
+{
+    const int ss = x.L->s * x.L->s;
+    TimedLaunch tl(kSmall, x.st);
+    const unsigned rblocks = static_cast<unsigned>(std::min(kRedBlocks, ss));
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(rblocks, static_cast<unsigned>(x.L->nchips)), dim3(kThreads), 0, x.st,
+                       x.cds, ss);
+    BKO_HIP(hipGetLastError());
+    return BKO_OK;
+}
+
+// which 1: W update with delta^+ factored in; 2: D, P update with the QR of
+// W factored in (mode 1, or 2 for an inner solve's first QR)
+template <class T, int NB>
+bko_status launch_fused_kernel(int which, const Ctx &x, double rel_thr, int mode)
+{
+    const dim3 grid(static_cast<unsigned>(x.L->total_wgs)), block(kThreads);
+    const int s = x.L->s;
+    if (which == 1) {
+        TimedLaunch tl(kUpdate, x.st);
+        hipLaunchKernelGGL((update_w_fused_kernel<T, NB>), grid, block, 0, x.st, x.cds, x.tab, s, rel_thr);
+    } else {
+        TimedLaunch tl(::bko::kUpdateDQP, x.st);
+        hipLaunchKernelGGL((update_dqp_fused_kernel<T, NB>), grid, block, 0, x.st, x.cds, x.tab, s, rel_thr, mode);
+    }
+    BKO_HIP(hipGetLastError());
+    return BKO_OK;
+}
+
+template <class T>
+bko_status launch_fused(int which, const Ctx &x, double rel_thr, int mode)
+{
+    return nb_for(x.L->s) == 1 ? launch_fused_kernel<T, 1>(which, x, rel_thr, mode)
+                               : launch_fused_kernel<T, 2>(which, x, rel_thr, mode);
+}
+
 // One block iteration for every chip of the batch.
 template <class T>
 bko_status iteration(const Ctx &x, double rel_thr)
 {
     bko_status rc;
     if ((rc = launch_row<T>(0, x, 0)) != BKO_OK) return rc;
+    if (fused_factor(x.L->s)) {
+        if ((rc = launch_reduce(x)) != BKO_OK) return rc;
+        if ((rc = launch_fused<T>(1, x, rel_thr, 0)) != BKO_OK) return rc;
+        if ((rc = launch_reduce(x)) != BKO_OK) return rc;
+        return launch_fused<T>(2, x, rel_thr, 1);
+    }
     if ((rc = launch_reduce_factor(x, rel_thr, 0)) != BKO_OK) return rc;
     if ((rc = launch_row<T>(1, x, 0)) != BKO_OK) return rc;
     if ((rc = launch_reduce_factor(x, rel_thr, 1)) != BKO_OK) return rc;
@@ -1518,8 +1858,13 @@ bko_status batch_solve_t(const Layout &L, void *work, const double *const *B, co
                            x.tab, s);
         BKO_HIP(hipGetLastError());
         if ((rc = launch_row<T>(1, x, 1)) != BKO_OK) return rc;
-        if ((rc = launch_reduce_factor(x, rel_thr, 2)) != BKO_OK) return rc;
-        if ((rc = launch_row<T>(2, x, 0)) != BKO_OK) return rc;
+        if (fused_factor(s)) {
+            if ((rc = launch_reduce(x)) != BKO_OK) return rc;
+            if ((rc = launch_fused<T>(2, x, rel_thr, 2)) != BKO_OK) return rc;
+        } else {
+            if ((rc = launch_reduce_factor(x, rel_thr, 2)) != BKO_OK) return rc;
+            if ((rc = launch_row<T>(2, x, 0)) != BKO_OK) return rc;
+        }
         int budget = 0;
         for (int c = 0; c < nc; ++c)
             if (!cs[c].done) budget = std::max(budget, max_iter - cs[c].info.iters);
