@@ -153,36 +153,65 @@ __device__ inline const ChipDev &chip_of(const ChipDev *cds, const uint16_t *tab
 
 // ------------------------------------------------------------------ Gram partials
 
-// Sum the four waves' 16x16 FP64 blocks into an s x s partial in LDS (lds:
-// at least s * s doubles) and write it to out.  kSym: only upper blocks were
-// formed.
-template <int NB, bool kSym, int NBLK, int kNT = kThreads>
+// Row and column block of Gram block q: the upper blocks (a <= b) in order
+// when kSym, else all blocks row by row.
+template <int NB, bool kSym> __device__ __forceinline__ void gram_block(int q, int &a, int &b)
+{
+    if (!kSym) {
+        a = q / NB;
+        b = q % NB;
+        return;
+    }
+    a = 0;
+    while (q >= NB - a) {
+        q -= NB - a;
+        ++a;
+    }
+    b = a + q;
+}
+
+// LDS doubles publish_partial needs: each wave stores CB blocks per round.
+template <int kNT> __host__ __device__ constexpr int publish_lds(int cb) { return cb * (kNT / 64) * 4 * 64; }
+
+// Sum the waves' 16x16 FP64 Gram blocks and write the s x s partial to out.
+// Each round, every wave stores CB of its blocks to its own LDS slots (lane
+// fastest, no bank conflicts); after one barrier wave c % NW sums block c
+// over the waves in wave order and writes it.  kSym: only upper blocks were
+// formed; each is also written transposed.  lds: publish_lds<kNT>(CB)
+// doubles.
+template <int NB, bool kSym, int NBLK, int kNT = kThreads, int CB = (NBLK < 4 ? NBLK : 4)>
 __device__ void publish_partial(const d4 (&g)[NBLK], int s, double *lds, gptr<double> out)
 {
-    const int ss = s * s;
+    constexpr int NW = kNT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    for (int e = threadIdx.x; e < ss; e += kNT) lds[e] = 0.0;
-    __syncthreads();
-    for (int wv = 0; wv < kNT / 64; ++wv) {
-        if (wave == wv) {
 #pragma unroll
-            for (int a = 0; a < NB; ++a)
+    for (int q0 = 0; q0 < NBLK; q0 += CB) {
+        if (q0 > 0) __syncthreads();
 #pragma unroll
-                for (int b = kSym ? a : 0; b < NB; ++b)
+        for (int c = 0; c < CB; ++c)
+            if (q0 + c < NBLK) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int i = a * 16 + mfma_row<true>(lg, r), j = b * 16 + li;
-                        if (i < s && j < s) {
-                            const double v = kSym ? g[ublock<NB>(a, b)][r] : g[a * NB + b][r];
-                            lds[i * s + j] += v;
-                            if (kSym && a != b) lds[j * s + i] += v;
-                        }
-                    }
-        }
+                for (int r = 0; r < 4; ++r) lds[((wave * CB + c) * 4 + r) * 64 + lane] = g[q0 + c][r];
+            }
         __syncthreads();
+        for (int c = wave; c < CB && q0 + c < NBLK; c += NW) {
+            int a, b;
+            gram_block<NB, kSym>(q0 + c, a, b);
+            const int j = b * 16 + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double v = lds[(c * 4 + r) * 64 + lane];
+#pragma unroll
+                for (int wv = 1; wv < NW; ++wv) v += lds[((wv * CB + c) * 4 + r) * 64 + lane];
+                const int i = a * 16 + mfma_row<true>(lg, r);
+                if (i < s && j < s) {
+                    out[i * s + j] = v;
+                    if (kSym && a != b) out[j * s + i] = v;
+                }
+            }
+        }
     }
-    for (int e = threadIdx.x; e < ss; e += kNT) out[e] = lds[e];
 }
 
 // ------------------------------------------------------------------ stencil product + Gram
@@ -310,6 +339,8 @@ __global__ __launch_bounds__(kSpThreads) void spmm_gram_kernel(const ChipDev *__
             __syncthreads();
         }
     }
+    static_assert(spmm_gram_lds<T, NB>() >= sizeof(double) * publish_lds<kSpThreads>(NB * NB < 4 ? NB * NB : 4),
+                  "publish_partial needs more LDS than the staged tiles");
     publish_partial<NB, false, NB * NB, kSpThreads>(acc, s, reinterpret_cast<double *>(smem),
                                                     glb(cd.parts) + static_cast<size_t>(local) * s * s);
 }
@@ -375,15 +406,16 @@ __device__ __forceinline__ double recip(double p)
 // Masked LDL^T elimination of [G | I] by one wavefront, for s <= SP <= 32:
 // lane c holds column c of the 2 SP columns in registers; each pivot row of
 // the column is broadcast with readlane, so no LDS traffic or barrier per
-// pivot.  Indices s <= i < SP are decoupled padding with pivot gmax.
-// Writes the result (A[i][j], j < 2s: left half U, right half E) to LDS.
+// pivot.  Indices s <= i < SP are decoupled padding with pivot gmax.  g is
+// an LDS copy of the Gram with row stride ld; the result (A[i][j], j < 2s:
+// left half U, right half E) goes to LDS and may overwrite g (every read of
+// g precedes the first write).
 template <int SP>
-__device__ __forceinline__ void wave_eliminate(const gptr<const double> __restrict__ gram, int s, double rel_thr,
-                                               double *A, int *active)
+__device__ __forceinline__ void wave_eliminate(const double *g, int ld, int s, double rel_thr, double *A, int *active)
 {
     const int lane = threadIdx.x & 63;
     const int w = 2 * s;
-    double gmax = lane < s ? gram[lane * s + lane] : 0.0;
+    double gmax = lane < s ? g[lane * ld + lane] : 0.0;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, off));
     const double thr = rel_thr * gmax;
@@ -391,7 +423,7 @@ __device__ __forceinline__ void wave_eliminate(const gptr<const double> __restri
 #pragma unroll
     for (int i = 0; i < SP; ++i) {
         if (lane < SP)
-            a[i] = (i < s && lane < s) ? 0.5 * (gram[i * s + lane] + gram[lane * s + i]) : (i == lane ? gmax : 0.0);
+            a[i] = (i < s && lane < s) ? 0.5 * (g[i * ld + lane] + g[lane * ld + i]) : (i == lane ? gmax : 0.0);
         else
             a[i] = (i == lane - SP) ? 1.0 : 0.0;
     }
@@ -463,7 +495,7 @@ __device__ __forceinline__ void small_gemm(int s, FA fa, FB fb, FO out)
 
 // LDS of a workgroup that factors its chip's s x s Gram itself (s <= 32).
 struct FacScratch {
-    double A[2 * 32 * 32];  // [U | E] after the elimination, s x 2s
+    double A[2 * 32 * 32];  // the Gram (row stride s + 1), then [U | E] after the elimination, s x 2s
     double G[32 * 32];
     double Cl[32 * 32];
     double dv[32];
@@ -471,13 +503,40 @@ struct FacScratch {
     int notconv;
 };
 
-// The calling workgroup factors gram (s <= SP <= 32): one wave eliminates
-// [G | I] into fs.A, then fs.dv = 1 / pivot (mode 0) or 1 / sqrt(pivot).
-// Every workgroup that calls this on the same Gram gets the same factors.
-template <int SP>
-__device__ void factor_small(gptr<const double> gram, int s, double rel_thr, int mode, FacScratch &fs)
+// The Gram entries this thread stages: fetched into registers first so that
+// the workgroup's other loads can be issued behind them.
+constexpr int kGramRegs = 32 * 32 / kThreads;
+__device__ __forceinline__ void gram_fetch(gptr<const double> gram, int s, double (&v)[kGramRegs])
 {
-    if (threadIdx.x < 64) wave_eliminate<SP>(gram, s, rel_thr, fs.A, fs.active);
+    const int ss = s * s;
+#pragma unroll
+    for (int q = 0; q < kGramRegs; ++q) {
+        const int e = threadIdx.x + q * kThreads;
+        v[q] = e < ss ? gram[e] : 0.0;
+    }
+}
+
+__device__ __forceinline__ void gram_stash(const double (&v)[kGramRegs], int s, FacScratch &fs)
+{
+    const int ss = s * s;
+#pragma unroll
+    for (int q = 0; q < kGramRegs; ++q) {
+        const int e = threadIdx.x + q * kThreads;
+        if (e < ss) fs.A[(e / s) * (s + 1) + e % s] = v[q];
+    }
+}
+
+// The calling workgroup factors the Gram it stashed in fs.A (s <= SP <= 32;
+// the workgroup has synchronised since): wave 0 eliminates [G | I] into
+// fs.A while the other waves run overlap(), then fs.dv = 1 / pivot (mode 0)
+// or 1 / sqrt(pivot).  Every workgroup that calls this on the same Gram gets
+// the same factors.
+template <int SP, class F>
+__device__ __forceinline__ void factor_small(int s, double rel_thr, int mode, FacScratch &fs, F overlap)
+{
+    static_assert(kFacThreads == kThreads, "the fused kernels factor with their own workgroup");
+    if (threadIdx.x < 64) wave_eliminate<SP>(fs.A, s + 1, s, rel_thr, fs.A, fs.active);
+    else overlap();
     __syncthreads();
     const int w = 2 * s;
     for (int k = threadIdx.x; k < s; k += kFacThreads)
@@ -495,8 +554,9 @@ __device__ void factor_small(gptr<const double> gram, int s, double rel_thr, int
 // of [G | I] in registers; per pivot the owners publish the pivot row (with
 // its reciprocal) and column into double-buffered LDS vectors, one barrier
 // per pivot.  The s x s products afterwards run on the FP64 matrix cores.
-// SP > 0 selects the one-wavefront elimination (s <= SP <= 32).
-template <int E, int SP>
+// The Gram is staged in LDS first by coalesced loads.  (s <= 32 factors
+// inside the update kernels instead.)
+template <int E>
 __global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__restrict__ cds, int s, double rel_thr,
                                                              int mode)
 {
@@ -505,7 +565,7 @@ __global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__re
     if (ctrl[kConverged]) return;
     const gptr<const double> __restrict__ gram = glb(static_cast<const double *>(cd.gram));
     const SmallG sm(cd.sm);
-    constexpr int EA = SP > 0 ? 1 : E;  // register row segment of the LDS elimination
+    constexpr int EA = E;  // register row segment
     extern __shared__ __align__(16) double lds[];
     const int ss = s * s, w = 2 * s;
     // every region is padded by E doubles so that a row segment can be read
@@ -529,19 +589,27 @@ __global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__re
         rowbuf[2 * w + E + e] = 0.0;
     }
     {
-        // all loads of C in flight before the LDS stores
+        // all loads of C and of the Gram in flight before the LDS stores
         constexpr int IT = kMaxS * kMaxS / kFacThreads;
-        double cv[IT];
+        double cv[IT], gv[IT];
 #pragma unroll
-        for (int i = 0; i < IT; ++i) cv[i] = tid + i * kFacThreads < ss ? sm.C[tid + i * kFacThreads] : 0.0;
+        for (int i = 0; i < IT; ++i) {
+            const int e = tid + i * kFacThreads;
+            cv[i] = e < ss ? sm.C[e] : 0.0;
+            gv[i] = e < ss ? gram[e] : 0.0;
+        }
 #pragma unroll
-        for (int i = 0; i < IT; ++i)
-            if (tid + i * kFacThreads < ss) Cl[tid + i * kFacThreads] = cv[i];
+        for (int i = 0; i < IT; ++i) {
+            const int e = tid + i * kFacThreads;
+            if (e < ss) {
+                Cl[e] = cv[i];
+                G[e] = gv[i];
+            }
+        }
     }
     if (tid == 0) notconv = 0;
-    if constexpr (SP > 0) {
-        if (tid < 64) wave_eliminate<SP>(gram, s, rel_thr, A, active);
-    } else {
+    __syncthreads();
+    {
         const int tpr = (w + EA - 1) / EA;
         const int i = tid / tpr, j0 = (tid % tpr) * EA;
         const bool live = i < s;
@@ -550,10 +618,10 @@ __global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__re
         for (int q = 0; q < EA; ++q) {
             const int j = j0 + q;
             a[q] = 0.0;
-            if (live && j < w) a[q] = j < s ? 0.5 * (gram[i * s + j] + gram[j * s + i]) : (j - s == i ? 1.0 : 0.0);
+            if (live && j < w) a[q] = j < s ? 0.5 * (G[i * s + j] + G[j * s + i]) : (j - s == i ? 1.0 : 0.0);
         }
         if (tid < 64) {
-            double v = tid < s ? gram[tid * s + tid] : 0.0;
+            double v = tid < s ? G[tid * s + tid] : 0.0;
             for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
             if (tid == 0) gmax = v;
         }
@@ -783,6 +851,7 @@ __global__ __launch_bounds__(kThreads) void update_w_kernel(const ChipDev *__res
                                                       g[ublock<NB>(ab, bb)]);
         }
     }
+    static_assert(kMaxS * kMaxS >= publish_lds<kThreads>(4), "publish_partial LDS");
     publish_partial<NB, true>(g, s, lds, glb(cd.parts) + static_cast<size_t>(local) * s * s);
 }
 
@@ -868,10 +937,20 @@ __global__ __launch_bounds__(kThreads) void update_dqp_kernel(const ChipDev *__r
 //
 // For s <= 32 the two s x s factorisations of an iteration run inside the
 // kernels that consume them: every workgroup factors the reduced Gram
-// itself (one wavefront, a few microseconds, identical results in every
-// workgroup), which removes two launches and their gaps from each iteration.
-// Workgroup 0 of the chip also publishes what later kernels need (M1 for the
-// D update, C, M3, the control words).
+// itself (one wavefront, identical results in every workgroup), which
+// removes two launches and their gaps from each iteration.  Workgroup 0 of
+// the chip also publishes what later kernels need (M1 for the D update, C,
+// M3, the control words).
+//
+// The factorisation's latency is hidden where the data allow: the Gram is
+// fetched first, the workgroup's first row blocks are loaded behind it, and
+// while wave 0 eliminates, waves 1..3 do the part of their update that does
+// not depend on the new factors (W S^+ here, D += P M1 in update_dqp); wave
+// 0 does its part after the elimination.
+
+// 16-row blocks per wave held in registers at once by the fused kernels
+// (FP64 holds fewer, to keep two waves per SIMD).
+template <class T, bool kW> constexpr int fused_rows() { return sizeof(T) == 4 ? 4 : (kW ? 1 : 2); }
 
 // W <- W S^+ - AP delta^+ with delta^+ factored here (see update_w_kernel).
 template <class T, int NB>
@@ -889,11 +968,51 @@ __global__ __launch_bounds__(kThreads) void update_w_fused_kernel(const ChipDev 
     constexpr int KS = 4 * NB;
     constexpr int SP = 16 * NB;
     constexpr int MST = SP + 1;
+    constexpr int PRE = fused_rows<T, true>();
+    constexpr int NG = 4 / PRE;
     __shared__ T M3s[SP * MST];
     __shared__ T M2s[SP * MST];  // -delta^+
     __shared__ FacScratch fs;
     const bool f64 = sizeof(T) == 8;
     const SmallG sm(cd.sm);
+    const gptr<T> __restrict__ W = glb(static_cast<T *>(cd.W));
+    const gptr<const T> __restrict__ AP = glb(static_cast<const T *>(cd.AP));
+    const int64_t ldw = cd.ldw;
+    const int64_t ntiles = ldw / kTileRows;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    T wa[PRE][KS], aa[PRE][KS];
+    V wm[PRE][NB];  // W S^+ of the held row blocks
+    auto load = [&](int64_t tile, int gi) {
+#pragma unroll
+        for (int p = 0; p < PRE; ++p) {
+            const int64_t r0 = tile * kTileRows + wave * 64 + (gi * PRE + p) * 16;
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+                const int col = 4 * t + lg;
+                wa[p][t] = col < s ? W[col * ldw + r0 + li] : T(0);
+                aa[p][t] = col < s ? AP[col * ldw + r0 + li] : T(0);
+            }
+        }
+    };
+    auto part_w = [&]() {
+#pragma unroll
+        for (int p = 0; p < PRE; ++p)
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+                const int colj = jb * 16 + li;
+                V acc;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] = T(0);
+#pragma unroll
+                for (int t = 0; t < KS; ++t) acc = MF<T>::mma(wa[p][t], M3s[(4 * t + lg) * MST + colj], acc);
+                wm[p][jb] = acc;
+            }
+    };
+    double gv[kGramRegs];
+    gram_fetch(glb(static_cast<const double *>(cd.gram)), s, gv);
+    const bool first = local < ntiles;
+    if (first) load(local, 0);
     {
         T *const dst[1] = {M3s};
         const gptr<const T> src[1] = {
@@ -902,7 +1021,12 @@ __global__ __launch_bounds__(kThreads) void update_w_fused_kernel(const ChipDev 
         stage_small<T, SP, MST, 1>(dst, src, s, neg);
         for (int e = threadIdx.x; e < SP * MST; e += kThreads) M2s[e] = T(0);
     }
-    factor_small<SP>(glb(static_cast<const double *>(cd.gram)), s, rel_thr, 0, fs);
+    gram_stash(gv, s, fs);
+    __syncthreads();
+    factor_small<SP>(s, rel_thr, 0, fs, [&] {
+        if (first) part_w();
+    });
+    if (wave == 0 && first) part_w();
     const int w = 2 * s;
     // delta^+ = E^T diag(dv) E (E = right half of the eliminated [G | I])
     small_gemm(
@@ -924,70 +1048,51 @@ __global__ __launch_bounds__(kThreads) void update_w_fused_kernel(const ChipDev 
             });
         __syncthreads();
     }
-    const gptr<T> __restrict__ W = glb(static_cast<T *>(cd.W));
-    const gptr<const T> __restrict__ AP = glb(static_cast<const T *>(cd.AP));
-    const int64_t ldw = cd.ldw;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int li = lane & 15, lg = lane >> 4;
     d4 g[NB * (NB + 1) / 2];
 #pragma unroll
     for (int q = 0; q < NB * (NB + 1) / 2; ++q) g[q] = d4{0.0, 0.0, 0.0, 0.0};
-    const int64_t ntiles = ldw / kTileRows;
     for (int64_t tile = local; tile < ntiles; tile += wgs) {
-        // FP32: the next 16-row block's operands load while this one computes
-        constexpr int NBUF = sizeof(T) == 4 ? 2 : 1;
-        T wa[NBUF][KS], aa[NBUF][KS];
-        auto load = [&](int rb, int b) {
-            const int64_t r0 = tile * kTileRows + wave * 64 + rb * 16;
 #pragma unroll
-            for (int t = 0; t < KS; ++t) {
-                const int col = 4 * t + lg;
-                wa[b][t] = col < s ? W[col * ldw + r0 + li] : T(0);
-                aa[b][t] = col < s ? AP[col * ldw + r0 + li] : T(0);
+        for (int gi = 0; gi < NG; ++gi) {
+            if (tile != local || gi != 0) {
+                load(tile, gi);
+                part_w();
             }
-        };
-        if (NBUF == 2) load(0, 0);
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
-            const int b = NBUF == 2 ? (rb & 1) : 0;
-            if (NBUF == 1) load(rb, 0);
-            else if (rb + 1 < 4) load(rb + 1, b ^ 1);
-            const int64_t r0 = tile * kTileRows + wave * 64 + rb * 16;
-            V wv[NB];
+            for (int p = 0; p < PRE; ++p) {
+                const int64_t r0 = tile * kTileRows + wave * 64 + (gi * PRE + p) * 16;
+                V wv[NB];
 #pragma unroll
-            for (int jb = 0; jb < NB; ++jb) {
-                const int colj = jb * 16 + li;
-                V acc;
+                for (int jb = 0; jb < NB; ++jb) {
+                    const int colj = jb * 16 + li;
+                    V acc = wm[p][jb];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r] = T(0);
-#pragma unroll
-                for (int t = 0; t < KS; ++t) acc = MF<T>::mma(wa[b][t], M3s[(4 * t + lg) * MST + colj], acc);
-#pragma unroll
-                for (int t = 0; t < KS; ++t) acc = MF<T>::mma(aa[b][t], M2s[(4 * t + lg) * MST + colj], acc);
-                wv[jb] = acc;
-            }
-            // rows rb of W were read (this block's buffer); the next block's
-            // rows are different, so the new block can be written now
-#pragma unroll
-            for (int jb = 0; jb < NB; ++jb) {
-                const int colj = jb * 16 + li;
-                if (colj < s) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) W[colj * ldw + r0 + mfma_row<kF64>(lg, r)] = wv[jb][r];
+                    for (int t = 0; t < KS; ++t) acc = MF<T>::mma(aa[p][t], M2s[(4 * t + lg) * MST + colj], acc);
+                    wv[jb] = acc;
                 }
+                // this wave loaded these rows of W before: write the new block
+#pragma unroll
+                for (int jb = 0; jb < NB; ++jb) {
+                    const int colj = jb * 16 + li;
+                    if (colj < s) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) W[colj * ldw + r0 + mfma_row<kF64>(lg, r)] = wv[jb][r];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int ab = 0; ab < NB; ++ab)
+#pragma unroll
+                        for (int bb = ab; bb < NB; ++bb)
+                            g[ublock<NB>(ab, bb)] = mma64(static_cast<double>(wv[ab][r]),
+                                                          static_cast<double>(wv[bb][r]), g[ublock<NB>(ab, bb)]);
             }
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int ab = 0; ab < NB; ++ab)
-#pragma unroll
-                    for (int bb = ab; bb < NB; ++bb)
-                        g[ublock<NB>(ab, bb)] = mma64(static_cast<double>(wv[ab][r]), static_cast<double>(wv[bb][r]),
-                                                      g[ublock<NB>(ab, bb)]);
         }
     }
     // the factor scratch is dead here: it holds the partial's reduction
-    publish_partial<NB, true>(g, s, fs.A, glb(cd.parts) + static_cast<size_t>(local) * s * s);
+    static_assert(sizeof(FacScratch) >= sizeof(double) * publish_lds<kThreads>(3), "publish_partial LDS");
+    publish_partial<NB, true>(g, s, reinterpret_cast<double *>(&fs), glb(cd.parts) + static_cast<size_t>(local) * s * s);
 }
 
 // D += P M1; P = W S^+ + P S^T with W^T W = S^T S factored here (mode 1, or
@@ -1010,12 +1115,65 @@ __global__ __launch_bounds__(kThreads) void update_dqp_fused_kernel(const ChipDe
     constexpr int KS = 4 * NB;
     constexpr int SP = 16 * NB;
     constexpr int MST = SP + 1;
+    constexpr int PRE = fused_rows<T, false>();
+    constexpr int NG = 4 / PRE;
     __shared__ T M1[SP * MST];
     __shared__ T M3[SP * MST];
     __shared__ T M4[SP * MST];
     __shared__ FacScratch fs;
     const bool f64 = sizeof(T) == 8;
     const SmallG sm(cd.sm);
+    const gptr<T> __restrict__ D = glb(static_cast<T *>(cd.Dv));
+    const gptr<T> __restrict__ P = glb(static_cast<T *>(cd.P));
+    const gptr<const T> __restrict__ W = glb(static_cast<const T *>(cd.W));
+    const int64_t ldw = cd.ldw;
+    const int64_t ntiles = ldw / kTileRows;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    T pa[PRE][KS], wa[PRE][KS], dd[PRE][NB][4];
+    auto load = [&](int64_t tile, int gi) {
+#pragma unroll
+        for (int p = 0; p < PRE; ++p) {
+            const int64_t r0 = tile * kTileRows + wave * 64 + (gi * PRE + p) * 16;
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+                const int col = 4 * t + lg;
+                pa[p][t] = col < s ? P[col * ldw + r0 + li] : T(0);
+                wa[p][t] = col < s ? W[col * ldw + r0 + li] : T(0);
+            }
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+                const int colj = jb * 16 + li;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    dd[p][jb][r] = colj < s ? D[colj * ldw + r0 + mfma_row<kF64>(lg, r)] : T(0);
+            }
+        }
+    };
+    // D += P M1 for the held row blocks (independent of this step's factors)
+    auto part_d = [&](int64_t tile, int gi) {
+#pragma unroll
+        for (int p = 0; p < PRE; ++p) {
+            const int64_t r0 = tile * kTileRows + wave * 64 + (gi * PRE + p) * 16;
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+                const int colj = jb * 16 + li;
+                V ad;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ad[r] = dd[p][jb][r];
+#pragma unroll
+                for (int t = 0; t < KS; ++t) ad = MF<T>::mma(pa[p][t], M1[(4 * t + lg) * MST + colj], ad);
+                if (colj < s) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) D[colj * ldw + r0 + mfma_row<kF64>(lg, r)] = ad[r];
+                }
+            }
+        }
+    };
+    double gv[kGramRegs];
+    gram_fetch(glb(static_cast<const double *>(cd.gram)), s, gv);
+    const bool first = local < ntiles;
+    if (first) load(local, 0);
     {
         T *const dst[1] = {M1};
         const gptr<const T> src[1] = {
@@ -1023,7 +1181,12 @@ __global__ __launch_bounds__(kThreads) void update_dqp_fused_kernel(const ChipDe
         const bool neg[1] = {false};
         stage_small<T, SP, MST, 1>(dst, src, s, neg);
     }
-    factor_small<SP>(glb(static_cast<const double *>(cd.gram)), s, rel_thr, mode, fs);
+    gram_stash(gv, s, fs);
+    __syncthreads();
+    factor_small<SP>(s, rel_thr, mode, fs, [&] {
+        if (first) part_d(local, 0);
+    });
+    if (wave == 0 && first) part_d(local, 0);
     const int w = 2 * s;
     // M3[k][j] = S^+[k][j] = E[j][k] dv[j] (k <= j);  M4[k][j] = S[j][k] = U[j][k] dv[j] (k >= j)
     for (int e = threadIdx.x; e < SP * MST; e += kThreads) {
@@ -1071,63 +1234,29 @@ __global__ __launch_bounds__(kThreads) void update_dqp_fused_kernel(const ChipDe
         }
     }
     __syncthreads();
-    const gptr<T> __restrict__ D = glb(static_cast<T *>(cd.Dv));
-    const gptr<T> __restrict__ P = glb(static_cast<T *>(cd.P));
-    const gptr<const T> __restrict__ W = glb(static_cast<const T *>(cd.W));
-    const int64_t ldw = cd.ldw;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int li = lane & 15, lg = lane >> 4;
-    const int64_t ntiles = ldw / kTileRows;
     for (int64_t tile = local; tile < ntiles; tile += wgs) {
-        // FP32: the next 16-row block's operands load while this one computes
-        // (FP64 keeps one buffer: two would halve the resident waves)
-        constexpr int NBUF = sizeof(T) == 4 ? 2 : 1;
-        T pa[NBUF][KS], wa[NBUF][KS], dd[NBUF][NB][4];
-        auto load = [&](int rb, int b) {
-            const int64_t r0 = tile * kTileRows + wave * 64 + rb * 16;
 #pragma unroll
-            for (int t = 0; t < KS; ++t) {
-                const int col = 4 * t + lg;
-                pa[b][t] = col < s ? P[col * ldw + r0 + li] : T(0);
-                wa[b][t] = col < s ? W[col * ldw + r0 + li] : T(0);
+        for (int gi = 0; gi < NG; ++gi) {
+            if (tile != local || gi != 0) {
+                load(tile, gi);
+                part_d(tile, gi);
             }
 #pragma unroll
-            for (int jb = 0; jb < NB; ++jb) {
-                const int colj = jb * 16 + li;
+            for (int p = 0; p < PRE; ++p) {
+                const int64_t r0 = tile * kTileRows + wave * 64 + (gi * PRE + p) * 16;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) dd[b][jb][r] = colj < s ? D[colj * ldw + r0 + mfma_row<kF64>(lg, r)] : T(0);
-            }
-        };
-        if (NBUF == 2) load(0, 0);
+                for (int jb = 0; jb < NB; ++jb) {
+                    const int colj = jb * 16 + li;
+                    V ap;
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
-            const int b = NBUF == 2 ? (rb & 1) : 0;
-            if (NBUF == 1) load(rb, 0);
-            else if (rb + 1 < 4) load(rb + 1, b ^ 1);
-            const int64_t r0 = tile * kTileRows + wave * 64 + rb * 16;
+                    for (int r = 0; r < 4; ++r) ap[r] = T(0);
 #pragma unroll
-            for (int jb = 0; jb < NB; ++jb) {
-                const int colj = jb * 16 + li;
-                V ad, ap;
+                    for (int t = 0; t < KS; ++t) ap = MF<T>::mma(wa[p][t], M3[(4 * t + lg) * MST + colj], ap);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    ad[r] = dd[b][jb][r];
-                    ap[r] = T(0);
-                }
+                    for (int t = 0; t < KS; ++t) ap = MF<T>::mma(pa[p][t], M4[(4 * t + lg) * MST + colj], ap);
+                    if (colj < s) {
 #pragma unroll
-                for (int t = 0; t < KS; ++t) {
-                    const int k = 4 * t + lg;
-                    ad = MF<T>::mma(pa[b][t], M1[k * MST + colj], ad);
-                    ap = MF<T>::mma(wa[b][t], M3[k * MST + colj], ap);
-                }
-#pragma unroll
-                for (int t = 0; t < KS; ++t) ap = MF<T>::mma(pa[b][t], M4[(4 * t + lg) * MST + colj], ap);
-                if (colj < s) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int64_t idx = colj * ldw + r0 + mfma_row<kF64>(lg, r);
-                        D[idx] = ad[r];
-                        P[idx] = ap[r];
+                        for (int r = 0; r < 4; ++r) P[colj * ldw + r0 + mfma_row<kF64>(lg, r)] = ap[r];
                     }
                 }
             }
@@ -1578,6 +1707,7 @@ size_t row_kernel_lds(int s, bko_dtype compute)
 bko_status launch_reduce_factor(const Ctx &x, double rel_thr, int mode)
 {
     const int s = x.L->s, ss = s * s;
+    BKO_CHECK(s > 32 && factor_segment(s) >= 16, "the separate factorisation kernel is for s > 32, got s = %d", s);
     TimedLaunch tl(kSmall, x.st);
     const unsigned rblocks = static_cast<unsigned>(std::min(kRedBlocks, ss));
     hipLaunchKernelGGL(gram_reduce_kernel, dim3(rblocks, static_cast<unsigned>(x.L->nchips)), dim3(kThreads), 0, x.st,
@@ -1586,17 +1716,9 @@ bko_status launch_reduce_factor(const Ctx &x, double rel_thr, int mode)
     // A, G, C (each padded by E <= 32), two pivot rows (padded) and columns
     const size_t lds = sizeof(double) * (4 * ss + 3 * 32 + 2 * (2 * s + 32) + 2 * s);
     const dim3 grid(static_cast<unsigned>(x.L->nchips));
-#define BKO_FACTOR(E, SP) \
-    hipLaunchKernelGGL((factor_kernel<E, SP>), grid, dim3(kFacThreads), lds, x.st, x.cds, s, rel_thr, mode)
     const int e = factor_segment(s);
-    if (s <= 8) BKO_FACTOR(1, 8);
-    else if (s <= 16 && e == 1) BKO_FACTOR(1, 16);
-    else if (s <= 16) BKO_FACTOR(2, 16);
-    else if (s <= 32 && e == 4) BKO_FACTOR(4, 32);
-    else if (s <= 32) BKO_FACTOR(8, 32);
-    else if (e == 16) BKO_FACTOR(16, 0);
-    else BKO_FACTOR(32, 0);
-#undef BKO_FACTOR
+    if (e == 16) hipLaunchKernelGGL((factor_kernel<16>), grid, dim3(kFacThreads), lds, x.st, x.cds, s, rel_thr, mode);
+    else hipLaunchKernelGGL((factor_kernel<32>), grid, dim3(kFacThreads), lds, x.st, x.cds, s, rel_thr, mode);
     BKO_HIP(hipGetLastError());
     return BKO_OK;
 }
