@@ -415,17 +415,28 @@ __device__ __forceinline__ void wave_eliminate(const double *g, int ld, int s, d
 {
     const int lane = threadIdx.x & 63;
     const int w = 2 * s;
-    double gmax = lane < s ? g[lane * ld + lane] : 0.0;
+    // every lane reads (at a clamped index) so that the reads issue back to
+    // back, with no branch between them
+    const int lc = lane < s ? lane : 0;
+    double x[SP], y[SP];
+#pragma unroll
+    for (int i = 0; i < SP; ++i) {
+        const int ic = i < s ? i : 0;
+        x[i] = g[ic * ld + lc];
+        y[i] = g[lc * ld + ic];
+    }
+    double gmax = g[lc * ld + lc];
+    gmax = lane < s ? gmax : 0.0;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, off));
     const double thr = rel_thr * gmax;
     double a[SP];
 #pragma unroll
     for (int i = 0; i < SP; ++i) {
-        if (lane < SP)
-            a[i] = (i < s && lane < s) ? 0.5 * (g[i * ld + lane] + g[lane * ld + i]) : (i == lane ? gmax : 0.0);
-        else
-            a[i] = (i == lane - SP) ? 1.0 : 0.0;
+        const double gi = 0.5 * (x[i] + y[i]);
+        const double left = (i < s && lane < s) ? gi : (i == lane ? gmax : 0.0);
+        const double right = (i == lane - SP) ? 1.0 : 0.0;
+        a[i] = lane < SP ? left : right;
     }
 #pragma unroll
     for (int k = 0; k < SP; ++k) {
@@ -758,6 +769,32 @@ __device__ inline void stage_small(T *const (&dst)[NM], const gptr<const T> (&sr
     }
 }
 
+// stage_small split in two for one matrix: fetch its entries of the padded
+// SP x MST tile into registers (so that later loads can be issued behind
+// them), then store them to LDS.
+template <int SP, int MST> constexpr int small_regs() { return (SP * MST + kThreads - 1) / kThreads; }
+
+template <class T, int SP, int MST>
+__device__ __forceinline__ void small_fetch(gptr<const T> src, int s, T (&v)[small_regs<SP, MST>()])
+{
+#pragma unroll
+    for (int i = 0; i < small_regs<SP, MST>(); ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        const int k = e / MST, j = e % MST;
+        v[i] = (e < SP * MST && k < s && j < s) ? src[k * s + j] : T(0);
+    }
+}
+
+template <class T, int SP, int MST>
+__device__ __forceinline__ void small_stash(T *dst, const T (&v)[small_regs<SP, MST>()], bool neg)
+{
+#pragma unroll
+    for (int i = 0; i < small_regs<SP, MST>(); ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        if (e < SP * MST) dst[e] = neg ? -v[i] : v[i];
+    }
+}
+
 // W <- W M3 - AP M2 (the previous step's Q = W S^+ formed on the fly, matrix
 // cores in the storage precision) and the W^T W partials from the same
 // registers.  With init != 0, W holds the residual and only its Gram is
@@ -942,11 +979,12 @@ __global__ __launch_bounds__(kThreads) void update_dqp_kernel(const ChipDev *__r
 // the chip also publishes what later kernels need (M1 for the D update, C,
 // M3, the control words).
 //
-// The factorisation's latency is hidden where the data allow: the Gram is
-// fetched first, the workgroup's first row blocks are loaded behind it, and
-// while wave 0 eliminates, waves 1..3 do the part of their update that does
-// not depend on the new factors (W S^+ here, D += P M1 in update_dqp); wave
-// 0 does its part after the elimination.
+// The factorisation's latency is partly hidden: the Gram and the small
+// matrices are fetched first and staged in LDS, then, while wave 0
+// eliminates, waves 1..3 load their first row blocks and do the part of
+// their update that does not depend on the new factors (W S^+ here, D +=
+// P M1 in update_dqp); wave 0 loads its rows and does its part in the row
+// loop, so the eliminating wave holds no row data.
 
 // 16-row blocks per wave held in registers at once by the fused kernels
 // (FP64 holds fewer, to keep two waves per SIMD).
@@ -1009,24 +1047,23 @@ __global__ __launch_bounds__(kThreads) void update_w_fused_kernel(const ChipDev 
                 wm[p][jb] = acc;
             }
     };
-    double gv[kGramRegs];
+    double gv[kGramRegs], cv[kGramRegs];
+    T mv[small_regs<SP, MST>()];
     gram_fetch(glb(static_cast<const double *>(cd.gram)), s, gv);
+    small_fetch<T, SP, MST>(glb(f64 ? reinterpret_cast<const T *>(cd.sm.M3) : reinterpret_cast<const T *>(cd.sm.M3f)),
+                            s, mv);
+    if (local == 0) gram_fetch(sm.C, s, cv);
     const bool first = local < ntiles;
-    if (first) load(local, 0);
-    {
-        T *const dst[1] = {M3s};
-        const gptr<const T> src[1] = {
-            glb(f64 ? reinterpret_cast<const T *>(cd.sm.M3) : reinterpret_cast<const T *>(cd.sm.M3f))};
-        const bool neg[1] = {false};
-        stage_small<T, SP, MST, 1>(dst, src, s, neg);
-        for (int e = threadIdx.x; e < SP * MST; e += kThreads) M2s[e] = T(0);
-    }
+    small_stash<T, SP, MST>(M3s, mv, false);
+    for (int e = threadIdx.x; e < SP * MST; e += kThreads) M2s[e] = T(0);
     gram_stash(gv, s, fs);
     __syncthreads();
     factor_small<SP>(s, rel_thr, 0, fs, [&] {
-        if (first) part_w();
+        if (first) {
+            load(local, 0);
+            part_w();
+        }
     });
-    if (wave == 0 && first) part_w();
     const int w = 2 * s;
     // delta^+ = E^T diag(dv) E (E = right half of the eliminated [G | I])
     small_gemm(
@@ -1038,7 +1075,9 @@ __global__ __launch_bounds__(kThreads) void update_w_fused_kernel(const ChipDev 
     __syncthreads();
     if (local == 0) {
         // M1 = delta^+ C for this step's update of D
-        for (int e = threadIdx.x; e < s * s; e += kThreads) fs.Cl[e] = sm.C[e];
+#pragma unroll
+        for (int q = 0; q < kGramRegs; ++q)
+            if (threadIdx.x + q * kThreads < s * s) fs.Cl[threadIdx.x + q * kThreads] = cv[q];
         __syncthreads();
         small_gemm(
             s, [&](int i, int k) { return fs.G[i * s + k]; }, [&](int k, int j) { return fs.Cl[k * s + j]; },
@@ -1054,7 +1093,7 @@ __global__ __launch_bounds__(kThreads) void update_w_fused_kernel(const ChipDev 
     for (int64_t tile = local; tile < ntiles; tile += wgs) {
 #pragma unroll
         for (int gi = 0; gi < NG; ++gi) {
-            if (tile != local || gi != 0) {
+            if (tile != local || gi != 0 || wave == 0) {
                 load(tile, gi);
                 part_w();
             }
@@ -1170,23 +1209,26 @@ __global__ __launch_bounds__(kThreads) void update_dqp_fused_kernel(const ChipDe
             }
         }
     };
-    double gv[kGramRegs];
+    double gv[kGramRegs], cv[kGramRegs];
+    T mv[small_regs<SP, MST>()];
     gram_fetch(glb(static_cast<const double *>(cd.gram)), s, gv);
-    const bool first = local < ntiles;
-    if (first) load(local, 0);
-    {
-        T *const dst[1] = {M1};
-        const gptr<const T> src[1] = {
-            glb(f64 ? reinterpret_cast<const T *>(cd.sm.M1) : reinterpret_cast<const T *>(cd.sm.M1f))};
-        const bool neg[1] = {false};
-        stage_small<T, SP, MST, 1>(dst, src, s, neg);
+    small_fetch<T, SP, MST>(glb(f64 ? reinterpret_cast<const T *>(cd.sm.M1) : reinterpret_cast<const T *>(cd.sm.M1f)),
+                            s, mv);
+    int iters = 0;
+    if (local == 0) {
+        gram_fetch(sm.C, s, cv);
+        iters = ctrl[kIters];
     }
+    const bool first = local < ntiles;
+    small_stash<T, SP, MST>(M1, mv, false);
     gram_stash(gv, s, fs);
     __syncthreads();
     factor_small<SP>(s, rel_thr, mode, fs, [&] {
-        if (first) part_d(local, 0);
+        if (first) {
+            load(local, 0);
+            part_d(local, 0);
+        }
     });
-    if (wave == 0 && first) part_d(local, 0);
     const int w = 2 * s;
     // M3[k][j] = S^+[k][j] = E[j][k] dv[j] (k <= j);  M4[k][j] = S[j][k] = U[j][k] dv[j] (k >= j)
     for (int e = threadIdx.x; e < SP * MST; e += kThreads) {
@@ -1205,7 +1247,9 @@ __global__ __launch_bounds__(kThreads) void update_dqp_fused_kernel(const ChipDe
     }
     if (local == 0) {
         // C <- S C, S[i][k] = U[i][k] dv[i] (k >= i); convergence on ||C e_j||
-        for (int e = threadIdx.x; e < s * s; e += kThreads) fs.Cl[e] = sm.C[e];
+#pragma unroll
+        for (int q = 0; q < kGramRegs; ++q)
+            if (threadIdx.x + q * kThreads < s * s) fs.Cl[threadIdx.x + q * kThreads] = cv[q];
         if (threadIdx.x == 0) fs.notconv = 0;
         __syncthreads();
         small_gemm(
@@ -1227,7 +1271,7 @@ __global__ __launch_bounds__(kThreads) void update_dqp_fused_kernel(const ChipDe
         if (threadIdx.x == 0) {
             int inactive = 0;
             for (int k = 0; k < s; ++k) inactive += fs.active[k] ? 0 : 1;
-            ctrl[kIters] += mode == 1 ? 1 : 0;
+            ctrl[kIters] = iters + (mode == 1 ? 1 : 0);
             ctrl[kDeflated] = inactive;
             if (inactive == s) ctrl[kAllDeflated] = 1;
             if (fs.notconv == 0 || inactive == s) ctrl[kConverged] = 1;
@@ -1237,7 +1281,7 @@ __global__ __launch_bounds__(kThreads) void update_dqp_fused_kernel(const ChipDe
     for (int64_t tile = local; tile < ntiles; tile += wgs) {
 #pragma unroll
         for (int gi = 0; gi < NG; ++gi) {
-            if (tile != local || gi != 0) {
+            if (tile != local || gi != 0 || wave == 0) {
                 load(tile, gi);
                 part_d(tile, gi);
             }
