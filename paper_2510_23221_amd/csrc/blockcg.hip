@@ -216,16 +216,23 @@ __device__ void publish_partial(const d4 (&g)[NBLK], int s, double *lds, gptr<do
 
 // ------------------------------------------------------------------ stencil product + Gram
 
+// Consecutive cells one 16-byte access covers.
+template <class T> __host__ __device__ constexpr int vec_cells() { return 16 / static_cast<int>(sizeof(T)); }
+
 // Rows of a 256-row tile staged in LDS at once: the whole tile when P and AP
 // of all 16 NB columns fit in 70 KB (two workgroups per CU), else half.
+// Staged columns are padded by one 16-byte vector.
 template <class T, int NB> __host__ __device__ constexpr int stage_rows()
 {
-    return 2 * 16 * NB * (kTileRows + 1) * static_cast<int>(sizeof(T)) <= 70 * 1024 ? kTileRows : kTileRows / 2;
+    return 2 * 16 * NB * (kTileRows + vec_cells<T>()) * static_cast<int>(sizeof(T)) <= 70 * 1024 ? kTileRows
+                                                                                                 : kTileRows / 2;
 }
+
+template <class T, int NB> __host__ __device__ constexpr int stage_ld() { return stage_rows<T, NB>() + vec_cells<T>(); }
 
 template <class T, int NB> __host__ __device__ constexpr size_t spmm_gram_lds()
 {
-    return 2 * sizeof(T) * 16 * NB * (stage_rows<T, NB>() + 1);
+    return 2 * sizeof(T) * 16 * NB * stage_ld<T, NB>();
 }
 
 // AP = A P for the chip's tiles, and the chip's P^T AP partial of this
@@ -241,7 +248,7 @@ __global__ __launch_bounds__(kSpThreads) void spmm_gram_kernel(const ChipDev *__
 {
     constexpr int TR = stage_rows<T, NB>();
     constexpr int SP = 16 * NB;
-    constexpr int LD = TR + 1;
+    constexpr int LD = stage_ld<T, NB>();
     constexpr int CSTEP = kSpThreads / TR;  // column classes
     constexpr int NW = kSpThreads / 64;     // waves
     int local;
@@ -341,6 +348,146 @@ __global__ __launch_bounds__(kSpThreads) void spmm_gram_kernel(const ChipDev *__
     }
     static_assert(spmm_gram_lds<T, NB>() >= sizeof(double) * publish_lds<kSpThreads>(NB * NB < 4 ? NB * NB : 4),
                   "publish_partial needs more LDS than the staged tiles");
+    publish_partial<NB, false, NB * NB, kSpThreads>(acc, s, reinterpret_cast<double *>(smem),
+                                                    glb(cd.parts) + static_cast<size_t>(local) * s * s);
+}
+
+// 16-byte vector of block elements.
+template <class T> struct Vec16;
+template <> struct Vec16<float> {
+    using type = f4;
+};
+template <> struct Vec16<double> {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    using type = d2;
+};
+
+template <class T> __device__ __forceinline__ typename Vec16<T>::type ld16(gptr<const T> p)
+{
+    return *reinterpret_cast<gptr<const typename Vec16<T>::type>>(p);
+}
+
+// spmm_gram_kernel with V = 16 / sizeof(T) consecutive cells per thread, so
+// that every access to P, AP, the coefficients and the LDS stage is one
+// 16-byte operation (chips whose nx is a multiple of V: a group of V cells
+// then lies in one x-row).  The x neighbours inside the group come from its
+// own vector, the two outside it from scalar loads.
+template <class T, int NB>
+__global__ __launch_bounds__(kSpThreads) void spmm_gram_vec_kernel(const ChipDev *__restrict__ cds,
+                                                                   const uint16_t *__restrict__ tab, int s)
+{
+    using VT = typename Vec16<T>::type;
+    constexpr int V = vec_cells<T>();
+    constexpr int TR = stage_rows<T, NB>();
+    constexpr int SP = 16 * NB;
+    constexpr int LD = stage_ld<T, NB>();
+    constexpr int TPC = TR / V;              // threads per column class
+    constexpr int CSTEP = kSpThreads / TPC;  // column classes
+    constexpr int NW = kSpThreads / 64;
+    static_assert(kSpThreads % TPC == 0 && (LD * sizeof(T)) % 16 == 0, "vector staging");
+    int local;
+    const ChipDev &cd = chip_of(cds, tab, local);
+    const int wgs = cd.wgs;
+    gptr<int> ctrl = glb(cd.ctrl);
+    if (ctrl[kConverged]) {
+        if (local == 0 && threadIdx.x == 0) ctrl[kStop] = 1;
+        return;
+    }
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *Ps = reinterpret_cast<T *>(smem);
+    T *APs = Ps + SP * LD;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    for (int e = s * LD + tid; e < SP * LD; e += kSpThreads) {
+        Ps[e] = T(0);
+        APs[e] = T(0);
+    }
+    const gptr<const T> __restrict__ P = glb(static_cast<const T *>(cd.P));
+    const gptr<T> __restrict__ AP = glb(static_cast<T *>(cd.AP));
+    const gptr<const T> __restrict__ cdiag = glb(static_cast<const T *>(cd.cdiag));
+    const gptr<const T> __restrict__ cwx = glb(static_cast<const T *>(cd.cwx));
+    const gptr<const T> __restrict__ cwy = glb(static_cast<const T *>(cd.cwy));
+    const gptr<const T> __restrict__ cwz = glb(static_cast<const T *>(cd.cwz));
+    const int nx = cd.nx, ny = cd.ny, nz = cd.nz;
+    const int64_t n = cd.n, ldw = cd.ldw;
+    const int64_t plane = static_cast<int64_t>(nx) * ny;
+    const int cell = (tid % TPC) * V, cls = tid / TPC;
+    const VT zero = VT(T(0));
+
+    d4 acc[NB * NB];
+#pragma unroll
+    for (int q = 0; q < NB * NB; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+    const int64_t ntiles = ldw / kTileRows;
+    for (int64_t tile = local; tile < ntiles; tile += wgs) {
+        for (int half = 0; half < kTileRows / TR; ++half) {
+            const int64_t a = tile * kTileRows + half * TR + cell;
+            if (a < n) {
+                const int i0 = static_cast<int>(a % nx);
+                const int64_t q = a / nx;
+                const int j = static_cast<int>(q % ny);
+                const int l = static_cast<int>(q / ny);
+                // a missing neighbour reads the group itself with a zero coupling
+                const int64_t oxl = i0 > 0 ? -1 : 0, oxr = i0 + V < nx ? V : V - 1;
+                const int64_t oym = j > 0 ? -static_cast<int64_t>(nx) : 0, oyp = j < ny - 1 ? nx : 0;
+                const int64_t ozm = l > 0 ? -plane : 0, ozp = l < nz - 1 ? plane : 0;
+                const VT d = ld16(cdiag + a), cxp = ld16(cwx + a), cyp = ld16(cwy + a), czp = ld16(cwz + a);
+                const VT cym = j > 0 ? ld16(cwy + a - nx) : zero;
+                const VT czm = l > 0 ? ld16(cwz + a - plane) : zero;
+                VT cxm;
+                cxm[0] = i0 > 0 ? cwx[a - 1] : T(0);
+#pragma unroll
+                for (int e = 1; e < V; ++e) cxm[e] = cxp[e - 1];
+#pragma unroll 2
+                for (int c = cls; c < s; c += CSTEP) {
+                    const gptr<const T> x = P + c * ldw + a;
+                    const VT xc = ld16(x), xym = ld16(x + oym), xyp = ld16(x + oyp), xzm = ld16(x + ozm),
+                             xzp = ld16(x + ozp);
+                    const T xl = x[oxl], xr = x[oxr];
+                    VT y;
+#pragma unroll
+                    for (int e = 0; e < V; ++e) {
+                        const T left = e == 0 ? xl : xc[e > 0 ? e - 1 : 0];
+                        const T right = e == V - 1 ? xr : xc[e < V - 1 ? e + 1 : 0];
+                        const T nb = cxm[e] * left + cxp[e] * right + cym[e] * xym[e] + cyp[e] * xyp[e] +
+                                     czm[e] * xzm[e] + czp[e] * xzp[e];
+                        y[e] = d[e] * xc[e] - nb;
+                    }
+                    *reinterpret_cast<gptr<VT>>(AP + c * ldw + a) = y;
+                    *reinterpret_cast<VT *>(Ps + c * LD + cell) = xc;
+                    *reinterpret_cast<VT *>(APs + c * LD + cell) = y;
+                }
+            } else {
+                // padding rows of the tile: zero in the Gram (AP keeps its zero padding)
+                for (int c = cls; c < s; c += CSTEP) {
+                    *reinterpret_cast<VT *>(Ps + c * LD + cell) = zero;
+                    *reinterpret_cast<VT *>(APs + c * LD + cell) = zero;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int rb = 0; rb < TR / (16 * NW); ++rb) {
+                const int r = wave * (TR / NW) + rb * 16 + lg * 4;
+                double u[NB][4], v[NB][4];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const int col = b * 16 + li;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        u[b][t] = static_cast<double>(Ps[col * LD + r + t]);
+                        v[b][t] = static_cast<double>(APs[col * LD + r + t]);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int x = 0; x < NB; ++x)
+#pragma unroll
+                        for (int y = 0; y < NB; ++y) acc[x * NB + y] = mma64(u[x][t], v[y][t], acc[x * NB + y]);
+            }
+            __syncthreads();
+        }
+    }
     publish_partial<NB, false, NB * NB, kSpThreads>(acc, s, reinterpret_cast<double *>(smem),
                                                     glb(cd.parts) + static_cast<size_t>(local) * s * s);
 }
@@ -1545,6 +1692,7 @@ struct ChipHost {
 
 struct Layout {
     int nchips = 0, s = 0, total_wgs = 0, tiles_per_wg = 1;
+    int nx_align = 4;  // largest of 1, 2, 4 dividing every chip's nx
     bko_dtype compute = BKO_F64;
     size_t off_cds = 0, off_tab = 0, off_th = 0, off_ctrl = 0, off_norms = 0, off_alpha = 0, off_dots = 0, bytes = 0;
     std::vector<ChipHost> chips;
@@ -1605,6 +1753,7 @@ Layout make_layout(const Operator *const *ops, int nchips, int s, bko_dtype comp
         h.wgs = std::min((h.tiles + tiles_per_wg - 1) / tiles_per_wg, max_parts(h.tiles, s));
         h.wg_base = total;
         total += h.wgs;
+        while (ops[c]->nx % L.nx_align != 0) L.nx_align /= 2;
     }
     L.total_wgs = total;
     int table = 0;  // sized for one tile per workgroup, so offsets do not depend on the tuning
@@ -1705,8 +1854,12 @@ bko_status launch_row_kernels(int which, const Ctx &x, int init)
     const dim3 grid(static_cast<unsigned>(x.L->total_wgs)), block(kThreads);
     if (which == 0) {
         TimedLaunch tl(kSpmm, x.st);
-        hipLaunchKernelGGL((spmm_gram_kernel<T, NB>), grid, dim3(kSpThreads), (spmm_gram_lds<T, NB>()), x.st, x.cds,
-                           x.tab, s);
+        if (x.L->nx_align % vec_cells<T>() == 0)
+            hipLaunchKernelGGL((spmm_gram_vec_kernel<T, NB>), grid, dim3(kSpThreads), (spmm_gram_lds<T, NB>()), x.st,
+                               x.cds, x.tab, s);
+        else
+            hipLaunchKernelGGL((spmm_gram_kernel<T, NB>), grid, dim3(kSpThreads), (spmm_gram_lds<T, NB>()), x.st,
+                               x.cds, x.tab, s);
     } else if (which == 1) {
         TimedLaunch tl(kUpdate, x.st);
         hipLaunchKernelGGL((update_w_kernel<T, NB>), grid, block, 0, x.st, x.cds, x.tab, s, init);
