@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cg-columns", type=int, default=512, help="columns of the per-sample CG baseline (0: skip)")
+    ap.add_argument("--precond", choices=["none", "jacobi"], default="jacobi",
+                    help="preconditioner of the block solve and of the per-sample CG baseline alike")
     ap.add_argument("--only", choices=["apply", "combine", "copy"], default=None,
                     help="run one kernel family at the workload's shape (for counter profiles)")
     return ap.parse_args()
@@ -121,7 +123,8 @@ def main():
     comb_compute = capi.BF16 if w.scheme == "mixed_bf16" else capi.F64
     apply_compute = capi.F32 if w.scheme == "mixed_bf16" else capi.F64
 
-    G = capi.HeatOperator.from_chip(chip, dev)
+    pc = capi.PRECOND_JACOBI if args.precond == "jacobi" else capi.PRECOND_NONE
+    G = capi.HeatOperator.from_chip(chip, dev, precond=pc)
     B = torch.as_tensor(w.B[0], device=dev)
     C = torch.as_tensor(w.C[0], device=dev)
     X = torch.empty_like(B)
@@ -215,7 +218,7 @@ def main():
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "grid": list(chip.dims), "s": s, "M": m, "tol": w.tol,
-                   "scheme": w.scheme, "T_F_dtype": str(t_dtype).replace("torch.", "")},
+                   "scheme": w.scheme, "T_F_dtype": str(t_dtype).replace("torch.", ""), "precond": args.precond},
         "roofline": roofline,
         "stencil": roof("apply"),
         "census_ms_per_step": {k: round(v[1], 4) for k, v in census.items()},
@@ -241,7 +244,8 @@ def bench_batched(args):
 
     dev = torch.device("cuda:0")
     w = synth.workload(2, m=args.m, nchips=args.nchips)
-    Gs = [capi.HeatOperator.from_chip(c, dev) for c in w.chips]
+    pc = capi.PRECOND_JACOBI if args.precond == "jacobi" else capi.PRECOND_NONE
+    Gs = [capi.HeatOperator.from_chip(c, dev, precond=pc) for c in w.chips]
     Bs = [torch.as_tensor(B, device=dev) for B in w.B]
     Cs = [torch.as_tensor(C, device=dev) for C in w.C]
     Xs = [torch.empty_like(B) for B in Bs]
@@ -277,7 +281,8 @@ def bench_batched(args):
            "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": w.name, "nchips": len(w.chips), "cells_total": int(sum(c.n for c in w.chips)),
-                      "s": w.s, "M_per_chip": w.m, "tol": w.tol, "scheme": "mixed", "T_F_dtype": "float64"},
+                      "s": w.s, "M_per_chip": w.m, "tol": w.tol, "scheme": "mixed", "T_F_dtype": "float64",
+                      "precond": args.precond},
            "autotuned_tiles_per_workgroup": tpw,
            "iters": {"min": min(i["iters"] for i in last), "max": max(i["iters"] for i in last),
                      "mean": sum(i["iters"] for i in last) / len(last)},

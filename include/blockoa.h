@@ -65,6 +65,13 @@ typedef enum {
 
 typedef struct bko_operator *bko_op;
 
+/* Preconditioner of the solves on an operator (bko_operator_set_precond).
+ * The paper leaves it unstated; the default is none. */
+typedef enum {
+    BKO_PRECOND_NONE = 0,
+    BKO_PRECOND_JACOBI = 1 /* diagonal (Jacobi) preconditioning, see below */
+} bko_precond;
+
 typedef struct {
     int iters;          /* inner block iterations, summed over refinements   */
     int refinements;    /* outer FP64 true-residual corrections (>= 1)        */
@@ -88,7 +95,9 @@ const char *bko_last_error(void);
  * Bytes the caller must provide as coefficient storage for an nx x ny x nz
  * grid (Sec. II-B: the discretised operator A of Eq. (2)).  Storage holds
  * the diagonal and the three forward-face couplings per cell in FP64 and an
- * FP32 copy, each array 256-byte aligned.
+ * FP32 copy, the same four arrays of the diagonally scaled operator S A S
+ * (S = diag(A)^(-1/2), for Jacobi preconditioning) in FP64 and FP32, and S
+ * in FP64: 104 bytes per cell, each array 256-byte aligned.
  */
 bko_status bko_operator_bytes(int nx, int ny, int nz, size_t *bytes);
 
@@ -120,6 +129,24 @@ bko_status bko_assemble_heat_operator(int nx, int ny, int nz, double lx, double 
 
 /* Grid of an operator: writes nx, ny, nz (any pointer may be NULL). */
 bko_status bko_operator_dims(bko_op A, int *nx, int *ny, int *nz);
+
+/*
+ * Preconditioner of every later solve on A (bko_block_krylov_solve, batch
+ * solves of chips on A, bko_cg_solve).  The paper does not state one
+ * (Sec. V names PETSc without its options); BKO_PRECOND_NONE is the default.
+ * BKO_PRECOND_JACOBI:
+ *   block solve: the block iteration runs on the symmetrically scaled system
+ *     (S A S) Y = S R, D = S Y, with S = diag(A)^(-1/2) (Jacobi applied on
+ *     both sides, so the iterated operator stays symmetric positive
+ *     definite); the FP64 correction loop still forms R = B - A X with the
+ *     unscaled A and stops on the unscaled relative residual, so the
+ *     solution meets the same tolerance as without preconditioning.
+ *   per-sample CG: preconditioned CG with M = diag(A) (z = M^-1 r,
+ *     rho = r'z), stopping on the unpreconditioned ||r|| <= tol ||b||.
+ * Errors: BKO_EINVAL for a NULL handle or an unknown kind.
+ */
+bko_status bko_operator_set_precond(bko_op A, int kind);
+bko_status bko_operator_get_precond(bko_op A, int *kind);
 
 /* Free the handle (host memory only; the coefficient buffer stays the caller's). */
 bko_status bko_destroy_operator(bko_op A);

@@ -13,6 +13,10 @@ Everything here is plain FP64:
 * :func:`cg_many` -- unpreconditioned CG from x0 = 0, one right-hand side at a
   time (the direct solution method of Sec. II-D; CG baseline of Sec. V-A).
   The method's block solve reaches X = A^-1 B, which is what this computes.
+* :func:`jacobi_scaling`, :func:`pcg` -- the diagonal (Jacobi) preconditioner:
+  S = diag(A)^(-1/2) and the symmetrically scaled S A S, and preconditioned
+  CG with M = diag(A) (the paper leaves the preconditioner unstated; these
+  define the optional Jacobi mode of the solves).
 * :func:`gemm` -- T = X C by plain loops (Sec. III-B, Eq. (5), raw weights).
 * :func:`apply_many` -- F = A T by CSR products (Sec. III-C, Eq. (6)).
 * :mod:`oracle.conv_ref` -- FP64 convolution encoder-decoder forward and
@@ -142,6 +146,54 @@ def cg_many(A: CSR, B: np.ndarray, tol: float, maxit: int = 100000, nthreads: in
     lib.orc_cg_many(A.n, _p(A.rowptr), _p(A.col), _p(A.val), s, _p(B), A.n, _p(X), A.n, tol, maxit,
                     _p(iters), _p(relres), nthreads)
     return X, iters, relres
+
+
+def diagonal(A: CSR) -> np.ndarray:
+    """The diagonal entries of A."""
+    d = np.zeros(A.n)
+    for r in range(A.n):
+        for p in range(A.rowptr[r], A.rowptr[r + 1]):
+            if A.col[p] == r:
+                d[r] += A.val[p]
+    return d
+
+
+def jacobi_scaling(A: CSR):
+    """Symmetric diagonal scaling: S = diag(A)^(-1/2) and S A S as CSR, entry
+    (i, j) = a_ij s_i s_j.  Returns (S as a vector, S A S)."""
+    sc = 1.0 / np.sqrt(diagonal(A))
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    val = A.val * sc[rows] * sc[A.col]
+    return sc, CSR(A.n, A.rowptr.copy(), A.col.copy(), val)
+
+
+def pcg(A: CSR, b: np.ndarray, tol: float, maxit: int = 100000, minv: np.ndarray = None):
+    """Preconditioned CG from x0 = 0 with M^-1 = diag(minv) (plain CG when
+    minv is None): z = M^-1 r, rho = r^T z, alpha = rho / p^T A p,
+    x += alpha p, r -= alpha A p, beta = rho' / rho, p = z' + beta p; stops
+    when ||r|| <= tol ||b|| (the unpreconditioned residual) or after maxit
+    iterations.  Returns (x, iterations, true relative residual)."""
+    b = np.asarray(b, dtype=np.float64)
+    w = np.ones(A.n) if minv is None else np.asarray(minv, dtype=np.float64)
+    x = np.zeros(A.n)
+    r = b.copy()
+    z = w * r
+    p = z.copy()
+    rho = r @ z
+    bn = np.linalg.norm(b)
+    it = 0
+    while np.linalg.norm(r) > tol * bn and it < maxit:
+        q = spmv(A, p)
+        alpha = rho / (p @ q)
+        x += alpha * p
+        r -= alpha * q
+        z = w * r
+        rho_new = r @ z
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+        it += 1
+    res = np.linalg.norm(b - spmv(A, x)) / bn if bn > 0 else 0.0
+    return x, it, res
 
 
 def gemm(X: np.ndarray, C: np.ndarray, nthreads: int = 0) -> np.ndarray:

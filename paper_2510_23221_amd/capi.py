@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libblockoa.so")
 
 OK, EINVAL, ENOTSPD, ENOCONV, EBREAKDOWN, EHIP, ENOMEM, ENOTIMPL = range(8)
 F64, F32, BF16 = 0, 1, 2
+PRECOND_NONE, PRECOND_JACOBI = 0, 1
 BC_DIRICHLET0, BC_ADIABATIC, BC_ROBIN = 0, 1, 2
 STATUS_NAMES = {0: "BKO_OK", 1: "BKO_EINVAL", 2: "BKO_ENOTSPD", 3: "BKO_ENOCONV",
                 4: "BKO_EBREAKDOWN", 5: "BKO_EHIP", 6: "BKO_ENOMEM", 7: "BKO_ENOTIMPL"}
@@ -38,7 +39,8 @@ EXPORTED = ("bko_version", "bko_last_error", "bko_operator_bytes", "bko_assemble
             "bko_batch_tune", "bko_batch_solve", "bko_nn_conv2d", "bko_nn_wgrad_work_floats",
             "bko_nn_conv2d_wgrad", "bko_unet_create", "bko_unet_destroy", "bko_unet_sizes", "bko_unet_set_params",
             "bko_unet_forward", "bko_unet_gradient", "bko_unet_adam_step", "bko_lstart_pack",
-            "bko_lstart_pack_target", "bko_lstart_unpack", "bko_jacobi_smooth")
+            "bko_lstart_pack_target", "bko_lstart_unpack", "bko_jacobi_smooth", "bko_operator_set_precond",
+            "bko_operator_get_precond")
 
 
 class BlockoaError(RuntimeError):
@@ -181,21 +183,47 @@ class HeatOperator:
         self.handle = handle
 
     @classmethod
-    def from_chip(cls, chip, device="cuda", stream=None) -> "HeatOperator":
+    def from_chip(cls, chip, device="cuda", stream=None, precond: int = 0) -> "HeatOperator":
         k = torch.as_tensor(chip.k, dtype=torch.float64, device=device)
-        return cls(chip.nx, chip.ny, chip.nz, chip.lx, chip.ly, chip.lz, k, chip.bc, chip.h, stream)
+        op = cls(chip.nx, chip.ny, chip.nz, chip.lx, chip.ly, chip.lz, k, chip.bc, chip.h, stream)
+        if precond:
+            op.precond = precond
+        return op
+
+    @property
+    def precond(self) -> int:
+        """PRECOND_NONE or PRECOND_JACOBI: the preconditioner of every solve on this operator."""
+        out = ctypes.c_int()
+        _check(load_library().bko_operator_get_precond(self.handle, ctypes.byref(out)))
+        return out.value
+
+    @precond.setter
+    def precond(self, kind: int):
+        _check(load_library().bko_operator_set_precond(self.handle, int(kind)))
+
+    def _arrays(self, first: int, count: int, esize: int):
+        n = self.n
+        base = self._coeff_ptr - self.coeff.data_ptr()
+        sizes = [8] * 4 + [4] * 4 + [8] * 4 + [4] * 4 + [8]
+        off = 0
+        for k in range(first):
+            off = (off + sizes[k] * n + 255) // 256 * 256
+        out = []
+        for k in range(first, first + count):
+            assert sizes[k] == esize
+            t = self.coeff[base + off: base + off + esize * n].view(torch.float64 if esize == 8 else torch.float32)
+            out.append(t)
+            off = (off + esize * n + 255) // 256 * 256
+        return out
 
     def coefficients(self):
         """(diag, wx, wy, wz) FP64 views of the coefficient storage (for tests)."""
-        n = self.n
-        out = []
-        base = self._coeff_ptr - self.coeff.data_ptr()
-        off = 0
-        for _ in range(4):
-            t = self.coeff[base + off: base + off + 8 * n].view(torch.float64)
-            out.append(t)
-            off = (off + 8 * n + 255) // 256 * 256
-        return tuple(out)
+        return tuple(self._arrays(0, 4, 8))
+
+    def scaled_coefficients(self):
+        """(diag, wx, wy, wz) FP64 views of the Jacobi-scaled operator S A S and
+        the scale S = diag(A)^(-1/2) (for tests)."""
+        return tuple(self._arrays(8, 4, 8)), self._arrays(16, 1, 8)[0]
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -87,8 +87,9 @@ struct SmallG;
 // What a grouped kernel knows about one chip.
 struct ChipDev {
     // operator: coefficients in the block precision, and in FP64
-    const void *cdiag, *cwx, *cwy, *cwz;
-    const double *d64, *x64, *y64, *z64;
+    const void *cdiag, *cwx, *cwy, *cwz;   // the iterated operator (S A S under Jacobi)
+    const double *d64, *x64, *y64, *z64;  // A, for the FP64 residual
+    const double *scale;                  // S = diag(A)^(-1/2) under Jacobi, else null
     int nx, ny, nz, wgs;   // wgs: workgroups of the row kernels for this chip
     int64_t n, ldw;        // cells, padded rows of every internal block
     int wg_base, pad;
@@ -1493,15 +1494,17 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const ChipDev *__res
     }
 }
 
-// Per-workgroup column sums of squares of B (which = 0) or R64 (which = 1)
-// over the chip's rows, into parts[local * s + c].
+// Per-workgroup column sums of squares of B (which = 0), R64 (which = 1) or
+// S R64 (which = 2, chips under Jacobi scaling; others skip) over the chip's
+// rows, into parts[local * s + c].
 __global__ __launch_bounds__(kThreads) void colsq_kernel(const ChipDev *__restrict__ cds, const uint16_t *__restrict__ tab,
                                                          int s, int which)
 {
     int local;
     const ChipDev &cd = chip_of(cds, tab, local);
     const int wgs = cd.wgs;
-    if (which == 1 && !cd.ctrl[kActive]) return;
+    if (which >= 1 && !cd.ctrl[kActive]) return;
+    if (which == 2 && !cd.scale) return;
     __shared__ double sh[kThreads / 64][kMaxS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const double *src = which == 0 ? cd.B : cd.R64;
@@ -1512,7 +1515,7 @@ __global__ __launch_bounds__(kThreads) void colsq_kernel(const ChipDev *__restri
         for (int64_t tile = local; tile < ntiles; tile += wgs) {
             const int64_t a = tile * kTileRows + threadIdx.x;
             if (a < cd.n) {
-                const double v = src[c * ld + a];
+                const double v = which == 2 ? src[c * ld + a] * cd.scale[a] : src[c * ld + a];
                 acc = fma(v, v, acc);
             }
         }
@@ -1533,7 +1536,8 @@ __global__ __launch_bounds__(kThreads) void colsq_kernel(const ChipDev *__restri
 __global__ __launch_bounds__(kThreads) void colsq_reduce_kernel(const ChipDev *__restrict__ cds, int s, int which)
 {
     const ChipDev &cd = cds[blockIdx.x];
-    if (which == 1 && !cd.ctrl[kActive]) return;
+    if (which >= 1 && !cd.ctrl[kActive]) return;
+    if (which == 2 && !cd.scale) return;
     for (int c = threadIdx.x; c < s; c += kThreads) {
         double t = 0.0;
         for (int p = 0; p < cd.wgs; ++p) t += cd.parts[static_cast<size_t>(p) * s + c];
@@ -1541,8 +1545,8 @@ __global__ __launch_bounds__(kThreads) void colsq_reduce_kernel(const ChipDev *_
     }
 }
 
-// Inner-solve start for active chips: W = (T) R64, D = P = AP = 0 (padding
-// rows included); C = I and M1 = 0.
+// Inner-solve start for active chips: W = (T) R64 (S R64 under Jacobi
+// scaling), D = P = AP = 0 (padding rows included); C = I and M1 = 0.
 template <class T>
 __global__ __launch_bounds__(kThreads) void inner_start_kernel(const ChipDev *__restrict__ cds,
                                                                const uint16_t *__restrict__ tab, int s)
@@ -1555,9 +1559,10 @@ __global__ __launch_bounds__(kThreads) void inner_start_kernel(const ChipDev *__
     T *W = static_cast<T *>(cd.W), *D = static_cast<T *>(cd.Dv), *P = static_cast<T *>(cd.P), *AP = static_cast<T *>(cd.AP);
     for (int64_t tile = local; tile < ntiles; tile += wgs) {
         const int64_t a = tile * kTileRows + threadIdx.x;
+        const double sa = cd.scale ? (a < cd.n ? cd.scale[a] : 0.0) : 1.0;
         for (int c = 0; c < s; ++c) {
             const int64_t e = c * ldw + a;
-            W[e] = static_cast<T>(cd.R64[e]);
+            W[e] = static_cast<T>(cd.R64[e] * sa);
             D[e] = T(0);
             P[e] = T(0);
             AP[e] = T(0);
@@ -1659,7 +1664,7 @@ __global__ __launch_bounds__(kThreads) void scale_cols_kernel(const ChipDev *__r
     }
 }
 
-// X (FP64) += D (type T) for active chips.
+// X (FP64) += D (type T), or S D under Jacobi scaling, for active chips.
 template <class T>
 __global__ __launch_bounds__(kThreads) void add_out_kernel(const ChipDev *__restrict__ cds,
                                                            const uint16_t *__restrict__ tab, int s)
@@ -1673,7 +1678,8 @@ __global__ __launch_bounds__(kThreads) void add_out_kernel(const ChipDev *__rest
     for (int64_t tile = local; tile < ntiles; tile += wgs) {
         const int64_t a = tile * kTileRows + threadIdx.x;
         if (a >= cd.n) continue;
-        for (int c = 0; c < s; ++c) cd.X[c * cd.ldx + a] += static_cast<double>(D[c * cd.ldw + a]);
+        const double sa = cd.scale ? cd.scale[a] : 1.0;
+        for (int c = 0; c < s; ++c) cd.X[c * cd.ldx + a] += sa * static_cast<double>(D[c * cd.ldw + a]);
     }
 }
 
@@ -1782,10 +1788,19 @@ std::vector<ChipDev> chip_records(const Layout &L, void *work, const double *con
         const Operator &op = *h.op;
         ChipDev &d = v[c];
         std::memset(&d, 0, sizeof(d));
-        d.cdiag = f64 ? static_cast<const void *>(op.diag64) : static_cast<const void *>(op.diag32);
-        d.cwx = f64 ? static_cast<const void *>(op.wx64) : static_cast<const void *>(op.wx32);
-        d.cwy = f64 ? static_cast<const void *>(op.wy64) : static_cast<const void *>(op.wy32);
-        d.cwz = f64 ? static_cast<const void *>(op.wz64) : static_cast<const void *>(op.wz32);
+        if (op.precond == BKO_PRECOND_JACOBI) {
+            d.cdiag = f64 ? static_cast<const void *>(op.sdiag64) : static_cast<const void *>(op.sdiag32);
+            d.cwx = f64 ? static_cast<const void *>(op.swx64) : static_cast<const void *>(op.swx32);
+            d.cwy = f64 ? static_cast<const void *>(op.swy64) : static_cast<const void *>(op.swy32);
+            d.cwz = f64 ? static_cast<const void *>(op.swz64) : static_cast<const void *>(op.swz32);
+            d.scale = op.scale64;
+        } else {
+            d.cdiag = f64 ? static_cast<const void *>(op.diag64) : static_cast<const void *>(op.diag32);
+            d.cwx = f64 ? static_cast<const void *>(op.wx64) : static_cast<const void *>(op.wx32);
+            d.cwy = f64 ? static_cast<const void *>(op.wy64) : static_cast<const void *>(op.wy32);
+            d.cwz = f64 ? static_cast<const void *>(op.wz64) : static_cast<const void *>(op.wz32);
+            d.scale = nullptr;
+        }
         d.d64 = op.diag64;
         d.x64 = op.wx64;
         d.y64 = op.wy64;
@@ -2051,9 +2066,12 @@ bko_status batch_solve_t(const Layout &L, void *work, const double *const *B, co
     }
     // chip records and the workgroup table (host copies live until the final synchronisation)
     const std::vector<ChipDev> recs = chip_records(L, work, B, ldb, X, ldx, X0, ldx0);
+    bool any_scaled = false;
+    for (const ChipDev &r : recs) any_scaled = any_scaled || r.scale != nullptr;
     const std::vector<uint16_t> tabh = wg_table(L);
     std::vector<int> ctrlh(static_cast<size_t>(kCtrlInts) * nc, 0);
-    std::vector<double> thh(static_cast<size_t>(kMaxS) * nc, 0.0), nh(static_cast<size_t>(kMaxS) * nc, 0.0);
+    std::vector<double> thh(static_cast<size_t>(kMaxS) * nc, 0.0), nh(static_cast<size_t>(kMaxS) * nc, 0.0),
+        sh(static_cast<size_t>(kMaxS) * nc, 0.0);
     Ctx x{&L, reinterpret_cast<const ChipDev *>(base + L.off_cds), reinterpret_cast<const uint16_t *>(base + L.off_tab), st};
     int *ctrl_d = reinterpret_cast<int *>(base + L.off_ctrl);
     double *th_d = reinterpret_cast<double *>(base + L.off_th);
@@ -2129,6 +2147,12 @@ bko_status batch_solve_t(const Layout &L, void *work, const double *const *B, co
         }
         if ((rc = host_norms(x, 1)) != BKO_OK) return rc;
         BKO_HIP(hipMemcpyAsync(nh.data(), norms_d, sizeof(double) * nh.size(), hipMemcpyDeviceToHost, st));
+        if (any_scaled) {
+            // norms of S R for the chips under Jacobi scaling (their inner
+            // solves measure the scaled residual)
+            if ((rc = host_norms(x, 2)) != BKO_OK) return rc;
+            BKO_HIP(hipMemcpyAsync(sh.data(), norms_d, sizeof(double) * sh.size(), hipMemcpyDeviceToHost, st));
+        }
         BKO_HIP(hipStreamSynchronize(st));
         int active = 0;
         for (int c = 0; c < nc; ++c) {
@@ -2165,8 +2189,16 @@ bko_status batch_solve_t(const Layout &L, void *work, const double *const *B, co
             ch[kActive] = 1;
             ++active;
             for (int j = 0; j < s; ++j) {
-                const double target = 0.5 * tol * k.bnorm[j];
-                thh[static_cast<size_t>(c) * kMaxS + j] = f64 ? target : std::max(target, inner_rel_f32 * k.rnorm[j]);
+                // under Jacobi scaling the inner target is the scaled one,
+                // by the ratio of the scaled to the unscaled residual norm at
+                // the start (the FP64 loop checks the unscaled residual)
+                double rn = k.rnorm[j], ratio = 1.0;
+                if (recs[c].scale) {
+                    rn = std::sqrt(sh[static_cast<size_t>(c) * kMaxS + j]);
+                    ratio = k.rnorm[j] > 0.0 ? rn / k.rnorm[j] : 1.0;
+                }
+                const double target = 0.5 * tol * k.bnorm[j] * ratio;
+                thh[static_cast<size_t>(c) * kMaxS + j] = f64 ? target : std::max(target, inner_rel_f32 * rn);
             }
         }
         if (active == 0) break;

@@ -48,6 +48,16 @@ CoeffLayout coeff_layout(int64_t n)
         L.off[a] = off;
         off = align_up(off + sizeof(float) * static_cast<size_t>(n), 256);
     }
+    for (int a = 8; a < 12; ++a) {
+        L.off[a] = off;
+        off = align_up(off + sizeof(double) * static_cast<size_t>(n), 256);
+    }
+    for (int a = 12; a < 16; ++a) {
+        L.off[a] = off;
+        off = align_up(off + sizeof(float) * static_cast<size_t>(n), 256);
+    }
+    L.off[16] = off;
+    off = align_up(off + sizeof(double) * static_cast<size_t>(n), 256);
     L.status_off = off;
     L.bytes = off + 256;
     return L;
@@ -185,6 +195,41 @@ __global__ __launch_bounds__(256) void assemble_kernel(int nx, int ny, int nz, F
     wz32[a] = static_cast<float>(plus[2]);
 }
 
+// The symmetrically scaled operator S A S with S = diag(A)^(-1/2) (the
+// Jacobi preconditioner applied on both sides, which keeps the operator
+// symmetric): diagonal d s^2, forward coupling w_ab s_a s_b.
+__global__ void scale_coeff_kernel(int nx, int ny, int nz, const double *__restrict__ diag,
+                                   const double *__restrict__ wx, const double *__restrict__ wy,
+                                   const double *__restrict__ wz, double *__restrict__ sdiag64,
+                                   double *__restrict__ swx64, double *__restrict__ swy64,
+                                   double *__restrict__ swz64, float *__restrict__ sdiag32, float *__restrict__ swx32,
+                                   float *__restrict__ swy32, float *__restrict__ swz32, double *__restrict__ scale)
+{
+    const int64_t plane = static_cast<int64_t>(nx) * ny;
+    const int64_t n = plane * nz;
+    const int64_t a = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const int i = static_cast<int>(a % nx);
+    const int j = static_cast<int>((a / nx) % ny);
+    const int l = static_cast<int>(a / plane);
+    const double sa = 1.0 / sqrt(diag[a]);
+    // a coupling to a missing neighbour is zero; its partner's scale is unused
+    const double sx = i < nx - 1 ? 1.0 / sqrt(diag[a + 1]) : 0.0;
+    const double sy = j < ny - 1 ? 1.0 / sqrt(diag[a + nx]) : 0.0;
+    const double sz = l < nz - 1 ? 1.0 / sqrt(diag[a + plane]) : 0.0;
+    const double d = diag[a] * sa * sa;
+    const double cx = wx[a] * sa * sx, cy = wy[a] * sa * sy, cz = wz[a] * sa * sz;
+    scale[a] = sa;
+    sdiag64[a] = d;
+    swx64[a] = cx;
+    swy64[a] = cy;
+    swz64[a] = cz;
+    sdiag32[a] = static_cast<float>(d);
+    swx32[a] = static_cast<float>(cx);
+    swy32[a] = static_cast<float>(cy);
+    swz32[a] = static_cast<float>(cz);
+}
+
 __global__ void zero_kernel(uint32_t *p, size_t words)
 {
     const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
@@ -293,6 +338,18 @@ bko_status bko_assemble_heat_operator(int nx, int ny, int nz, double lx, double 
         set_error("%d cells have conductivity <= 0 or not finite", nbad);
         return BKO_ENOTSPD;
     }
+    // every diagonal is positive here (each cell couples to a neighbour or a
+    // non-adiabatic face with positive weight), so S is defined
+    hipLaunchKernelGGL(scale_coeff_kernel, dim3(blocks), dim3(256), 0, s, nx, ny, nz,
+                       reinterpret_cast<const double *>(base + L.off[0]), reinterpret_cast<const double *>(base + L.off[1]),
+                       reinterpret_cast<const double *>(base + L.off[2]), reinterpret_cast<const double *>(base + L.off[3]),
+                       reinterpret_cast<double *>(base + L.off[8]), reinterpret_cast<double *>(base + L.off[9]),
+                       reinterpret_cast<double *>(base + L.off[10]), reinterpret_cast<double *>(base + L.off[11]),
+                       reinterpret_cast<float *>(base + L.off[12]), reinterpret_cast<float *>(base + L.off[13]),
+                       reinterpret_cast<float *>(base + L.off[14]), reinterpret_cast<float *>(base + L.off[15]),
+                       reinterpret_cast<double *>(base + L.off[16]));
+    BKO_HIP(hipGetLastError());
+    BKO_HIP(hipStreamSynchronize(s));
     Operator *op = new Operator();
     op->nx = nx;
     op->ny = ny;
@@ -310,6 +367,16 @@ bko_status bko_assemble_heat_operator(int nx, int ny, int nz, double lx, double 
     op->wx32 = reinterpret_cast<const float *>(base + L.off[5]);
     op->wy32 = reinterpret_cast<const float *>(base + L.off[6]);
     op->wz32 = reinterpret_cast<const float *>(base + L.off[7]);
+    op->sdiag64 = reinterpret_cast<const double *>(base + L.off[8]);
+    op->swx64 = reinterpret_cast<const double *>(base + L.off[9]);
+    op->swy64 = reinterpret_cast<const double *>(base + L.off[10]);
+    op->swz64 = reinterpret_cast<const double *>(base + L.off[11]);
+    op->sdiag32 = reinterpret_cast<const float *>(base + L.off[12]);
+    op->swx32 = reinterpret_cast<const float *>(base + L.off[13]);
+    op->swy32 = reinterpret_cast<const float *>(base + L.off[14]);
+    op->swz32 = reinterpret_cast<const float *>(base + L.off[15]);
+    op->scale64 = reinterpret_cast<const double *>(base + L.off[16]);
+    op->precond = BKO_PRECOND_NONE;
     *out = reinterpret_cast<bko_op>(op);
     return BKO_OK;
     BKO_GUARD_END
@@ -322,6 +389,21 @@ bko_status bko_operator_dims(bko_op A, int *nx, int *ny, int *nz)
     if (nx) *nx = op->nx;
     if (ny) *ny = op->ny;
     if (nz) *nz = op->nz;
+    return BKO_OK;
+}
+
+bko_status bko_operator_set_precond(bko_op A, int kind)
+{
+    BKO_CHECK(A != nullptr, "operator handle is NULL");
+    BKO_CHECK(kind == BKO_PRECOND_NONE || kind == BKO_PRECOND_JACOBI, "unknown preconditioner %d", kind);
+    reinterpret_cast<Operator *>(A)->precond = kind;
+    return BKO_OK;
+}
+
+bko_status bko_operator_get_precond(bko_op A, int *kind)
+{
+    BKO_CHECK(A != nullptr && kind != nullptr, "NULL argument");
+    *kind = reinterpret_cast<const Operator *>(A)->precond;
     return BKO_OK;
 }
 

@@ -6,7 +6,10 @@
 //     x_0 = 0, r_0 = p_0 = b
 //     alpha = (r^T r) / (p^T A p) ; x += alpha p ; r -= alpha A p
 //     beta  = (r'^T r') / (r^T r) ; p  = r' + beta p
-// until ||r|| <= tol ||b||.  FP64 throughout, no preconditioner.
+// until ||r|| <= tol ||b||.  FP64 throughout.  With the operator's Jacobi
+// preconditioner (M = diag(A)) it is preconditioned CG: z = M^-1 r,
+// rho = r^T z, beta = rho' / rho, p = z' + beta p, with the same stop test
+// on the unpreconditioned residual.
 //
 // Kernels per iteration (one stream, no host round trip): stencil A p; column
 // dot partials p^T A p; per-column alpha; x, r update with r^T r partials;
@@ -32,6 +35,7 @@ struct CgWork {
     int64_t ldw;
     double *R, *P, *AP;
     double *part;     // [chunks][m] column partial sums
+    double *part2;    // [chunks][m] partial sums of r^T M^-1 r (preconditioned)
     double *rho, *alpha, *beta, *th2;
     int *done, *iters, *ctrl;
     int chunks;
@@ -55,6 +59,7 @@ inline CgWork carve_cg(void *base, int64_t n, int m)
     w.P = reinterpret_cast<double *>(take(blk));
     w.AP = reinterpret_cast<double *>(take(blk));
     w.part = reinterpret_cast<double *>(take(sizeof(double) * static_cast<size_t>(w.chunks) * m));
+    w.part2 = reinterpret_cast<double *>(take(sizeof(double) * static_cast<size_t>(w.chunks) * m));
     w.rho = reinterpret_cast<double *>(take(sizeof(double) * m));
     w.alpha = reinterpret_cast<double *>(take(sizeof(double) * m));
     w.beta = reinterpret_cast<double *>(take(sizeof(double) * m));
@@ -77,11 +82,13 @@ __device__ inline double block_sum(double v, double *sh)
     return sh[0];
 }
 
-// part[c * m + j] = sum over rows of chunk c of a_j * b_j (grid: chunks x m)
+// part[c * m + j] = sum over rows of chunk c of a_j * b_j, times scale^2
+// per row when scale is given (grid: chunks x m)
 __global__ __launch_bounds__(kCgThreads) void coldot_kernel(const double *__restrict__ a, int64_t lda,
                                                             const double *__restrict__ b, int64_t ldb, int64_t n,
                                                             int m, double *__restrict__ part,
-                                                            const int *__restrict__ done)
+                                                            const int *__restrict__ done,
+                                                            const double *__restrict__ scale = nullptr)
 {
     __shared__ double sh[kCgThreads];
     const int j = blockIdx.y;
@@ -90,7 +97,10 @@ __global__ __launch_bounds__(kCgThreads) void coldot_kernel(const double *__rest
     const int64_t r1 = min(n, r0 + kRowsPerChunk);
     const double *aj = a + j * lda, *bj = b + j * ldb;
     double acc = 0.0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += kCgThreads) acc = fma(aj[r], bj[r], acc);
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += kCgThreads) {
+        const double w = scale ? scale[r] * scale[r] : 1.0;
+        acc = fma(aj[r] * w, bj[r], acc);
+    }
     const double t = block_sum(acc, sh);
     if (threadIdx.x == 0) part[static_cast<int64_t>(blockIdx.x) * m + j] = t;
 }
@@ -113,12 +123,15 @@ __global__ void cg_alpha_kernel(const double *__restrict__ part, int chunks, int
     alpha[j] = pap > 0.0 ? rho[j] / pap : 0.0;
 }
 
-// x += alpha p ; r -= alpha A p ; part = chunk sums of r^T r  (grid: chunks x m)
+// x += alpha p ; r -= alpha A p ; part = chunk sums of r^T r and, with a
+// preconditioner (scale^2 = M^-1), part2 = chunk sums of r^T M^-1 r
+// (grid: chunks x m)
 __global__ __launch_bounds__(kCgThreads) void cg_update_kernel(double *__restrict__ X, int64_t ldx,
                                                                double *__restrict__ R, const double *__restrict__ P,
                                                                const double *__restrict__ AP, int64_t ldw, int64_t n,
                                                                int m, const double *__restrict__ alpha,
-                                                               double *__restrict__ part,
+                                                               double *__restrict__ part, double *__restrict__ part2,
+                                                               const double *__restrict__ scale,
                                                                const int *__restrict__ done)
 {
     __shared__ double sh[kCgThreads];
@@ -129,21 +142,28 @@ __global__ __launch_bounds__(kCgThreads) void cg_update_kernel(double *__restric
     const int64_t r1 = min(n, r0 + kRowsPerChunk);
     double *xj = X + j * ldx, *rj = R + j * ldw;
     const double *pj = P + j * ldw, *qj = AP + j * ldw;
-    double acc = 0.0;
+    double acc = 0.0, acc2 = 0.0;
     for (int64_t r = r0 + threadIdx.x; r < r1; r += kCgThreads) {
         xj[r] = fma(a, pj[r], xj[r]);
         const double rv = fma(-a, qj[r], rj[r]);
         rj[r] = rv;
         acc = fma(rv, rv, acc);
+        if (scale) acc2 = fma(rv * scale[r] * scale[r], rv, acc2);
     }
     const double t = block_sum(acc, sh);
     if (threadIdx.x == 0) part[static_cast<int64_t>(blockIdx.x) * m + j] = t;
+    if (scale) {
+        __syncthreads();
+        const double t2 = block_sum(acc2, sh);
+        if (threadIdx.x == 0) part2[static_cast<int64_t>(blockIdx.x) * m + j] = t2;
+    }
 }
 
 // Per column: the new r^T r, the stop test and beta; one workgroup counts the
 // columns still running into ctrl[kRemaining].  With first != 0 the partials
 // hold r_0^T r_0 and only rho and the stop test are set.
-__global__ __launch_bounds__(kCgThreads) void cg_beta_kernel(const double *__restrict__ part, int chunks, int m,
+__global__ __launch_bounds__(kCgThreads) void cg_beta_kernel(const double *__restrict__ part,
+                                                             const double *__restrict__ part2, int chunks, int m,
                                                              double *__restrict__ rho, double *__restrict__ beta,
                                                              const double *__restrict__ th2, int *__restrict__ done,
                                                              int *__restrict__ iters, int *__restrict__ ctrl, int first)
@@ -153,12 +173,13 @@ __global__ __launch_bounds__(kCgThreads) void cg_beta_kernel(const double *__res
     for (int j = threadIdx.x; j < m; j += kCgThreads) {
         if (done[j]) continue;
         const double rr = sum_parts(part, chunks, m, j);
+        const double rz = part2 ? sum_parts(part2, chunks, m, j) : rr;  // r^T z (z = M^-1 r)
         if (first) {
-            rho[j] = rr;
+            rho[j] = rz;
             iters[j] = 0;
         } else {
-            beta[j] = rho[j] > 0.0 ? rr / rho[j] : 0.0;
-            rho[j] = rr;
+            beta[j] = rho[j] > 0.0 ? rz / rho[j] : 0.0;
+            rho[j] = rz;
             iters[j] += 1;
         }
         if (rr <= th2[j]) done[j] = 1;
@@ -168,9 +189,11 @@ __global__ __launch_bounds__(kCgThreads) void cg_beta_kernel(const double *__res
     if (threadIdx.x == 0) ctrl[kRemaining] = static_cast<int>(tot);
 }
 
-// p = r + beta p for active columns (grid: blocks over rows x m)
+// p = z + beta p for active columns, z = r or M^-1 r = scale^2 r (grid:
+// blocks over rows x m)
 __global__ __launch_bounds__(kCgThreads) void cg_p_kernel(double *__restrict__ P, const double *__restrict__ R,
                                                           int64_t ldw, int64_t n, const double *__restrict__ beta,
+                                                          const double *__restrict__ scale,
                                                           const int *__restrict__ done, int first)
 {
     const int j = blockIdx.y;
@@ -178,7 +201,8 @@ __global__ __launch_bounds__(kCgThreads) void cg_p_kernel(double *__restrict__ P
     const int64_t r = static_cast<int64_t>(blockIdx.x) * kCgThreads + threadIdx.x;
     if (r >= n) return;
     const double b = first ? 0.0 : beta[j];
-    P[j * ldw + r] = first ? R[j * ldw + r] : fma(b, P[j * ldw + r], R[j * ldw + r]);
+    const double z = scale ? R[j * ldw + r] * scale[r] * scale[r] : R[j * ldw + r];
+    P[j * ldw + r] = first ? z : fma(b, P[j * ldw + r], z);
 }
 
 // R (ldw) = B (ldb), X = 0, rows < n
@@ -229,9 +253,15 @@ bko_status cg_solve(const Operator &op, int m, const double *B, int64_t ldb, dou
                        nullptr);
     hipLaunchKernelGGL(cg_threshold_kernel, dim3(col_blocks), dim3(256), 0, st, w.part, w.chunks, m, tol, w.th2,
                        w.done);
-    hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(kCgThreads), 0, st, w.part, w.chunks, m, w.rho, w.beta, w.th2,
-                       w.done, w.iters, w.ctrl, 1);
-    hipLaunchKernelGGL(cg_p_kernel, rows_grid, dim3(kCgThreads), 0, st, w.P, w.R, w.ldw, n, w.beta, w.done, 1);
+    // Jacobi: z = M^-1 r with M^-1 = scale^2
+    const double *scale = op.precond == BKO_PRECOND_JACOBI ? op.scale64 : nullptr;
+    double *part2 = scale ? w.part2 : nullptr;
+    if (scale)
+        hipLaunchKernelGGL(coldot_kernel, chunk_grid, dim3(kCgThreads), 0, st, w.R, w.ldw, w.R, w.ldw, n, m, w.part2,
+                           nullptr, scale);
+    hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(kCgThreads), 0, st, w.part, part2, w.chunks, m, w.rho, w.beta,
+                       w.th2, w.done, w.iters, w.ctrl, 1);
+    hipLaunchKernelGGL(cg_p_kernel, rows_grid, dim3(kCgThreads), 0, st, w.P, w.R, w.ldw, n, w.beta, scale, w.done, 1);
     BKO_HIP(hipGetLastError());
 
     int remaining = m, launched = 0, chunk = 8;
@@ -249,11 +279,11 @@ bko_status cg_solve(const Operator &op, int m, const double *B, int64_t ldb, dou
             hipLaunchKernelGGL(cg_alpha_kernel, dim3(col_blocks), dim3(256), 0, st, w.part, w.chunks, m, w.rho,
                                w.alpha, w.done);
             hipLaunchKernelGGL(cg_update_kernel, chunk_grid, dim3(kCgThreads), 0, st, X, ldx, w.R, w.P, w.AP, w.ldw,
-                               n, m, w.alpha, w.part, w.done);
-            hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(kCgThreads), 0, st, w.part, w.chunks, m, w.rho, w.beta,
-                               w.th2, w.done, w.iters, w.ctrl, 0);
-            hipLaunchKernelGGL(cg_p_kernel, rows_grid, dim3(kCgThreads), 0, st, w.P, w.R, w.ldw, n, w.beta, w.done,
-                               0);
+                               n, m, w.alpha, w.part, part2, scale, w.done);
+            hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(kCgThreads), 0, st, w.part, part2, w.chunks, m, w.rho,
+                               w.beta, w.th2, w.done, w.iters, w.ctrl, 0);
+            hipLaunchKernelGGL(cg_p_kernel, rows_grid, dim3(kCgThreads), 0, st, w.P, w.R, w.ldw, n, w.beta, scale,
+                               w.done, 0);
             BKO_HIP(hipGetLastError());
         }
         launched += todo;

@@ -136,14 +136,20 @@ struct Operator {
     double lx, ly, lz;
     int64_t n;
     void *coeff;          // caller-owned device buffer
-    // FP64 coefficient arrays (device pointers into coeff)
+    // FP64 coefficient arrays (device pointers into coeff) and FP32 copies
     const double *diag64, *wx64, *wy64, *wz64;
     const float *diag32, *wx32, *wy32, *wz32;
+    // the symmetrically diagonal-scaled operator S A S, S = diag(A)^(-1/2)
+    // (its diagonal is 1 up to rounding), FP64 and FP32, and S in FP64
+    const double *sdiag64, *swx64, *swy64, *swz64;
+    const float *sdiag32, *swx32, *swy32, *swz32;
+    const double *scale64;
+    int precond;  // bko_precond used by the solves on this operator
 };
 
 // Byte layout of the coefficient buffer.
 struct CoeffLayout {
-    size_t off[8];
+    size_t off[17];  // A in FP64 (4), FP32 (4); S A S in FP64 (4), FP32 (4); S in FP64
     size_t status_off;
     size_t bytes;
 };
