@@ -393,15 +393,23 @@ bko_status bko_lstart_unpack(int n, const float *y, int m, const double *scale, 
 
 /*
  * Optional per-kernel timing: `mask` selects kernel families (bit f = family
- * f, 0 = off).  For a selected family the library records a HIP event pair
- * around every launch on the launch stream and accumulates the elapsed time
- * when queried (which synchronises).
+ * f, 0 = off).  For a selected family the library takes a HIP event pair per
+ * launch on the launch stream and accumulates the elapsed time when queried
+ * (which synchronises): the block-solve kernels take the pair inside their
+ * own dispatch (kernel begin and end, what a kernel trace records); the
+ * operator action, combine and per-sample CG stencil bracket their launch
+ * with stream markers.  bko_timing_set_stride(k) times one launch in every
+ * k of each family (k >= 1, default 1; resets the per-family counters), so
+ * that the events' own cost stays small in a timed loop; bko_timing_query
+ * then counts the timed launches only.
  * Families: 0 = operator action, 1 = combine, 2 = Gram partials, 3 = block
- * update W, 4 = Gram reduction + s x s factorisation, 5 = block-solve stencil
- * product, 6 = FP64 residual, 7 = block update D, Q, P.  Used to report
- * per-kernel bandwidth.
+ * update W, 4 = Gram reduction (+ s x s factorisation for s > 32), 5 =
+ * block-solve stencil product, 6 = FP64 residual, 7 = block update D, Q, P.
+ * Timed launches are not captured into graphs.  Used to report per-kernel
+ * bandwidth.
  */
 bko_status bko_timing_enable(int mask);
+bko_status bko_timing_set_stride(int every);
 bko_status bko_timing_query(int family, int *launches, double *total_ms);
 bko_status bko_timing_reset(void);
 

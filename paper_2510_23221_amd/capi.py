@@ -40,7 +40,7 @@ EXPORTED = ("bko_version", "bko_last_error", "bko_operator_bytes", "bko_assemble
             "bko_nn_conv2d_wgrad", "bko_unet_create", "bko_unet_destroy", "bko_unet_sizes", "bko_unet_set_params",
             "bko_unet_forward", "bko_unet_gradient", "bko_unet_adam_step", "bko_lstart_pack",
             "bko_lstart_pack_target", "bko_lstart_unpack", "bko_jacobi_smooth", "bko_operator_set_precond",
-            "bko_operator_get_precond")
+            "bko_operator_get_precond", "bko_timing_set_stride")
 
 
 class BlockoaError(RuntimeError):
@@ -612,6 +612,11 @@ def residual(A: HeatOperator, B: torch.Tensor, X: torch.Tensor, R: Optional[torc
 # ------------------------------------------------------------------ timing hooks
 
 FAMILY = {"apply": 0, "combine": 1, "gram": 2, "update_w": 3, "factor": 4, "spmm": 5, "resid": 6, "update_dqp": 7}
+
+
+def timing_stride(every: int = 1):
+    """Time one launch in every `every` of each selected family."""
+    _check(load_library().bko_timing_set_stride(int(every)))
 
 
 def timing_enable(families=None):

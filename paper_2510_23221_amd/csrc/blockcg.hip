@@ -1870,19 +1870,17 @@ bko_status launch_row_kernels(int which, const Ctx &x, int init)
     if (which == 0) {
         TimedLaunch tl(kSpmm, x.st);
         if (x.L->nx_align % vec_cells<T>() == 0)
-            hipLaunchKernelGGL((spmm_gram_vec_kernel<T, NB>), grid, dim3(kSpThreads), (spmm_gram_lds<T, NB>()), x.st,
-                               x.cds, x.tab, s);
+            tl.launch(spmm_gram_vec_kernel<T, NB>, grid, dim3(kSpThreads), spmm_gram_lds<T, NB>(), x.cds, x.tab, s);
         else
-            hipLaunchKernelGGL((spmm_gram_kernel<T, NB>), grid, dim3(kSpThreads), (spmm_gram_lds<T, NB>()), x.st,
-                               x.cds, x.tab, s);
+            tl.launch(spmm_gram_kernel<T, NB>, grid, dim3(kSpThreads), spmm_gram_lds<T, NB>(), x.cds, x.tab, s);
     } else if (which == 1) {
         TimedLaunch tl(kUpdate, x.st);
-        hipLaunchKernelGGL((update_w_kernel<T, NB>), grid, block, 0, x.st, x.cds, x.tab, s, init);
+        tl.launch(update_w_kernel<T, NB>, grid, block, 0, x.cds, x.tab, s, init);
     } else {
         TimedLaunch tl(::bko::kUpdateDQP, x.st);
         const size_t sp = 16 * NB;
-        hipLaunchKernelGGL((update_dqp_kernel<T, NB>), grid, block, 3 * sizeof(T) * sp * (sp + 1), x.st, x.cds, x.tab,
-                           s);
+        tl.launch(update_dqp_kernel<T, NB>, grid, block, static_cast<uint32_t>(3 * sizeof(T) * sp * (sp + 1)), x.cds,
+                  x.tab, s);
     }
     BKO_HIP(hipGetLastError());
     return BKO_OK;
@@ -1943,8 +1941,7 @@ bko_status launch_reduce(const Ctx &x)
     const int ss = x.L->s * x.L->s;
     TimedLaunch tl(kSmall, x.st);
     const unsigned rblocks = static_cast<unsigned>(std::min(kRedBlocks, ss));
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3(rblocks, static_cast<unsigned>(x.L->nchips)), dim3(kThreads), 0, x.st,
-                       x.cds, ss);
+    tl.launch(gram_reduce_kernel, dim3(rblocks, static_cast<unsigned>(x.L->nchips)), dim3(kThreads), 0, x.cds, ss);
     BKO_HIP(hipGetLastError());
     return BKO_OK;
 }
@@ -1958,10 +1955,10 @@ bko_status launch_fused_kernel(int which, const Ctx &x, double rel_thr, int mode
     const int s = x.L->s;
     if (which == 1) {
         TimedLaunch tl(kUpdate, x.st);
-        hipLaunchKernelGGL((update_w_fused_kernel<T, NB>), grid, block, 0, x.st, x.cds, x.tab, s, rel_thr);
+        tl.launch(update_w_fused_kernel<T, NB>, grid, block, 0, x.cds, x.tab, s, rel_thr);
     } else {
         TimedLaunch tl(::bko::kUpdateDQP, x.st);
-        hipLaunchKernelGGL((update_dqp_fused_kernel<T, NB>), grid, block, 0, x.st, x.cds, x.tab, s, rel_thr, mode);
+        tl.launch(update_dqp_fused_kernel<T, NB>, grid, block, 0, x.cds, x.tab, s, rel_thr, mode);
     }
     BKO_HIP(hipGetLastError());
     return BKO_OK;
@@ -2141,8 +2138,7 @@ bko_status batch_solve_t(const Layout &L, void *work, const double *const *B, co
         // R = B - A X in FP64 and its column norms, for the chips still running
         {
             TimedLaunch tl(kResid, st);
-            hipLaunchKernelGGL(residual_kernel, dim3(static_cast<unsigned>(L.total_wgs)), dim3(kThreads), 0, st, x.cds,
-                               x.tab, s);
+            tl.launch(residual_kernel, dim3(static_cast<unsigned>(L.total_wgs)), dim3(kThreads), 0, x.cds, x.tab, s);
             BKO_HIP(hipGetLastError());
         }
         if ((rc = host_norms(x, 1)) != BKO_OK) return rc;

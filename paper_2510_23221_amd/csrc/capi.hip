@@ -74,6 +74,8 @@ struct TimingState {
     std::vector<Pair> pending;
     int launches[kNumFamilies] = {};
     double total_ms[kNumFamilies] = {};
+    unsigned stride = 1;                  // time one launch in every `stride` of a family
+    unsigned counter[kNumFamilies] = {};  // launches seen per family
 };
 TimingState &timing()
 {
@@ -109,13 +111,26 @@ bko_status drain(TimingState &t)
 
 bool timing_active() { return timing().mask != 0; }
 
-TimedLaunch::TimedLaunch(int fam, hipStream_t s) : family(fam), stream(s), ev0(nullptr)
+TimedLaunch::TimedLaunch(int fam, hipStream_t s) : family(fam), stream(s), ev0(nullptr), ev1(nullptr), in_dispatch(false)
 {
     TimingState &t = timing();
     if (!(t.mask & (1u << fam))) return;
     std::lock_guard<std::mutex> g(t.mu);
-    hipEvent_t e = take_event(t);
-    if (e && hipEventRecord(e, s) == hipSuccess) ev0 = e;
+    if (t.counter[fam]++ % t.stride != 0) return;
+    hipEvent_t a = take_event(t), b = take_event(t);
+    if (!a || !b) {
+        if (a) t.pool.push_back(a);
+        if (b) t.pool.push_back(b);
+        return;
+    }
+    // the start marker; launch() re-records it inside the kernel's dispatch
+    if (hipEventRecord(a, s) == hipSuccess) {
+        ev0 = a;
+        ev1 = b;
+    } else {
+        t.pool.push_back(a);
+        t.pool.push_back(b);
+    }
 }
 
 TimedLaunch::~TimedLaunch()
@@ -123,10 +138,13 @@ TimedLaunch::~TimedLaunch()
     if (!ev0) return;
     TimingState &t = timing();
     std::lock_guard<std::mutex> g(t.mu);
-    hipEvent_t e = take_event(t);
-    if (e && hipEventRecord(e, stream) == hipSuccess) {
-        t.pending.push_back({family, static_cast<hipEvent_t>(ev0), e});
+    hipEvent_t b = static_cast<hipEvent_t>(ev1);
+    if (in_dispatch || hipEventRecord(b, stream) == hipSuccess) {
+        t.pending.push_back({family, static_cast<hipEvent_t>(ev0), b});
         if (t.pending.size() > 4096) drain(t);
+    } else {
+        t.pool.push_back(static_cast<hipEvent_t>(ev0));
+        t.pool.push_back(b);
     }
 }
 
@@ -783,6 +801,16 @@ bko_status bko_timing_enable(int enable)
     TimingState &t = timing();
     std::lock_guard<std::mutex> g(t.mu);
     t.mask = static_cast<unsigned>(enable);
+    return BKO_OK;
+}
+
+bko_status bko_timing_set_stride(int every)
+{
+    BKO_CHECK(every >= 1, "timing stride must be >= 1, got %d", every);
+    TimingState &t = timing();
+    std::lock_guard<std::mutex> g(t.mu);
+    t.stride = static_cast<unsigned>(every);
+    for (unsigned &c : t.counter) c = 0;
     return BKO_OK;
 }
 

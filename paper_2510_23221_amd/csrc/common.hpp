@@ -2,6 +2,7 @@
 // conversion, launch bookkeeping and error plumbing.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -173,12 +174,28 @@ enum TimingFamily {
 // are not captured into graphs).
 bool timing_active();
 
+// Events around the launches of one scope when its family is timed: by
+// default two stream markers bracket the scope; launch() instead has the
+// kernel's own dispatch take the two timestamps (its begin and end, as a
+// kernel trace records them), so one-kernel scopes carry no marker gaps.
 struct TimedLaunch {
     TimedLaunch(int family, hipStream_t s);
     ~TimedLaunch();
+    template <class F, class... Args>
+    void launch(F kernel, dim3 grid, dim3 block, uint32_t shmem, Args... args)
+    {
+        if (ev0) {
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, static_cast<hipEvent_t>(ev0),
+                                  static_cast<hipEvent_t>(ev1), 0, args...);
+            in_dispatch = true;
+        } else {
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, args...);
+        }
+    }
     int family;
     hipStream_t stream;
-    void *ev0;
+    void *ev0, *ev1;
+    bool in_dispatch;
 };
 
 }  // namespace bko
