@@ -1683,6 +1683,24 @@ __global__ __launch_bounds__(kThreads) void add_out_kernel(const ChipDev *__rest
     }
 }
 
+// prog[chip] = max_j ||C e_j|| / th_j, the inner solve's residual over its
+// target (||r_j|| = ||C e_j||), or 0 for a chip that has converged (one
+// wavefront per chip).
+__global__ __launch_bounds__(64) void progress_kernel(const ChipDev *__restrict__ cds, int s, double *__restrict__ prog)
+{
+    const ChipDev &cd = cds[blockIdx.x];
+    const int lane = threadIdx.x;
+    double q = 0.0;
+    if (!cd.ctrl[kConverged] && lane < s) {
+        double n2 = 0.0;
+        for (int r = 0; r < s; ++r) n2 = fma(cd.sm.C[r * s + lane], cd.sm.C[r * s + lane], n2);
+        q = sqrt(n2) / cd.sm.th[lane];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) q = fmax(q, __shfl_xor(q, off));
+    if (lane == 0) prog[blockIdx.x] = cd.ctrl[kConverged] ? 0.0 : q;
+}
+
 // ------------------------------------------------------------------ host side
 
 inline int nb_for(int s) { return (s + 15) / 16; }
@@ -1700,7 +1718,8 @@ struct Layout {
     int nchips = 0, s = 0, total_wgs = 0, tiles_per_wg = 1;
     int nx_align = 4;  // largest of 1, 2, 4 dividing every chip's nx
     bko_dtype compute = BKO_F64;
-    size_t off_cds = 0, off_tab = 0, off_th = 0, off_ctrl = 0, off_norms = 0, off_alpha = 0, off_dots = 0, bytes = 0;
+    size_t off_cds = 0, off_tab = 0, off_th = 0, off_ctrl = 0, off_norms = 0, off_alpha = 0, off_dots = 0, off_prog = 0,
+           bytes = 0;
     std::vector<ChipHost> chips;
 };
 
@@ -1770,6 +1789,7 @@ Layout make_layout(const Operator *const *ops, int nchips, int s, bko_dtype comp
     L.off_norms = take(sizeof(double) * kMaxS * nchips);
     L.off_alpha = take(sizeof(double) * kMaxS * nchips);
     L.off_dots = take(sizeof(double) * 2 * kMaxS * nchips);
+    L.off_prog = take(sizeof(double) * nchips);
     for (int c = 0; c < nchips; ++c) L.chips[c].off = take(chip_region_bytes(L.chips[c].ldw, s, compute, nullptr));
     L.bytes = o;
     return L;
@@ -2002,25 +2022,30 @@ bko_status run_chunk(const Ctx &x, double rel_thr, int len, GraphCache *gc, void
     }
     if (gc->work != work) gc->clear();
     gc->work = work;
-    auto found = gc->execs.find(len);
-    if (found == gc->execs.end()) {
-        BKO_HIP(hipStreamBeginCapture(x.st, hipStreamCaptureModeThreadLocal));
-        bko_status rc = BKO_OK;
-        for (int it = 0; it < len && rc == BKO_OK; ++it) rc = iteration<T>(x, rel_thr);
-        hipGraph_t g = nullptr;
-        const hipError_t e = hipStreamEndCapture(x.st, &g);
-        if (rc != BKO_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return rc;
+    // a chunk of any length replays the graphs of its binary digits, so at
+    // most seven graphs (1, 2, 4, ..., 64 iterations) are ever captured
+    for (int bit = 64; bit >= 1; bit >>= 1) {
+        if (!(len & bit)) continue;
+        auto found = gc->execs.find(bit);
+        if (found == gc->execs.end()) {
+            BKO_HIP(hipStreamBeginCapture(x.st, hipStreamCaptureModeThreadLocal));
+            bko_status rc = BKO_OK;
+            for (int it = 0; it < bit && rc == BKO_OK; ++it) rc = iteration<T>(x, rel_thr);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(x.st, &g);
+            if (rc != BKO_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            hipGraphExec_t ex = nullptr;
+            const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ei != hipSuccess) return hip_fail(ei, "hipGraphInstantiate");
+            found = gc->execs.emplace(bit, ex).first;
         }
-        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-        hipGraphExec_t ex = nullptr;
-        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (ei != hipSuccess) return hip_fail(ei, "hipGraphInstantiate");
-        found = gc->execs.emplace(len, ex).first;
+        BKO_HIP(hipGraphLaunch(found->second, x.st));
     }
-    BKO_HIP(hipGraphLaunch(found->second, x.st));
     return BKO_OK;
 }
 
@@ -2215,14 +2240,48 @@ bko_status batch_solve_t(const Layout &L, void *work, const double *const *B, co
         int budget = 0;
         for (int c = 0; c < nc; ++c)
             if (!cs[c].done) budget = std::max(budget, max_iter - cs[c].info.iters);
+        // chunk lengths between convergence checks: each check also reads
+        // every chip's residual-over-target ratio; from its decay over the
+        // last chunk the next chunk runs the predicted remaining iterations
+        // (at most 64), so few launches past convergence are wasted
         int launched = 0, chunk = 4;
         std::vector<int> hc(ctrlh.size());
+        std::vector<double> prog(static_cast<size_t>(nc), 0.0), prev(static_cast<size_t>(nc), 0.0);
+        for (int c = 0; c < nc; ++c) {
+            if (cs[c].done) continue;
+            double q = 0.0;
+            for (int j = 0; j < s; ++j) {
+                const double t = thh[static_cast<size_t>(c) * kMaxS + j];
+                const double rn = recs[c].scale ? std::sqrt(sh[static_cast<size_t>(c) * kMaxS + j]) : cs[c].rnorm[j];
+                if (t > 0.0) q = std::max(q, rn / t);
+            }
+            prev[c] = q;
+        }
+        double *prog_d = reinterpret_cast<double *>(base + L.off_prog);
         while (true) {
             const int todo = std::min(chunk, budget - launched);
             if ((rc = run_chunk<T>(x, rel_thr, todo, gc, work)) != BKO_OK) return rc;
             launched += todo;
+            hipLaunchKernelGGL(progress_kernel, dim3(static_cast<unsigned>(nc)), dim3(64), 0, st, x.cds, s, prog_d);
+            BKO_HIP(hipGetLastError());
             BKO_HIP(hipMemcpyAsync(hc.data(), ctrl_d, sizeof(int) * hc.size(), hipMemcpyDeviceToHost, st));
+            BKO_HIP(hipMemcpyAsync(prog.data(), prog_d, sizeof(double) * prog.size(), hipMemcpyDeviceToHost, st));
             BKO_HIP(hipStreamSynchronize(st));
+            int predicted = 0;
+            bool known = true;
+            for (int c = 0; c < nc; ++c) {
+                if (cs[c].done || hc[static_cast<size_t>(c) * kCtrlInts + kConverged]) continue;
+                const double q = prog[c], q0 = prev[c];
+                prev[c] = q;
+                if (!(q > 1.0) || !(q0 > q) || !std::isfinite(q0)) {
+                    known = known && q > 0.0 && q <= 1.0;
+                    continue;
+                }
+                const double rate = std::log(q0 / q) / todo;  // per iteration
+                const double more = std::ceil(std::log(q) / rate) + 1.0;
+                predicted = std::max(predicted, static_cast<int>(std::min(more, 64.0)));
+            }
+            const int next = known && predicted > 0 ? predicted : std::min(chunk * 2, 64);
             bool all = true, capped = false;
             for (int c = 0; c < nc; ++c) {
                 if (cs[c].done) continue;
@@ -2240,7 +2299,7 @@ bko_status batch_solve_t(const Layout &L, void *work, const double *const *B, co
             }
             if (capped) BKO_HIP(hipStreamSynchronize(st));
             if (all || launched >= budget) break;
-            chunk = std::min(chunk * 2, 64);
+            chunk = std::max(1, next);
         }
         for (int c = 0; c < nc; ++c) {
             if (cs[c].done) continue;
