@@ -33,11 +33,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
-# HBM bytes per launch of the default workload's kernels: rocprofv3
-# FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads for a plain
-# device copy of known size (profiles/pmc_traffic_stack128x128x8.md).  Valid
-# only for the kernels as profiled there and the default workload.
-TRAFFIC_BYTES = {"combine": 7234.8e6}
+# HBM bytes per (working) launch of the default workload's kernels:
+# rocprofv3 FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads for
+# a plain device copy of known size (profiles/pmc_traffic_stack128x128x8.md).
+# Valid only for the kernels as profiled there and the default workload.
+TRAFFIC_BYTES = {"combine": 7235.9e6, "apply": 15216.0e6, "update_dqp": 130.3e6, "update_w": 74.6e6, "spmm": 75.7e6}
 
 # one launch in this many of the dominant block-solve kernel carries events
 # in the timed region
