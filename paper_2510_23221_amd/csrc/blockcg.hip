@@ -1531,17 +1531,40 @@ __global__ __launch_bounds__(kThreads) void colsq_kernel(const ChipDev *__restri
     }
 }
 
-// norms[c] = sum over the chip's workgroups of the column partials, in order
-// (one workgroup per chip).
+// Sum of column c over the chip's np workgroup partials (row stride ld) by
+// `lanes` consecutive lanes of one wave: lane l takes partials l, l + lanes,
+// ... in order, then the lanes combine in a fixed tree (deterministic).
+__device__ __forceinline__ double column_partials(const double *__restrict__ parts, int np, int ld, int c, int l,
+                                                  int lanes)
+{
+    double t = 0.0;
+#pragma unroll 8
+    for (int p = l; p < np; p += lanes) t += parts[static_cast<size_t>(p) * ld + c];
+    for (int off = lanes / 2; off > 0; off >>= 1) t += __shfl_down(t, off, lanes);
+    return t;
+}
+
+// Lanes per column for `cols` columns over one workgroup: a power of two,
+// at most a wave.
+__device__ __forceinline__ int lanes_per_column(int cols)
+{
+    int l = 64;
+    while (l > 1 && l * cols > kThreads) l >>= 1;
+    return l;
+}
+
+// norms[c] = sum over the chip's workgroups of the column partials (one
+// workgroup per chip).
 __global__ __launch_bounds__(kThreads) void colsq_reduce_kernel(const ChipDev *__restrict__ cds, int s, int which)
 {
     const ChipDev &cd = cds[blockIdx.x];
     if (which >= 1 && !cd.ctrl[kActive]) return;
     if (which == 2 && !cd.scale) return;
-    for (int c = threadIdx.x; c < s; c += kThreads) {
-        double t = 0.0;
-        for (int p = 0; p < cd.wgs; ++p) t += cd.parts[static_cast<size_t>(p) * s + c];
-        cd.norms[c] = t;
+    const int lanes = lanes_per_column(s);
+    for (int c0 = 0; c0 < s; c0 += kThreads / lanes) {
+        const int c = c0 + static_cast<int>(threadIdx.x) / lanes;
+        const double t = column_partials(cd.parts, cd.wgs, s, c < s ? c : 0, threadIdx.x % lanes, lanes);
+        if (c < s && threadIdx.x % lanes == 0) cd.norms[c] = t;
     }
 }
 
@@ -1632,17 +1655,18 @@ __global__ __launch_bounds__(kThreads) void x0_dots_kernel(const ChipDev *__rest
     }
 }
 
-// dots[chip * 2 kMaxS + c] = sum over the chip's workgroups, in order (one
+// dots[chip * 2 kMaxS + c] = sum over the chip's workgroups, in a fixed order (one
 // workgroup per chip).
 __global__ __launch_bounds__(kThreads) void x0_dots_reduce_kernel(const ChipDev *__restrict__ cds, int s,
                                                                   double *__restrict__ dots)
 {
     const ChipDev &cd = cds[blockIdx.x];
     if (!cd.X0) return;
-    for (int c = threadIdx.x; c < 2 * s; c += kThreads) {
-        double t = 0.0;
-        for (int p = 0; p < cd.wgs; ++p) t += cd.parts[static_cast<size_t>(p) * 2 * s + c];
-        dots[static_cast<size_t>(blockIdx.x) * 2 * kMaxS + c] = t;
+    const int lanes = lanes_per_column(2 * s);
+    for (int c0 = 0; c0 < 2 * s; c0 += kThreads / lanes) {
+        const int c = c0 + static_cast<int>(threadIdx.x) / lanes;
+        const double t = column_partials(cd.parts, cd.wgs, 2 * s, c < 2 * s ? c : 0, threadIdx.x % lanes, lanes);
+        if (c < 2 * s && threadIdx.x % lanes == 0) dots[static_cast<size_t>(blockIdx.x) * 2 * kMaxS + c] = t;
     }
 }
 
