@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--cg-columns", type=int, default=512, help="columns of the per-sample CG baseline (0: skip)")
     ap.add_argument("--precond", choices=["none", "jacobi"], default="jacobi",
                     help="preconditioner of the block solve and of the per-sample CG baseline alike")
+    ap.add_argument("--separate-output", action="store_true",
+                    help="combine and operator action as two passes even when T is FP64 (default: one pass, "
+                         "F = (A X) C)")
     ap.add_argument("--only", choices=["apply", "combine", "copy"], default=None,
                     help="run one kernel family at the workload's shape (for counter profiles)")
     return ap.parse_args()
@@ -142,11 +145,18 @@ def main():
         return
 
     infos = []
+    # one pass over the fields for both outputs when T and F are FP64 (pairs
+    # stay consistent to FP64 rounding); the BF16 scheme keeps two passes
+    fused = t_dtype == torch.float64 and not args.separate_output
+    cwork = torch.empty(capi_bytes_combine_apply(capi, G, s) + 256, dtype=torch.uint8, device=dev) if fused else None
 
     def step():
         _, info = capi.block_krylov_solve(G, B, w.tol, compute=compute, X=X, work=wview)
-        capi.combine(X, C, out_dtype=t_dtype, compute=comb_compute, T=T)
-        capi.apply_operator(G, T, out_dtype=t_dtype, compute=apply_compute, F=F)
+        if fused:
+            capi.combine_apply(G, X, C, T=T, F=F, work=cwork)
+        else:
+            capi.combine(X, C, out_dtype=t_dtype, compute=comb_compute, T=T)
+            capi.apply_operator(G, T, out_dtype=t_dtype, compute=apply_compute, F=F)
         infos.append(info)
 
     for _ in range(args.warmup):
@@ -161,7 +171,8 @@ def main():
     ldw = -(-n // 256) * 256                    # padded rows of the block-solve workspace
     per_launch_bytes = {
         "apply": n * m * 2 * wt + n * 4 * wc,
-        "combine": n * m * wt + n * s * 8 + s * m * 8,
+        # one pass: T and F written, X and A X read; else T written, X read
+        "combine": (2 * n * m * 8 + 2 * n * s * 8 + s * m * 8) if fused else (n * m * wt + n * s * 8 + s * m * 8),
         "spmm": n * s * 2 * wv + n * 4 * wcv,    # stencil + P^T AP Gram: P read, AP written
         "update_w": ldw * s * 3 * wv,           # W, AP read; W written
         "update_dqp": ldw * s * 5 * wv,         # D, P, W read; D, P written
@@ -183,7 +194,7 @@ def main():
     stride = TIMING_STRIDE if dom not in ("apply", "combine") else 1
     capi.timing_reset()
     capi.timing_stride(stride)
-    capi.timing_enable(sorted({dom, "apply"}))
+    capi.timing_enable(sorted({dom, "combine" if fused else "apply"}))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -214,7 +225,7 @@ def main():
         work = working.get(kind) or launches
         # achieved: the family's algorithmic bytes over its kernel time
         gbs = per_launch_bytes[kind] * work / (avg_ms * launches * 1e-3) / 1e9
-        traffic = TRAFFIC_BYTES.get(kind) if default_workload else None
+        traffic = TRAFFIC_BYTES.get(kind) if default_workload and not (fused and kind == "combine") else None
         return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kind,
                 "launches": launches, "working_launches": work, "timed_launches": timed,
@@ -236,9 +247,10 @@ def main():
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "grid": list(chip.dims), "s": s, "M": m, "tol": w.tol,
-                   "scheme": w.scheme, "T_F_dtype": str(t_dtype).replace("torch.", ""), "precond": args.precond},
+                   "scheme": w.scheme, "T_F_dtype": str(t_dtype).replace("torch.", ""), "precond": args.precond,
+                   "outputs": "one pass (T = X C, F = (A X) C)" if fused else "two passes (T = X C, F = A T)"},
         "roofline": roofline,
-        "stencil": roof("apply"),
+        "output": roof("combine") if fused else roof("apply"),
         "census_ms_per_step": {k: round(v[1], 4) for k, v in census.items()},
         "census_launches_per_step": {k: v[0] for k, v in census.items()},
         "solve": {"iters_per_step": it_total / args.steps, "refinements_per_step": ref_total / args.steps,
@@ -353,6 +365,13 @@ def bench_learned(args):
            "rejected_columns": int(sum(r["rejected"] for r in recs)),
            "max_rel_res": {"zero": max(r["zero_res"] for r in recs), "learned": max(r["learned_res"] for r in recs)}}
     print(json.dumps(res), flush=True)
+
+
+def capi_bytes_combine_apply(capi, G, s):
+    import ctypes
+    out = ctypes.c_size_t()
+    capi._check(capi.load_library().bko_combine_apply_workspace_bytes(G.handle, s, ctypes.byref(out)))
+    return out.value
 
 
 def per_sample_cg(G, B, C, w, cols, value):

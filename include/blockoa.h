@@ -280,6 +280,24 @@ bko_status bko_combine(int n, int s, int m, const void *X, int ldx, bko_dtype x_
                        const void *C, int ldc, bko_dtype c_t, void *T, int ldt, bko_dtype t_t,
                        bko_dtype compute, void *stream);
 
+/* Workspace bytes of bko_combine_apply (an n x s FP64 block). */
+bko_status bko_combine_apply_workspace_bytes(bko_op A, int s, size_t *bytes);
+
+/*
+ * The temperature fields and their operator action in one pass over the
+ * fields, FP64: T = X C (Sec. III-B, Eq. (5)) and F = A T (Sec. III-C,
+ * Eq. (6)) computed as F = (A X) C, which equals A (X C) exactly in exact
+ * arithmetic and to rounding in FP64 (every pair then satisfies
+ * ||A t - f|| <= a few ulp of |A||X||C|).  The s columns of A X are formed
+ * first (one stencil product over s columns, in the workspace), then one
+ * kernel writes both outputs, so T is never read back.  X n x s (ldx >= n),
+ * C s x m (ldc >= s), T and F n x m (ldt, ldf >= n), all FP64 device; T, F
+ * must not overlap X or each other.  work: caller workspace of
+ * bko_combine_apply_workspace_bytes, 256-byte aligned.  Asynchronous.
+ */
+bko_status bko_combine_apply(bko_op A, int s, int m, const double *X, int ldx, const double *C, int ldc, double *T,
+                             int ldt, double *F, int ldf, void *work, size_t work_bytes, void *stream);
+
 /* ----------------------------------------------- operator action (F = A T) */
 
 /*

@@ -40,7 +40,8 @@ EXPORTED = ("bko_version", "bko_last_error", "bko_operator_bytes", "bko_assemble
             "bko_nn_conv2d_wgrad", "bko_unet_create", "bko_unet_destroy", "bko_unet_sizes", "bko_unet_set_params",
             "bko_unet_forward", "bko_unet_gradient", "bko_unet_adam_step", "bko_lstart_pack",
             "bko_lstart_pack_target", "bko_lstart_unpack", "bko_jacobi_smooth", "bko_operator_set_precond",
-            "bko_operator_get_precond", "bko_timing_set_stride")
+            "bko_operator_get_precond", "bko_timing_set_stride", "bko_combine_apply_workspace_bytes",
+            "bko_combine_apply")
 
 
 class BlockoaError(RuntimeError):
@@ -583,6 +584,34 @@ def combine(X: torch.Tensor, C: torch.Tensor, out_dtype=torch.float64, compute: 
     tp, ldt, tt = _block(T, "T")
     _check(load_library().bko_combine(n, s, m, xp, ldx, xt, cp, ldc, ct, tp, ldt, tt, compute, _stream(stream)))
     return T
+
+
+def combine_apply(A: HeatOperator, X: torch.Tensor, C: torch.Tensor, T: Optional[torch.Tensor] = None,
+                  F: Optional[torch.Tensor] = None, work: Optional[torch.Tensor] = None, stream=None):
+    """T = X C and F = A T = (A X) C in FP64 in one pass over the fields
+    (X (s, N), C (M, s)); returns (T, F), each (M, N)."""
+    s, n = X.shape
+    m = C.shape[0]
+    if C.shape[1] != s or C.dtype != torch.float64 or X.dtype != torch.float64:
+        raise ValueError("X (s, N) and C (M, s) must be FP64")
+    if T is None:
+        T = torch.empty((m, n), dtype=torch.float64, device=X.device)
+    if F is None:
+        F = torch.empty((m, n), dtype=torch.float64, device=X.device)
+    lib = load_library()
+    need = ctypes.c_size_t()
+    _check(lib.bko_combine_apply_workspace_bytes(A.handle, s, ctypes.byref(need)))
+    if work is None or work.numel() < need.value + 256:
+        work = torch.empty(need.value + 256, dtype=torch.uint8, device=X.device)
+    wp = work.data_ptr() + ((-work.data_ptr()) % 256)
+    xp, ldx, _ = _block(X, "X")
+    if C.stride(1) != 1:
+        raise ValueError("C must have contiguous rows")
+    tp, ldt, _ = _block(T, "T")
+    fp, ldf, _ = _block(F, "F")
+    _check(lib.bko_combine_apply(A.handle, s, m, xp, ldx, _ptr(C), C.stride(0) if m > 1 else s, tp, ldt, fp, ldf,
+                                 ctypes.c_void_p(wp), need.value, _stream(stream)))
+    return T, F
 
 
 def apply_operator(A: HeatOperator, T: torch.Tensor, out_dtype=torch.float64, compute: int = F64,

@@ -489,6 +489,43 @@ bko_status bko_combine(int n, int s, int m, const void *X, int ldx, bko_dtype x_
     BKO_GUARD_END
 }
 
+static int64_t combine_apply_ld(int64_t n) { return static_cast<int64_t>(align_up(static_cast<size_t>(n), 32)); }
+
+bko_status bko_combine_apply_workspace_bytes(bko_op A, int s, size_t *bytes)
+{
+    BKO_CHECK(A != nullptr && bytes != nullptr, "NULL argument");
+    BKO_CHECK(s >= 1 && s <= 64, "s = %d outside [1, 64]", s);
+    const Operator *op = reinterpret_cast<const Operator *>(A);
+    *bytes = sizeof(double) * static_cast<size_t>(combine_apply_ld(op->n)) * s;
+    return BKO_OK;
+}
+
+bko_status bko_combine_apply(bko_op A, int s, int m, const double *X, int ldx, const double *C, int ldc, double *T,
+                             int ldt, double *F, int ldf, void *work, size_t work_bytes, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(A != nullptr, "operator handle is NULL");
+    const Operator &op = *reinterpret_cast<const Operator *>(A);
+    const int64_t n = op.n;
+    BKO_CHECK(s >= 1 && s <= 64 && m >= 0, "bad sizes s=%d m=%d", s, m);
+    if (m == 0) return BKO_OK;
+    BKO_CHECK(X && C && T && F, "NULL array");
+    BKO_CHECK(ldx >= n && ldc >= s && ldt >= n && ldf >= n, "bad leading dimension");
+    size_t need = 0;
+    bko_status st = bko_combine_apply_workspace_bytes(A, s, &need);
+    if (st != BKO_OK) return st;
+    BKO_CHECK(work != nullptr && work_bytes >= need, "workspace has %zu bytes, need %zu", work_bytes, need);
+    BKO_CHECK(reinterpret_cast<uintptr_t>(work) % 256 == 0, "workspace must be 256-byte aligned");
+    hipStream_t sm = static_cast<hipStream_t>(stream);
+    double *Y = static_cast<double *>(work);
+    const int64_t ldy = combine_apply_ld(n);
+    // Y = A X for the s basis columns, then T = X C and F = Y C in one pass
+    if ((st = launch_stencil(op, s, X, ldx, BKO_F64, Y, ldy, BKO_F64, BKO_F64, nullptr, 0, sm)) != BKO_OK) return st;
+    TimedLaunch tl(kCombine, sm);
+    return launch_combine_dual(n, s, m, X, ldx, Y, ldy, C, ldc, T, ldt, F, ldf, sm);
+    BKO_GUARD_END
+}
+
 bko_status bko_block_krylov_workspace_bytes(bko_op A, int s, bko_dtype compute, size_t *bytes)
 {
     BKO_CHECK(A != nullptr && bytes != nullptr, "NULL argument");

@@ -190,6 +190,123 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(int64_t n, int s, int
     }
 }
 
+// FP64 combination with direct stores, and its two-product form.
+//
+// The product is formed transposed, T^T tile = C^T X^T, so that the matrix
+// core's result layout puts 16 consecutive cells of one field in the 16
+// lanes of a lane group: every store instruction writes four full 128-byte
+// lines of T and no LDS staging or barrier is needed.  Each wave owns 16
+// cells (its X rows stay in registers as the B operand); the A operand (C
+// for 16 fields) is read straight from L2/global by each lane.  The k index
+// of the contraction is laid out so that lane group g holds k = g KS .. g KS
+// + KS - 1 (any bijection of k onto the MFMA slots gives the same sum).
+// kDual: also F = Y C with Y = A X, the operator action of every field
+// formed from the s columns of A X (Sec. III-C applied to Eq. (5)'s sum).
+template <bool kDual, int kMaxKS>
+__global__ __launch_bounds__(kThreads) void combine_direct_kernel(int64_t n, int s, int64_t m,
+                                                                  const double *__restrict__ X, int64_t ldx,
+                                                                  const double *__restrict__ Y, int64_t ldy,
+                                                                  const double *__restrict__ C, int64_t ldc,
+                                                                  double *__restrict__ T, int64_t ldt,
+                                                                  double *__restrict__ F, int64_t ldf,
+                                                                  int64_t fields_per_wg, uint32_t ntiles)
+{
+    const int ks = (s + 3) / 4;  // <= kMaxKS
+    const uint32_t tile = blockIdx.x % ntiles;
+    const uint32_t split = blockIdx.x / ntiles;
+    const int64_t f_begin = static_cast<int64_t>(split) * fields_per_wg;
+    const int64_t f_end = min(m, f_begin + fields_per_wg);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t cell = static_cast<int64_t>(tile) * kTM + wave * 16 + li;
+    const bool cell_ok = cell < n;
+    double xb[kMaxKS], yb[kDual ? kMaxKS : 1];
+#pragma unroll
+    for (int t = 0; t < kMaxKS; ++t) {
+        const int k = lg * ks + t;
+        const bool ok = t < ks && k < s && cell_ok;
+        xb[t] = ok ? X[static_cast<int64_t>(k) * ldx + cell] : 0.0;
+        if constexpr (kDual) yb[t] = ok ? Y[static_cast<int64_t>(k) * ldy + cell] : 0.0;
+    }
+    // 16 fields at a time; the next block's C loads are issued before this
+    // block's products and stores
+    double a[kMaxKS], an[kMaxKS];
+    auto load_c = [&](int64_t f0, double (&dst)[kMaxKS]) {
+        const int64_t field = f0 + li;
+#pragma unroll
+        for (int t = 0; t < kMaxKS; ++t) {
+            const int k = lg * ks + t;
+            dst[t] = (t < ks && k < s && field < f_end) ? C[field * ldc + k] : 0.0;
+        }
+    };
+    if (f_begin < f_end) load_c(f_begin, a);
+    for (int64_t f0 = f_begin; f0 < f_end; f0 += 16) {
+        if (f0 + 16 < f_end) load_c(f0 + 16, an);
+        d4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < kMaxKS; ++t) {
+            if (t < ks) {
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], xb[t], acc, 0, 0, 0);
+                if constexpr (kDual) acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], yb[t], acc2, 0, 0, 0);
+            }
+        }
+        if (cell_ok) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t field = f0 + mfma_row<true>(lg, r);
+                if (field < f_end) {
+                    T[field * ldt + cell] = acc[r];
+                    if constexpr (kDual) F[field * ldf + cell] = acc2[r];
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < kMaxKS; ++t) a[t] = an[t];
+    }
+}
+
+// Grid of the combination kernels: 64-cell tiles, the fields split so that
+// the grid has a few thousand workgroups.
+inline void combine_grid(int64_t n, int64_t m, uint32_t &ntiles, int64_t &fields_per_wg, uint64_t &nb)
+{
+    ntiles = static_cast<uint32_t>((n + kTM - 1) / kTM);
+    const int64_t ftiles = (m + kTN - 1) / kTN;
+    int64_t splits = std::max<int64_t>(1, std::min<int64_t>(ftiles, (8192 + ntiles - 1) / ntiles));
+    fields_per_wg = ((ftiles + splits - 1) / splits) * kTN;
+    splits = (m + fields_per_wg - 1) / fields_per_wg;
+    nb = static_cast<uint64_t>(ntiles) * splits;
+}
+
+bko_status run_direct(int64_t n, int s, int64_t m, const double *X, int64_t ldx, const double *Y, int64_t ldy,
+                      const double *C, int64_t ldc, double *T, int64_t ldt, double *F, int64_t ldf, hipStream_t stream)
+{
+    uint32_t ntiles;
+    int64_t fields_per_wg;
+    uint64_t nb;
+    combine_grid(n, m, ntiles, fields_per_wg, nb);
+    if (nb > 0x7fffffffu) {
+        set_error("combine grid too large");
+        return BKO_EINVAL;
+    }
+    const dim3 grid(static_cast<uint32_t>(nb)), block(kThreads);
+#define BKO_DIRECT(D, KS)                                                                                           \
+    hipLaunchKernelGGL((combine_direct_kernel<D, KS>), grid, block, 0, stream, n, s, m, X, ldx, Y, ldy, C, ldc, T, ldt, \
+                       F, ldf, fields_per_wg, ntiles)
+    const int ks = (s + 3) / 4;
+    if (Y) {
+        if (ks <= 4) BKO_DIRECT(true, 4);
+        else if (ks <= 8) BKO_DIRECT(true, 8);
+        else BKO_DIRECT(true, 16);
+    } else {
+        if (ks <= 4) BKO_DIRECT(false, 4);
+        else if (ks <= 8) BKO_DIRECT(false, 8);
+        else BKO_DIRECT(false, 16);
+    }
+#undef BKO_DIRECT
+    BKO_HIP(hipGetLastError());
+    return BKO_OK;
+}
+
 template <int kMode, class Tx, class Tc, class Tt>
 bko_status run(int64_t n, int s, int64_t m, const void *X, int64_t ldx, const void *C, int64_t ldc, void *T,
                int64_t ldt, hipStream_t stream)
@@ -259,11 +376,21 @@ bko_status launch_combine(int64_t n, int s, int64_t m, const void *X, int64_t ld
                           int64_t ldc, bko_dtype c_t, void *T, int64_t ldt, bko_dtype t_t, bko_dtype compute,
                           hipStream_t stream)
 {
+    if (compute == BKO_F64 && x_t == BKO_F64 && c_t == BKO_F64 && t_t == BKO_F64)
+        return run_direct(n, s, m, static_cast<const double *>(X), ldx, nullptr, 0, static_cast<const double *>(C), ldc,
+                          static_cast<double *>(T), ldt, nullptr, 0, stream);
     switch (compute) {
     case BKO_F64: return by_x<kF64>(n, s, m, X, ldx, x_t, C, ldc, c_t, T, ldt, t_t, stream);
     case BKO_F32: return by_x<kF32>(n, s, m, X, ldx, x_t, C, ldc, c_t, T, ldt, t_t, stream);
     default: return by_x<kBF16>(n, s, m, X, ldx, x_t, C, ldc, c_t, T, ldt, t_t, stream);
     }
+}
+
+bko_status launch_combine_dual(int64_t n, int s, int64_t m, const double *X, int64_t ldx, const double *Y, int64_t ldy,
+                               const double *C, int64_t ldc, double *T, int64_t ldt, double *F, int64_t ldf,
+                               hipStream_t stream)
+{
+    return run_direct(n, s, m, X, ldx, Y, ldy, C, ldc, T, ldt, F, ldf, stream);
 }
 
 }  // namespace bko

@@ -24,6 +24,10 @@ bko_status launch_jacobi(const Operator &op, int m, const double *B, int64_t ldb
 bko_status launch_combine(int64_t n, int s, int64_t m, const void *X, int64_t ldx, bko_dtype x_t,
                           const void *C, int64_t ldc, bko_dtype c_t, void *T, int64_t ldt,
                           bko_dtype t_t, bko_dtype compute, hipStream_t stream);
+// T = X C and F = Y C in FP64 with one pass over the fields (Y = A X).
+bko_status launch_combine_dual(int64_t n, int s, int64_t m, const double *X, int64_t ldx, const double *Y, int64_t ldy,
+                               const double *C, int64_t ldc, double *T, int64_t ldt, double *F, int64_t ldf,
+                               hipStream_t stream);
 
 // zero-fill bytes (a kernel, never a memset node, so it is safe in graphs)
 bko_status launch_zero(void *p, size_t bytes, hipStream_t stream);

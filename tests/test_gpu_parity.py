@@ -190,6 +190,46 @@ def test_combine_low_precision(dev, compute, tdt):
     assert (np.abs(T - T_ref) <= bound * 1.01 + 1e-30).all()
 
 
+def test_combine_f64_ragged_ld_views(dev):
+    """The FP64 direct-store kernel writes only its n x m window of a wider
+    buffer and reads X through a leading-dimension view."""
+    rng = np.random.default_rng(5)
+    s, m, n = 13, 37, 1000 + 3
+    Xb = torch.as_tensor(rng.standard_normal((s, n + 5)), device=dev)
+    X = Xb[:, 2:2 + n]
+    C = torch.as_tensor(rng.standard_normal((m, s)), device=dev)
+    Tb = torch.zeros((m, n + 11), dtype=torch.float64, device=dev)
+    T = Tb[:, 3:3 + n]
+    capi.combine(X, C, T=T)
+    T_ref = oracle.gemm(to_np(X), to_np(C))
+    bound = (s + 1) * U64 * (np.abs(to_np(C)) @ np.abs(to_np(X)))
+    assert (np.abs(to_np(T) - T_ref) <= bound * 1.01 + 1e-300).all()
+    assert (to_np(Tb[:, :3]) == 0).all() and (to_np(Tb[:, 3 + n:]) == 0).all()
+
+
+@pytest.mark.parametrize("kind,s,m", [("2d", 8, 300), ("ragged", 5, 77), ("stack", 32, 130), ("line", 17, 65)])
+def test_combine_apply_matches_oracle(ops, dev, kind, s, m):
+    """T = X C and F = (A X) C in one pass (Sec. III-B / III-C): T as the
+    plain combination, F against the oracle's A (X C) within the rounding of
+    both evaluation orders, and every pair consistent to FP64 rounding."""
+    chip, A, G = ops[kind]
+    rng = np.random.default_rng(70 + s)
+    X = rng.standard_normal((s, A.n))
+    C = rng.standard_normal((m, s))
+    T, F = capi.combine_apply(G, torch.as_tensor(X, device=dev), torch.as_tensor(C, device=dev))
+    T, F = to_np(T), to_np(F)
+    T_ref = oracle.gemm(X, C)
+    assert (np.abs(T - T_ref) <= (s + 1) * U64 * (np.abs(C) @ np.abs(X)) * 1.01 + 1e-300).all()
+    F_ref = oracle.apply_many(A, T_ref)
+    # |fl(fl(A X) C) - A X C| <= (8 + s + 1) u (|C| |A||X|); the oracle's own
+    # A (X C) is within (8 + s + 1) u of it as well
+    AXabs = oracle.apply_many(abs_csr(A), np.abs(X))
+    bound = 2 * (8 + s + 1) * U64 * (np.abs(C) @ AXabs)
+    assert (np.abs(F - F_ref) <= bound * 1.01 + 1e-300).all()
+    R = oracle.apply_many(A, T) - F
+    assert np.linalg.norm(R) <= 1e-12 * np.linalg.norm(F)
+
+
 def test_combine_ragged_ld(dev):
     rng = np.random.default_rng(4)
     s, m, n = 7, 19, 1001
