@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--cg-columns", type=int, default=512, help="columns of the per-sample CG baseline (0: skip)")
     ap.add_argument("--precond", choices=["none", "jacobi"], default="jacobi",
                     help="preconditioner of the block solve and of the per-sample CG baseline alike")
+    ap.add_argument("--noise", choices=["none", "uniform", "gaussian"], default="none",
+                    help="noise term of Eq. (5) added to every field (then the outputs take two passes)")
+    ap.add_argument("--noise-amp", type=float, default=0.01, help="noise half-width (uniform) or std (gaussian), K")
     ap.add_argument("--separate-output", action="store_true",
                     help="combine and operator action as two passes even when T is FP64 (default: one pass, "
                          "F = (A X) C)")
@@ -147,13 +150,20 @@ def main():
     infos = []
     # one pass over the fields for both outputs when T and F are FP64 (pairs
     # stay consistent to FP64 rounding); the BF16 scheme keeps two passes
-    fused = t_dtype == torch.float64 and not args.separate_output
+    noise_kind = {"none": capi.NOISE_NONE, "uniform": capi.NOISE_UNIFORM, "gaussian": capi.NOISE_GAUSSIAN}[args.noise]
+    if noise_kind != capi.NOISE_NONE and t_dtype != torch.float64:
+        raise SystemExit("bench.py: --noise needs FP64 fields")
+    fused = t_dtype == torch.float64 and not args.separate_output and noise_kind == capi.NOISE_NONE
     cwork = torch.empty(capi_bytes_combine_apply(capi, G, s) + 256, dtype=torch.uint8, device=dev) if fused else None
+    noise = capi.Noise(noise_kind, args.noise_amp, 20251021, 0)
 
     def step():
         _, info = capi.block_krylov_solve(G, B, w.tol, compute=compute, X=X, work=wview)
         if fused:
             capi.combine_apply(G, X, C, T=T, F=F, work=cwork)
+        elif noise_kind != capi.NOISE_NONE:
+            capi.combine_noisy(X, C, noise, T=T)
+            capi.apply_operator(G, T, out_dtype=t_dtype, compute=apply_compute, F=F)
         else:
             capi.combine(X, C, out_dtype=t_dtype, compute=comb_compute, T=T)
             capi.apply_operator(G, T, out_dtype=t_dtype, compute=apply_compute, F=F)
@@ -248,7 +258,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": list(chip.dims), "s": s, "M": m, "tol": w.tol,
                    "scheme": w.scheme, "T_F_dtype": str(t_dtype).replace("torch.", ""), "precond": args.precond,
-                   "outputs": "one pass (T = X C, F = (A X) C)" if fused else "two passes (T = X C, F = A T)"},
+                   "outputs": "one pass (T = X C, F = (A X) C)" if fused else "two passes (T = X C, F = A T)",
+                   "noise": args.noise if noise_kind == capi.NOISE_NONE else f"{args.noise} {args.noise_amp}"},
         "roofline": roofline,
         "output": roof("combine") if fused else roof("apply"),
         "census_ms_per_step": {k: round(v[1], 4) for k, v in census.items()},

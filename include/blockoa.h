@@ -280,6 +280,49 @@ bko_status bko_combine(int n, int s, int m, const void *X, int ldx, bko_dtype x_
                        const void *C, int ldc, bko_dtype c_t, void *T, int ldt, bko_dtype t_t,
                        bko_dtype compute, void *stream);
 
+/*
+ * Noise of Eq. (5) (Sec. III-B; the paper's default draws it uniformly from
+ * (-0.01, 0.01) at each grid point, Sec. V-B): a counter-based generator,
+ * Philox4x32-10 (Salmon et al., SC 2011), keyed by seed and counting
+ * (cell, global field index), so the value at (field f, cell a) does not
+ * depend on how the fields are split over calls.  With 52 bits u of the
+ * first two output words: uniform = amplitude ((2u + 1) 2^-52 - 1) on
+ * (-amplitude, amplitude); Gaussian = amplitude sqrt(-2 ln x1) cos(2 pi x2)
+ * (Box-Muller, x = (u + 1/2) 2^-52 from words 0-1 and 2-3).  The noise is
+ * added to every cell: the boundary models live in A, so the fields keep
+ * their boundary conditions.
+ */
+typedef enum { BKO_NOISE_NONE = 0, BKO_NOISE_UNIFORM = 1, BKO_NOISE_GAUSSIAN = 2 } bko_noise_kind;
+typedef struct {
+    int kind;              /* bko_noise_kind                                   */
+    double amplitude;      /* half-width (uniform) or standard deviation        */
+    unsigned long long seed;         /* generator key                          */
+    unsigned long long field_offset; /* global index of the call's field 0     */
+} bko_noise;
+
+/*
+ * T = X C + E (FP64): the combination of Eq. (5) with its noise term.  X
+ * n x s (ldx >= n), C s x m (ldc >= s), T n x m (ldt >= n); noise may be
+ * NULL (no noise).  The operator action of these fields is then
+ * bko_apply_operator on T (F = A T covers A E).  Asynchronous.
+ */
+bko_status bko_combine_noisy(int n, int s, int m, const double *X, int ldx, const double *C, int ldc, double *T,
+                             int ldt, const bko_noise *noise, void *stream);
+
+/* E (n x m, lde >= n, FP64 device) = the noise alone, as added by
+ * bko_combine_noisy.  Asynchronous. */
+bko_status bko_noise_fill(int n, int m, double *E, int lde, const bko_noise *noise, void *stream);
+
+/*
+ * The normalised weights of Eq. (5), alpha_i = mu_i / sum_j mu_j, in place
+ * on C (s x m, ldc >= s, FP64 device; column j holds field j's mu), the sum
+ * taken in index order.  The sum of s standard normals can be close to
+ * zero: a field with |sum| < min_abs_sum keeps its mu and gets flags[j] = 1
+ * (flags: m ints, device, written for every field; the caller draws new mu
+ * for the flagged fields and calls again).  Asynchronous.
+ */
+bko_status bko_normalize_weights(int s, int m, double *C, int ldc, double min_abs_sum, int *flags, void *stream);
+
 /* Workspace bytes of bko_combine_apply (an n x s FP64 block). */
 bko_status bko_combine_apply_workspace_bytes(bko_op A, int s, size_t *bytes);
 

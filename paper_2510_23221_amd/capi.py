@@ -23,6 +23,14 @@ LIB_PATH = os.path.join(_HERE, "libblockoa.so")
 OK, EINVAL, ENOTSPD, ENOCONV, EBREAKDOWN, EHIP, ENOMEM, ENOTIMPL = range(8)
 F64, F32, BF16 = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
+NOISE_NONE, NOISE_UNIFORM, NOISE_GAUSSIAN = 0, 1, 2
+
+
+class Noise(ctypes.Structure):
+    """The noise term of Eq. (5): kind, amplitude (half-width or standard
+    deviation), generator seed and the global index of the call's field 0."""
+    _fields_ = [("kind", ctypes.c_int), ("amplitude", ctypes.c_double), ("seed", ctypes.c_ulonglong),
+                ("field_offset", ctypes.c_ulonglong)]
 BC_DIRICHLET0, BC_ADIABATIC, BC_ROBIN = 0, 1, 2
 STATUS_NAMES = {0: "BKO_OK", 1: "BKO_EINVAL", 2: "BKO_ENOTSPD", 3: "BKO_ENOCONV",
                 4: "BKO_EBREAKDOWN", 5: "BKO_EHIP", 6: "BKO_ENOMEM", 7: "BKO_ENOTIMPL"}
@@ -41,7 +49,7 @@ EXPORTED = ("bko_version", "bko_last_error", "bko_operator_bytes", "bko_assemble
             "bko_unet_forward", "bko_unet_gradient", "bko_unet_adam_step", "bko_lstart_pack",
             "bko_lstart_pack_target", "bko_lstart_unpack", "bko_jacobi_smooth", "bko_operator_set_precond",
             "bko_operator_get_precond", "bko_timing_set_stride", "bko_combine_apply_workspace_bytes",
-            "bko_combine_apply")
+            "bko_combine_apply", "bko_combine_noisy", "bko_noise_fill", "bko_normalize_weights")
 
 
 class BlockoaError(RuntimeError):
@@ -113,6 +121,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                   ctypes.POINTER(SolveInfo), vp]),
         "bko_cg_solve": (i32, [vp, i32, vp, i32, vp, i32, dbl, i32, vp, sz, ctypes.POINTER(i32),
                                ctypes.POINTER(SolveInfo), vp]),
+        "bko_operator_set_precond": (i32, [vp, i32]),
+        "bko_operator_get_precond": (i32, [vp, ctypes.POINTER(i32)]),
+        "bko_timing_set_stride": (i32, [i32]),
+        "bko_combine_apply_workspace_bytes": (i32, [vp, i32, ctypes.POINTER(sz)]),
+        "bko_combine_apply": (i32, [vp, i32, i32, vp, i32, vp, i32, vp, i32, vp, i32, vp, sz, vp]),
+        "bko_combine_noisy": (i32, [i32, i32, i32, vp, i32, vp, i32, vp, i32, ctypes.POINTER(Noise), vp]),
+        "bko_noise_fill": (i32, [i32, i32, vp, i32, ctypes.POINTER(Noise), vp]),
+        "bko_normalize_weights": (i32, [i32, i32, vp, i32, dbl, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -584,6 +600,45 @@ def combine(X: torch.Tensor, C: torch.Tensor, out_dtype=torch.float64, compute: 
     tp, ldt, tt = _block(T, "T")
     _check(load_library().bko_combine(n, s, m, xp, ldx, xt, cp, ldc, ct, tp, ldt, tt, compute, _stream(stream)))
     return T
+
+
+def combine_noisy(X: torch.Tensor, C: torch.Tensor, noise: Optional[Noise] = None, T: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+    """T = X C + E in FP64 (X (s, N), C (M, s)); E the counter-based noise."""
+    s, n = X.shape
+    m = C.shape[0]
+    if C.shape[1] != s or C.dtype != torch.float64 or X.dtype != torch.float64:
+        raise ValueError("X (s, N) and C (M, s) must be FP64")
+    if T is None:
+        T = torch.empty((m, n), dtype=torch.float64, device=X.device)
+    xp, ldx, _ = _block(X, "X")
+    if C.stride(1) != 1:
+        raise ValueError("C must have contiguous rows")
+    tp, ldt, _ = _block(T, "T")
+    nz = ctypes.byref(noise) if noise is not None else None
+    _check(load_library().bko_combine_noisy(n, s, m, xp, ldx, _ptr(C), C.stride(0) if m > 1 else s, tp, ldt, nz,
+                                            _stream(stream)))
+    return T
+
+
+def noise_fill(n: int, m: int, noise: Noise, device="cuda", stream=None) -> torch.Tensor:
+    """The noise alone: E (M, N) FP64."""
+    E = torch.empty((m, n), dtype=torch.float64, device=device)
+    ep, lde, _ = _block(E, "E")
+    _check(load_library().bko_noise_fill(n, m, ep, lde, ctypes.byref(noise), _stream(stream)))
+    return E
+
+
+def normalize_weights(C: torch.Tensor, min_abs_sum: float, stream=None) -> torch.Tensor:
+    """alpha = mu / sum(mu) per field, in place on C (M, s) FP64; returns the
+    per-field flags (1: |sum| < min_abs_sum, left unnormalised)."""
+    m, s = C.shape
+    if C.dtype != torch.float64 or C.stride(1) != 1:
+        raise ValueError("C must be FP64 with contiguous rows")
+    flags = torch.empty(m, dtype=torch.int32, device=C.device)
+    _check(load_library().bko_normalize_weights(s, m, _ptr(C), C.stride(0) if m > 1 else s, float(min_abs_sum),
+                                                _ptr(flags), _stream(stream)))
+    return flags
 
 
 def combine_apply(A: HeatOperator, X: torch.Tensor, C: torch.Tensor, T: Optional[torch.Tensor] = None,

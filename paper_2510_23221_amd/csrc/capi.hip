@@ -489,6 +489,51 @@ bko_status bko_combine(int n, int s, int m, const void *X, int ldx, bko_dtype x_
     BKO_GUARD_END
 }
 
+static bool noise_ok(const bko_noise *nz)
+{
+    return nz == nullptr || ((nz->kind == BKO_NOISE_NONE || nz->kind == BKO_NOISE_UNIFORM ||
+                              nz->kind == BKO_NOISE_GAUSSIAN) && std::isfinite(nz->amplitude) && nz->amplitude >= 0.0);
+}
+
+bko_status bko_combine_noisy(int n, int s, int m, const double *X, int ldx, const double *C, int ldc, double *T,
+                             int ldt, const bko_noise *noise, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(n >= 0 && s >= 1 && s <= 64 && m >= 0, "bad sizes n=%d s=%d m=%d", n, s, m);
+    BKO_CHECK(noise_ok(noise), "bad noise description");
+    if (n == 0 || m == 0) return BKO_OK;
+    BKO_CHECK(X && C && T, "NULL array");
+    BKO_CHECK(ldx >= n && ldc >= s && ldt >= n, "bad leading dimension");
+    const int kind = noise ? noise->kind : BKO_NOISE_NONE;
+    TimedLaunch tl(kCombine, static_cast<hipStream_t>(stream));
+    return launch_combine_noisy(n, s, m, X, ldx, C, ldc, T, ldt, kind, noise ? noise->amplitude : 0.0,
+                                noise ? noise->seed : 0, noise ? noise->field_offset : 0, static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+bko_status bko_noise_fill(int n, int m, double *E, int lde, const bko_noise *noise, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(n >= 0 && m >= 0 && m <= 65535, "bad sizes n=%d m=%d (m <= 65535 per call)", n, m);
+    BKO_CHECK(noise != nullptr && noise_ok(noise), "bad noise description");
+    if (n == 0 || m == 0) return BKO_OK;
+    BKO_CHECK(E != nullptr && lde >= n, "bad output");
+    return launch_noise_fill(n, m, E, lde, noise->kind, noise->amplitude, noise->seed, noise->field_offset,
+                             static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+bko_status bko_normalize_weights(int s, int m, double *C, int ldc, double min_abs_sum, int *flags, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(s >= 1 && m >= 0 && ldc >= s, "bad sizes s=%d m=%d ldc=%d", s, m, ldc);
+    BKO_CHECK(std::isfinite(min_abs_sum) && min_abs_sum >= 0.0, "min_abs_sum must be finite and >= 0");
+    if (m == 0) return BKO_OK;
+    BKO_CHECK(C != nullptr && flags != nullptr, "NULL argument");
+    return launch_normalize_weights(s, m, C, ldc, min_abs_sum, flags, static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
 static int64_t combine_apply_ld(int64_t n) { return static_cast<int64_t>(align_up(static_cast<size_t>(n), 32)); }
 
 bko_status bko_combine_apply_workspace_bytes(bko_op A, int s, size_t *bytes)

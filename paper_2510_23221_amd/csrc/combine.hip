@@ -190,6 +190,92 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(int64_t n, int s, int
     }
 }
 
+// ---------------------------------------------------------------- noise
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC 2011): a counter-based generator, ten rounds of two
+// 32 x 32 -> 64-bit products with the published multipliers and Weyl key
+// increments.  The noise of field f (global index) at cell a is a pure
+// function of (seed, f, a), so any split of the fields over calls or
+// workgroups draws the same values.
+struct Philox4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                 uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
+        const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Philox4{{c0, c1, c2, c3}};
+}
+
+// An open-interval uniform in (0, 1) from 52 random bits: (u + 1/2) 2^-52.
+__device__ __forceinline__ double unit_open(uint32_t hi, uint32_t lo)
+{
+    const uint64_t u = (static_cast<uint64_t>(hi) << 20) | (lo >> 12);
+    return (static_cast<double>(u) + 0.5) * 0x1.0p-52;
+}
+
+// Noise value of (field, cell): uniform on (-a, a) as a ((2u + 1) 2^-52 - 1)
+// (exact before the product with a), or Gaussian N(0, a^2) by Box-Muller.
+__device__ __forceinline__ double noise_value(int kind, double amp, uint64_t seed, uint64_t field, int64_t cell)
+{
+    const Philox4 r = philox4x32_10(static_cast<uint32_t>(cell), static_cast<uint32_t>(static_cast<uint64_t>(cell) >> 32),
+                                    static_cast<uint32_t>(field), static_cast<uint32_t>(field >> 32),
+                                    static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+    if (kind == BKO_NOISE_UNIFORM) {
+        const uint64_t u = (static_cast<uint64_t>(r.v[0]) << 20) | (r.v[1] >> 12);
+        return amp * (static_cast<double>(2 * u + 1) * 0x1.0p-52 - 1.0);
+    }
+    const double x1 = unit_open(r.v[0], r.v[1]), x2 = unit_open(r.v[2], r.v[3]);
+    return amp * (sqrt(-2.0 * log(x1)) * cos(6.283185307179586476925 * x2));
+}
+
+struct NoiseArgs {
+    int kind;  // BKO_NOISE_*
+    double amp;
+    uint64_t seed, field_offset;
+};
+
+// E[f * lde + a] = noise of (field_offset + f, a)
+__global__ __launch_bounds__(kThreads) void noise_fill_kernel(int64_t n, int64_t m, double *__restrict__ E, int64_t lde,
+                                                              NoiseArgs na)
+{
+    const int64_t f = blockIdx.y;
+    for (int64_t a = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; a < n;
+         a += static_cast<int64_t>(gridDim.x) * kThreads)
+        E[f * lde + a] = noise_value(na.kind, na.amp, na.seed, na.field_offset + f, a);
+}
+
+// alpha_j = mu_j / sum_k mu_kj per field j (C column j, ldc), summed in k
+// order; a field whose |sum| < min_abs keeps its weights and gets flag 1.
+__global__ __launch_bounds__(kThreads) void normalize_weights_kernel(int s, int64_t m, double *__restrict__ C, int64_t ldc,
+                                                                     double min_abs, int *__restrict__ flags)
+{
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (j >= m) return;
+    double *c = C + j * ldc;
+    double sum = 0.0;
+    for (int k = 0; k < s; ++k) sum += c[k];
+    const bool bad = !(fabs(sum) >= min_abs);
+    flags[j] = bad ? 1 : 0;
+    if (bad) return;
+    for (int k = 0; k < s; ++k) c[k] = c[k] / sum;
+}
+
 // FP64 combination with direct stores, and its two-product form.
 //
 // The product is formed transposed, T^T tile = C^T X^T, so that the matrix
@@ -209,7 +295,7 @@ __global__ __launch_bounds__(kThreads) void combine_direct_kernel(int64_t n, int
                                                                   const double *__restrict__ C, int64_t ldc,
                                                                   double *__restrict__ T, int64_t ldt,
                                                                   double *__restrict__ F, int64_t ldf,
-                                                                  int64_t fields_per_wg, uint32_t ntiles)
+                                                                  int64_t fields_per_wg, uint32_t ntiles, NoiseArgs na)
 {
     const int ks = (s + 3) / 4;  // <= kMaxKS
     const uint32_t tile = blockIdx.x % ntiles;
@@ -255,7 +341,9 @@ __global__ __launch_bounds__(kThreads) void combine_direct_kernel(int64_t n, int
             for (int r = 0; r < 4; ++r) {
                 const int64_t field = f0 + mfma_row<true>(lg, r);
                 if (field < f_end) {
-                    T[field * ldt + cell] = acc[r];
+                    double t = acc[r];
+                    if (na.kind != BKO_NOISE_NONE) t += noise_value(na.kind, na.amp, na.seed, na.field_offset + field, cell);
+                    T[field * ldt + cell] = t;
                     if constexpr (kDual) F[field * ldf + cell] = acc2[r];
                 }
             }
@@ -278,7 +366,8 @@ inline void combine_grid(int64_t n, int64_t m, uint32_t &ntiles, int64_t &fields
 }
 
 bko_status run_direct(int64_t n, int s, int64_t m, const double *X, int64_t ldx, const double *Y, int64_t ldy,
-                      const double *C, int64_t ldc, double *T, int64_t ldt, double *F, int64_t ldf, hipStream_t stream)
+                      const double *C, int64_t ldc, double *T, int64_t ldt, double *F, int64_t ldf, hipStream_t stream,
+                      NoiseArgs na = NoiseArgs{BKO_NOISE_NONE, 0.0, 0, 0})
 {
     uint32_t ntiles;
     int64_t fields_per_wg;
@@ -291,7 +380,7 @@ bko_status run_direct(int64_t n, int s, int64_t m, const double *X, int64_t ldx,
     const dim3 grid(static_cast<uint32_t>(nb)), block(kThreads);
 #define BKO_DIRECT(D, KS)                                                                                           \
     hipLaunchKernelGGL((combine_direct_kernel<D, KS>), grid, block, 0, stream, n, s, m, X, ldx, Y, ldy, C, ldc, T, ldt, \
-                       F, ldf, fields_per_wg, ntiles)
+                       F, ldf, fields_per_wg, ntiles, na)
     const int ks = (s + 3) / 4;
     if (Y) {
         if (ks <= 4) BKO_DIRECT(true, 4);
@@ -391,6 +480,35 @@ bko_status launch_combine_dual(int64_t n, int s, int64_t m, const double *X, int
                                hipStream_t stream)
 {
     return run_direct(n, s, m, X, ldx, Y, ldy, C, ldc, T, ldt, F, ldf, stream);
+}
+
+bko_status launch_combine_noisy(int64_t n, int s, int64_t m, const double *X, int64_t ldx, const double *C, int64_t ldc,
+                                double *T, int64_t ldt, int kind, double amp, uint64_t seed, uint64_t field_offset,
+                                hipStream_t stream)
+{
+    return run_direct(n, s, m, X, ldx, nullptr, 0, C, ldc, T, ldt, nullptr, 0, stream,
+                      NoiseArgs{kind, amp, seed, field_offset});
+}
+
+bko_status launch_noise_fill(int64_t n, int64_t m, double *E, int64_t lde, int kind, double amp, uint64_t seed,
+                             uint64_t field_offset, hipStream_t stream)
+{
+    if (n == 0 || m == 0) return BKO_OK;
+    const unsigned bx = static_cast<unsigned>(std::min<int64_t>((n + kThreads - 1) / kThreads, 1024));
+    hipLaunchKernelGGL(noise_fill_kernel, dim3(bx, static_cast<unsigned>(m)), dim3(kThreads), 0, stream, n, m, E, lde,
+                       NoiseArgs{kind, amp, seed, field_offset});
+    BKO_HIP(hipGetLastError());
+    return BKO_OK;
+}
+
+bko_status launch_normalize_weights(int s, int64_t m, double *C, int64_t ldc, double min_abs, int *flags,
+                                    hipStream_t stream)
+{
+    if (m == 0) return BKO_OK;
+    hipLaunchKernelGGL(normalize_weights_kernel, dim3(static_cast<unsigned>((m + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, stream, s, m, C, ldc, min_abs, flags);
+    BKO_HIP(hipGetLastError());
+    return BKO_OK;
 }
 
 }  // namespace bko

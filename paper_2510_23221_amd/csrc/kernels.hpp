@@ -24,6 +24,16 @@ bko_status launch_jacobi(const Operator &op, int m, const double *B, int64_t ldb
 bko_status launch_combine(int64_t n, int s, int64_t m, const void *X, int64_t ldx, bko_dtype x_t,
                           const void *C, int64_t ldc, bko_dtype c_t, void *T, int64_t ldt,
                           bko_dtype t_t, bko_dtype compute, hipStream_t stream);
+// T = X C + E in FP64, E the counter-based noise of (seed, field_offset + f, cell).
+bko_status launch_combine_noisy(int64_t n, int s, int64_t m, const double *X, int64_t ldx, const double *C, int64_t ldc,
+                                double *T, int64_t ldt, int kind, double amp, uint64_t seed, uint64_t field_offset,
+                                hipStream_t stream);
+bko_status launch_noise_fill(int64_t n, int64_t m, double *E, int64_t lde, int kind, double amp, uint64_t seed,
+                             uint64_t field_offset, hipStream_t stream);
+// alpha = mu / sum(mu) per field in place; fields with |sum| < min_abs are
+// left as they are, flags[j] = 1 for them and 0 for the others (device).
+bko_status launch_normalize_weights(int s, int64_t m, double *C, int64_t ldc, double min_abs, int *flags,
+                                    hipStream_t stream);
 // T = X C and F = Y C in FP64 with one pass over the fields (Y = A X).
 bko_status launch_combine_dual(int64_t n, int s, int64_t m, const double *X, int64_t ldx, const double *Y, int64_t ldy,
                                const double *C, int64_t ldc, double *T, int64_t ldt, double *F, int64_t ldf,
