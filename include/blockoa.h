@@ -148,6 +148,24 @@ bko_status bko_operator_dims(bko_op A, int *nx, int *ny, int *nz);
 bko_status bko_operator_set_precond(bko_op A, int kind);
 bko_status bko_operator_get_precond(bko_op A, int *kind);
 
+/*
+ * Nonhomogeneous boundary data (Sec. II-A: Dirichlet u = u0, Robin ambient
+ * u_inf, Mixed) by lifting: with face temperatures u_face[f] (the Dirichlet
+ * value of a Dirichlet face, the ambient of a Robin face; ignored for
+ * adiabatic faces) the temperature x solves A x = q + g, where A is the
+ * operator assembled above and g_a = sum over the boundary faces of cell a
+ * of w_face u_face (the same face weights as A).  Writes g (n FP64, device).
+ * k_cell_dev: the conductivity the operator was assembled from.  Faces in
+ * the order -x, +x, -y, +y, -z, +z.  Asynchronous.
+ * Basis solutions of A X = Q + g 1^T combined with weights that sum to one
+ * (bko_normalize_weights) keep the boundary data exactly; the power of a
+ * field t is then A t - g (bko_add_column with alpha = -1).
+ */
+bko_status bko_boundary_source(bko_op A, const double *k_cell_dev, const double u_face[6], double *g, void *stream);
+
+/* F[:, j] += alpha g for j < m (F n x m, ldf >= n; g n; FP64 device).  Asynchronous. */
+bko_status bko_add_column(int n, int m, double *F, int ldf, const double *g, double alpha, void *stream);
+
 /* Free the handle (host memory only; the coefficient buffer stays the caller's). */
 bko_status bko_destroy_operator(bko_op A);
 

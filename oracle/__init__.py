@@ -13,6 +13,8 @@ Everything here is plain FP64:
 * :func:`cg_many` -- unpreconditioned CG from x0 = 0, one right-hand side at a
   time (the direct solution method of Sec. II-D; CG baseline of Sec. V-A).
   The method's block solve reaches X = A^-1 B, which is what this computes.
+* :func:`boundary_source` -- the right-hand-side source g of nonhomogeneous
+  boundary data (A x = q + g), face by face from the discretisation.
 * :func:`jacobi_scaling`, :func:`pcg` -- the diagonal (Jacobi) preconditioner:
   S = diag(A)^(-1/2) and the symmetrically scaled S A S, and preconditioned
   CG with M = diag(A) (the paper leaves the preconditioner unstated; these
@@ -194,6 +196,33 @@ def pcg(A: CSR, b: np.ndarray, tol: float, maxit: int = 100000, minv: np.ndarray
         it += 1
     res = np.linalg.norm(b - spmv(A, x)) / bn if bn > 0 else 0.0
     return x, it, res
+
+
+def boundary_source(nx, ny, nz, lx, ly, lz, k, bc, h, u_face) -> np.ndarray:
+    """g (N,): the right-hand-side source of nonhomogeneous boundary data
+    (Sec. II-A; Dirichlet value or Robin ambient u_face per face, -x, +x, -y,
+    +y, -z, +z).  A boundary face of cell a with weight w (the Dirichlet or
+    Robin weight of the assembly) contributes the flux w (x_a - u_face), so
+    A x = q + g with g_a = sum of w u_face over the cell's boundary faces."""
+    k = np.asarray(k, dtype=np.float64).reshape(nz, ny, nx)
+    d = (lx / nx, ly / ny, lz / nz)
+    g = np.zeros((nz, ny, nx))
+
+    def weight(kind, ka, dd, hh):
+        if kind == 0:  # Dirichlet
+            return 2.0 * ka / (dd * dd)
+        if kind == 2:  # Robin
+            return 1.0 / (dd * (dd / (2.0 * ka) + 1.0 / hh))
+        return np.zeros_like(ka)
+
+    # face f = 2 axis + side; axis 0 = x (last index), 1 = y, 2 = z (first)
+    for f in range(6):
+        ax, side = divmod(f, 2)
+        sl = [slice(None)] * 3
+        sl[2 - ax] = -1 if side else 0
+        sl = tuple(sl)
+        g[sl] += weight(bc[f], k[sl], d[ax], h[f]) * u_face[f]
+    return g.reshape(-1)
 
 
 def gemm(X: np.ndarray, C: np.ndarray, nthreads: int = 0) -> np.ndarray:

@@ -49,7 +49,8 @@ EXPORTED = ("bko_version", "bko_last_error", "bko_operator_bytes", "bko_assemble
             "bko_unet_forward", "bko_unet_gradient", "bko_unet_adam_step", "bko_lstart_pack",
             "bko_lstart_pack_target", "bko_lstart_unpack", "bko_jacobi_smooth", "bko_operator_set_precond",
             "bko_operator_get_precond", "bko_timing_set_stride", "bko_combine_apply_workspace_bytes",
-            "bko_combine_apply", "bko_combine_noisy", "bko_noise_fill", "bko_normalize_weights")
+            "bko_combine_apply", "bko_combine_noisy", "bko_noise_fill", "bko_normalize_weights",
+            "bko_boundary_source", "bko_add_column")
 
 
 class BlockoaError(RuntimeError):
@@ -129,6 +130,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bko_combine_noisy": (i32, [i32, i32, i32, vp, i32, vp, i32, vp, i32, ctypes.POINTER(Noise), vp]),
         "bko_noise_fill": (i32, [i32, i32, vp, i32, ctypes.POINTER(Noise), vp]),
         "bko_normalize_weights": (i32, [i32, i32, vp, i32, dbl, vp, vp]),
+        "bko_boundary_source": (i32, [vp, vp, ctypes.POINTER(dbl), vp, vp]),
+        "bko_add_column": (i32, [i32, i32, vp, i32, vp, dbl, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -600,6 +603,23 @@ def combine(X: torch.Tensor, C: torch.Tensor, out_dtype=torch.float64, compute: 
     tp, ldt, tt = _block(T, "T")
     _check(load_library().bko_combine(n, s, m, xp, ldx, xt, cp, ldc, ct, tp, ldt, tt, compute, _stream(stream)))
     return T
+
+
+def boundary_source(A: HeatOperator, u_face: Sequence[float], stream=None) -> torch.Tensor:
+    """g (N,) FP64: the right-hand-side source of nonhomogeneous boundary data
+    (face temperatures in the order -x, +x, -y, +y, -z, +z), A x = q + g."""
+    g = torch.empty(A.n, dtype=torch.float64, device=A.k.device)
+    uf = (ctypes.c_double * 6)(*[float(v) for v in u_face])
+    _check(load_library().bko_boundary_source(A.handle, _ptr(A.k), uf, _ptr(g), _stream(stream)))
+    return g
+
+
+def add_column(F: torch.Tensor, g: torch.Tensor, alpha: float = 1.0, stream=None) -> torch.Tensor:
+    """F[j, :] += alpha g for every row j of F ((M, N) FP64), in place."""
+    m, n = F.shape
+    fp, ldf, _ = _block(F, "F")
+    _check(load_library().bko_add_column(n, m, fp, ldf, _ptr(g), float(alpha), _stream(stream)))
+    return F
 
 
 def combine_noisy(X: torch.Tensor, C: torch.Tensor, noise: Optional[Noise] = None, T: Optional[torch.Tensor] = None,

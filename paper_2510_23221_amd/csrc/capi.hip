@@ -248,6 +248,39 @@ __global__ void scale_coeff_kernel(int nx, int ny, int nz, const double *__restr
     swz32[a] = static_cast<float>(cz);
 }
 
+// g_a = sum over the boundary faces of cell a of w_face u_face (Sec. II-A's
+// nonhomogeneous Dirichlet value u0 or Robin ambient u_inf): the source that
+// the face fluxes w (x_a - u_face) put on the right-hand side, A x = q + g.
+__global__ void boundary_source_kernel(int nx, int ny, int nz, FaceSpec fs, const double *__restrict__ k, double u0,
+                                       double u1, double u2, double u3, double u4, double u5, double *__restrict__ g)
+{
+    const int64_t plane = static_cast<int64_t>(nx) * ny;
+    const int64_t n = plane * nz;
+    const int64_t a = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const int idx[3] = {static_cast<int>(a % nx), static_cast<int>((a / nx) % ny), static_cast<int>(a / plane)};
+    const int dims[3] = {nx, ny, nz};
+    const double uf[6] = {u0, u1, u2, u3, u4, u5};
+    const double ka = k[a];
+    double v = 0.0;
+    for (int ax = 0; ax < 3; ++ax) {
+        if (idx[ax] == 0) v += face_boundary(fs.bc[2 * ax], ka, fs.d[ax], fs.h[2 * ax]) * uf[2 * ax];
+        if (idx[ax] == dims[ax] - 1)
+            v += face_boundary(fs.bc[2 * ax + 1], ka, fs.d[ax], fs.h[2 * ax + 1]) * uf[2 * ax + 1];
+    }
+    g[a] = v;
+}
+
+// F[:, j] += alpha g for j < m
+__global__ void add_column_kernel(int64_t n, int m, double *__restrict__ F, int64_t ldf, const double *__restrict__ g,
+                                  double alpha)
+{
+    const int64_t a = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const double v = alpha * g[a];
+    for (int j = blockIdx.y; j < m; j += gridDim.y) F[static_cast<int64_t>(j) * ldf + a] += v;
+}
+
 __global__ void zero_kernel(uint32_t *p, size_t words)
 {
     const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
@@ -395,6 +428,10 @@ bko_status bko_assemble_heat_operator(int nx, int ny, int nz, double lx, double 
     op->swz32 = reinterpret_cast<const float *>(base + L.off[15]);
     op->scale64 = reinterpret_cast<const double *>(base + L.off[16]);
     op->precond = BKO_PRECOND_NONE;
+    for (int f = 0; f < 6; ++f) {
+        op->bc[f] = fs.bc[f];
+        op->h[f] = fs.h[f];
+    }
     *out = reinterpret_cast<bko_op>(op);
     return BKO_OK;
     BKO_GUARD_END
@@ -423,6 +460,42 @@ bko_status bko_operator_get_precond(bko_op A, int *kind)
     BKO_CHECK(A != nullptr && kind != nullptr, "NULL argument");
     *kind = reinterpret_cast<const Operator *>(A)->precond;
     return BKO_OK;
+}
+
+bko_status bko_boundary_source(bko_op A, const double *k_cell_dev, const double u_face[6], double *g, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(A != nullptr && k_cell_dev != nullptr && u_face != nullptr && g != nullptr, "NULL argument");
+    const Operator &op = *reinterpret_cast<const Operator *>(A);
+    for (int f = 0; f < 6; ++f) BKO_CHECK(std::isfinite(u_face[f]), "face value %d is not finite", f);
+    FaceSpec fs{};
+    for (int f = 0; f < 6; ++f) {
+        fs.bc[f] = op.bc[f];
+        fs.h[f] = op.h[f];
+    }
+    fs.d[0] = op.lx / op.nx;
+    fs.d[1] = op.ly / op.ny;
+    fs.d[2] = op.lz / op.nz;
+    const unsigned blocks = static_cast<unsigned>((op.n + 255) / 256);
+    hipLaunchKernelGGL(boundary_source_kernel, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(stream), op.nx,
+                       op.ny, op.nz, fs, k_cell_dev, u_face[0], u_face[1], u_face[2], u_face[3], u_face[4], u_face[5], g);
+    BKO_HIP(hipGetLastError());
+    return BKO_OK;
+    BKO_GUARD_END
+}
+
+bko_status bko_add_column(int n, int m, double *F, int ldf, const double *g, double alpha, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(n >= 0 && m >= 0, "bad sizes n=%d m=%d", n, m);
+    if (n == 0 || m == 0) return BKO_OK;
+    BKO_CHECK(F != nullptr && g != nullptr && ldf >= n, "bad arguments");
+    const dim3 grid(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>(std::min(m, 256)));
+    hipLaunchKernelGGL(add_column_kernel, grid, dim3(256), 0, static_cast<hipStream_t>(stream), static_cast<int64_t>(n), m,
+                       F, static_cast<int64_t>(ldf), g, alpha);
+    BKO_HIP(hipGetLastError());
+    return BKO_OK;
+    BKO_GUARD_END
 }
 
 bko_status bko_destroy_operator(bko_op A)

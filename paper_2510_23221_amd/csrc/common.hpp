@@ -146,6 +146,8 @@ struct Operator {
     const float *sdiag32, *swx32, *swy32, *swz32;
     const double *scale64;
     int precond;  // bko_precond used by the solves on this operator
+    int bc[6];    // face kinds (-x, +x, -y, +y, -z, +z) and film coefficients,
+    double h[6];  // for the boundary source of nonhomogeneous data
 };
 
 // Byte layout of the coefficient buffer.
