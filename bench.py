@@ -296,6 +296,9 @@ def bench_batched(args):
     plan = capi.BatchPlan(Gs, w.s, capi.F32)
     stream = torch.cuda.Stream()
     infos = []
+    fused = not args.separate_output
+    cwork = torch.empty(capi_bytes_combine_apply(capi, max(Gs, key=lambda G: G.n), w.s) + 256, dtype=torch.uint8,
+                        device=dev)
     with torch.cuda.stream(stream):
         tpw = plan.tune(dev, stream=stream)
 
@@ -303,8 +306,11 @@ def bench_batched(args):
             _, inf = plan.solve(Bs, w.tol, Xs=Xs, stream=stream)
             for G, X, C in zip(Gs, Xs, Cs):
                 n = G.n
-                capi.combine(X, C, T=T[:, :n], stream=stream)
-                capi.apply_operator(G, T[:, :n], F=F[:, :n], stream=stream)
+                if fused:
+                    capi.combine_apply(G, X, C, T=T[:, :n], F=F[:, :n], work=cwork, stream=stream)
+                else:
+                    capi.combine(X, C, T=T[:, :n], stream=stream)
+                    capi.apply_operator(G, T[:, :n], F=F[:, :n], stream=stream)
             infos.append(inf)
 
         for _ in range(args.warmup):
@@ -323,7 +329,7 @@ def bench_batched(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": w.name, "nchips": len(w.chips), "cells_total": int(sum(c.n for c in w.chips)),
                       "s": w.s, "M_per_chip": w.m, "tol": w.tol, "scheme": "mixed", "T_F_dtype": "float64",
-                      "precond": args.precond},
+                      "precond": args.precond, "outputs": "one pass" if fused else "two passes"},
            "autotuned_tiles_per_workgroup": tpw,
            "iters": {"min": min(i["iters"] for i in last), "max": max(i["iters"] for i in last),
                      "mean": sum(i["iters"] for i in last) / len(last)},
@@ -345,7 +351,8 @@ def bench_learned(args):
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     w = synth.workload(4, m=args.m, nchips=args.nchips)
-    data = lstart.generate_pairs(w.chips, w.B, w.C, 1e-10, compute=capi.F32)
+    pc = capi.PRECOND_JACOBI if args.precond == "jacobi" else capi.PRECOND_NONE
+    data = lstart.generate_pairs(w.chips, w.B, w.C, 1e-10, compute=capi.F32, precond=pc)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     norm = lstart.fit_normalizer(data)
@@ -357,7 +364,7 @@ def bench_learned(args):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     chips, Bs = synth.learned_start_test_chips(args.test_chips, w.chips[0].dims, w.s)
-    recs = lstart.evaluate(net, norm, chips, Bs, w.tol, compute=capi.F32, smooth=20)
+    recs = lstart.evaluate(net, norm, chips, Bs, w.tol, compute=capi.F32, smooth=20, precond=pc)
     z = np.array([r["zero_iters"] for r in recs])
     zs = np.array([r["zero_smooth_iters"] for r in recs])
     ln = np.array([r["learned_iters"] for r in recs])
@@ -368,7 +375,7 @@ def bench_learned(args):
            "n_gpus": 1, "data": "synthetic", "dtype": "bf16 weights, f32 activations; f32+f64 solve",
            "config": {"workload": "learned-start-128x128x8", "train_chips": len(w.chips), "pairs": len(w.chips) * w.m,
                       "s": w.s, "test_chips": len(recs), "tol": w.tol, "params": net.nparams, "epochs": args.train_epochs,
-                      "smoothing_sweeps": 20},
+                      "smoothing_sweeps": 20, "precond": args.precond},
            "seconds": {"generate_pairs": round(t_gen, 2), "train": round(t_train, 2)},
            "train_loss": [(a, round(b, 6)) for a, b in log],
            "iters": {"zero": float(z.mean()), "zero_smoothed": float(zs.mean()), "learned": float(ln.mean())},

@@ -61,12 +61,12 @@ class ChipPairs:
 
 
 def generate_pairs(chips: List[synth.Chip], Bs: List[np.ndarray], Cs: List[np.ndarray], tol: float,
-                   device="cuda", compute=capi.F32) -> List[ChipPairs]:
+                   device="cuda", compute=capi.F32, precond: int = capi.PRECOND_NONE) -> List[ChipPairs]:
     """BlocKOA pairs of every training chip: block solve, combination and
     operator action, all on the GPU."""
     out = []
     for chip, B, C in zip(chips, Bs, Cs):
-        G = capi.HeatOperator.from_chip(chip, device)
+        G = capi.HeatOperator.from_chip(chip, device, precond=precond)
         Bd = torch.as_tensor(B, device=device)
         X, _ = capi.block_krylov_solve(G, Bd, tol, compute=compute)
         T = capi.combine(X, torch.as_tensor(C, device=device))
@@ -153,13 +153,14 @@ def predict_x0(net: capi.UNet, norm: Normalizer, chip: synth.Chip, k: torch.Tens
 
 
 def evaluate(net: Optional[capi.UNet], norm: Optional[Normalizer], chips: List[synth.Chip], Bs: List[np.ndarray],
-             tol: float, device="cuda", compute=capi.F32, smooth: int = 0):
+             tol: float, device="cuda", compute=capi.F32, smooth: int = 0, precond: int = capi.PRECOND_NONE):
     """Block solves of every chip from the zero start, from the zero start
     after the same smoothing sweeps, and (if net is given) from the learned
-    start.  Returns per-chip records (iterations, final residuals, seconds)."""
+    start, all with the given preconditioner.  Returns per-chip records
+    (iterations, final residuals, seconds)."""
     recs = []
     for chip, B in zip(chips, Bs):
-        G = capi.HeatOperator.from_chip(chip, device)
+        G = capi.HeatOperator.from_chip(chip, device, precond=precond)
         k = torch.as_tensor(chip.k, device=device)
         Bd = torch.as_tensor(B, device=device)
         torch.cuda.synchronize()
