@@ -557,12 +557,16 @@ __device__ __forceinline__ double recip(double p)
 // pivot.  Indices s <= i < SP are decoupled padding with pivot gmax.  g is
 // an LDS copy of the Gram with row stride ld; the result (A[i][j], j < 2s:
 // left half U, right half E) goes to LDS and may overwrite g (every read of
-// g precedes the first write).
+// g precedes the first write).  gmax_ext >= 0 replaces the block's own largest
+// diagonal in the deactivation threshold; ldA > 0 and roff place the output
+// rows (stride ldA) and the right half (from column roff) in a larger array.
 template <int SP>
-__device__ __forceinline__ void wave_eliminate(const double *g, int ld, int s, double rel_thr, double *A, int *active)
+__device__ __forceinline__ void wave_eliminate(const double *g, int ld, int s, double rel_thr, double *A, int *active,
+                                               double gmax_ext = -1.0, int ldA = 0, int roff = 0)
 {
     const int lane = threadIdx.x & 63;
-    const int w = 2 * s;
+    const int w = ldA > 0 ? ldA : 2 * s;  // output row stride
+    const int ro = ldA > 0 ? roff : s;    // output column of the right half's first column
     // every lane reads (at a clamped index) so that the reads issue back to
     // back, with no branch between them
     const int lc = lane < s ? lane : 0;
@@ -577,6 +581,7 @@ __device__ __forceinline__ void wave_eliminate(const double *g, int ld, int s, d
     gmax = lane < s ? gmax : 0.0;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, off));
+    if (gmax_ext >= 0.0) gmax = gmax_ext;
     const double thr = rel_thr * gmax;
     double a[SP];
 #pragma unroll
@@ -596,32 +601,11 @@ __device__ __forceinline__ void wave_eliminate(const double *g, int ld, int s, d
         for (int i = k + 1; i < SP; ++i) a[i] = fma(readlane_f64(a[i], k), m, a[i]);
         if (lane == 0 && k < s) active[k] = act ? 1 : 0;
     }
-    const int col = lane < SP ? (lane < s ? lane : -1) : (lane - SP < s ? s + lane - SP : -1);
+    const int col = lane < SP ? (lane < s ? lane : -1) : (lane - SP < s ? ro + lane - SP : -1);
     if (lane < 2 * SP && col >= 0) {
 #pragma unroll
         for (int i = 0; i < SP; ++i)
             if (i < s) A[i * w + col] = a[i];
-    }
-}
-
-// Publish pivot row r of the register-held [G | I], its reciprocal pivot
-// (*inv) and column r into the LDS vectors rn / cn.
-template <int E>
-__device__ __forceinline__ void publish_pivot(const double (&a)[E], int i, int j0, int w, bool live, int r, double *rn,
-                                              double *cn, double *inv)
-{
-    if (!live) return;
-    if (i == r) {
-#pragma unroll
-        for (int q = 0; q < E; ++q)
-            if (j0 + q < w) rn[j0 + q] = a[q];
-    }
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-        if (j0 + q == r) {
-            cn[i] = a[q];
-            if (i == r) *inv = 1.0 / a[q];  // read only when the pivot is active
-        }
     }
 }
 
@@ -709,13 +693,15 @@ __device__ __forceinline__ void factor_small(int s, double rel_thr, int mode, Fa
 // converged when ||C e_j|| <= th_j for every column (mode 2 is the first QR
 // of the residual and is not counted as an iteration).
 //
-// Work layout: each of the 256 threads owns E consecutive entries of one row
-// of [G | I] in registers; per pivot the owners publish the pivot row (with
-// its reciprocal) and column into double-buffered LDS vectors, one barrier
-// per pivot.  The s x s products afterwards run on the FP64 matrix cores.
-// The Gram is staged in LDS first by coalesced loads.  (s <= 32 factors
-// inside the update kernels instead.)
-template <int E>
+// Work layout: a blocked masked LDL^T of [G11 G12; G21 G22] with G11 the
+// leading 32 x 32 block: one wavefront eliminates [G11 | I] (readlane
+// broadcasts), the matrix cores form U12 = E11 G12 and the Schur complement
+// G22 - U12^T D1^+ U12, one wavefront eliminates it, and the matrix cores
+// assemble E21 = -E22 (U12^T D1^+) E11.  In exact arithmetic this is the
+// sequential elimination (inactive pivots contribute nothing to the Schur
+// complement); every pivot is tested against the same threshold on the
+// largest diagonal of G.  The s x s products afterwards run on the FP64
+// matrix cores too.
 __global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__restrict__ cds, int s, double rel_thr,
                                                              int mode)
 {
@@ -724,29 +710,17 @@ __global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__re
     if (ctrl[kConverged]) return;
     const gptr<const double> __restrict__ gram = glb(static_cast<const double *>(cd.gram));
     const SmallG sm(cd.sm);
-    constexpr int EA = E;  // register row segment
     extern __shared__ __align__(16) double lds[];
     const int ss = s * s, w = 2 * s;
-    // every region is padded by E doubles so that a row segment can be read
-    // whole; padding is zeroed, masked lanes multiply it by zero
-    double *A = lds;                        // s x 2s
-    double *G = A + 2 * ss + E;             // s x s scratch
-    double *Cl = G + ss + E;                // C
-    double *rowbuf = Cl + ss + E;           // 2 x (w + E)
-    double *colbuf = rowbuf + 2 * (w + E);  // 2 x s
+    double *A = lds;       // s x 2s: [U | E]
+    double *G = A + 2 * ss;  // s x s: the symmetrised Gram, then scratch
+    double *Cl = G + ss;   // C
     __shared__ int active[kMaxS];
     __shared__ double dv[kMaxS];
-    __shared__ double invb[2];
+    __shared__ double dp1[32];  // 1 / pivot of the first block (0 if inactive)
     __shared__ double gmax;
     __shared__ int notconv;
     const int tid = threadIdx.x;
-    for (int e = tid; e < E; e += kFacThreads) {
-        A[2 * ss + e] = 0.0;
-        G[ss + e] = 0.0;
-        Cl[ss + e] = 0.0;
-        rowbuf[w + e] = 0.0;
-        rowbuf[2 * w + E + e] = 0.0;
-    }
     {
         // all loads of C and of the Gram in flight before the LDS stores
         constexpr int IT = kMaxS * kMaxS / kFacThreads;
@@ -766,57 +740,62 @@ __global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__re
             }
         }
     }
+    for (int e = tid; e < s * w; e += kFacThreads) A[e] = 0.0;  // structural zeros of U21 and E12
     if (tid == 0) notconv = 0;
     __syncthreads();
-    {
-        const int tpr = (w + EA - 1) / EA;
-        const int i = tid / tpr, j0 = (tid % tpr) * EA;
-        const bool live = i < s;
-        double a[EA];
-#pragma unroll
-        for (int q = 0; q < EA; ++q) {
-            const int j = j0 + q;
-            a[q] = 0.0;
-            if (live && j < w) a[q] = j < s ? 0.5 * (G[i * s + j] + G[j * s + i]) : (j - s == i ? 1.0 : 0.0);
+    // symmetrise in place (each pair by one thread) and take the largest diagonal
+    for (int e = tid; e < ss; e += kFacThreads) {
+        const int i = e / s, j = e % s;
+        if (i < j) {
+            const double v = 0.5 * (G[i * s + j] + G[j * s + i]);
+            G[i * s + j] = v;
+            G[j * s + i] = v;
         }
-        if (tid < 64) {
-            double v = tid < s ? G[tid * s + tid] : 0.0;
-            for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-            if (tid == 0) gmax = v;
-        }
-        publish_pivot<EA>(a, i, j0, w, live, 0, rowbuf, colbuf, &invb[0]);
+    }
+    if (tid < 64) {
+        double v = tid < s ? G[tid * s + tid] : 0.0;
+        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+        if (tid == 0) gmax = v;
+    }
+    __syncthreads();
+    const int s1 = s < 32 ? s : 32, s2 = s - s1;
+    const double gm = gmax;
+    if (tid < 64) wave_eliminate<32>(G, s, s1, rel_thr, A, active, gm, w, s);
+    __syncthreads();
+    if (s2 > 0) {
+        for (int k = tid; k < s1; k += kFacThreads) dp1[k] = active[k] ? 1.0 / A[k * w + k] : 0.0;
+        // U12 = E11 G12 (E11[i][k] = A[i][s + k])
+        small_gemm(
+            32, [&](int i, int k) { return A[i * w + s + k]; },
+            [&](int k, int j) { return j < s2 ? G[k * s + s1 + j] : 0.0; },
+            [&](int i, int j, double v) {
+                if (j < s2) A[i * w + s1 + j] = v;
+            });
         __syncthreads();
-        const double thr = rel_thr * gmax;
-        const int ic = live ? i : 0;
-        for (int k = 0; k < s; ++k) {
-            const int b = k & 1;
-            const double *rb = rowbuf + b * (w + E);
-            const double *cb = colbuf + b * s;
-            const double p = rb[k];
-            const bool act = p > thr && isfinite(p);
-            // branch-free update: read the whole pivot-row segment, mask the multiplier
-            double r[EA];
-#pragma unroll
-            for (int q = 0; q < EA; ++q) r[q] = rb[j0 + q];
-            const double cv = cb[ic];
-            const double l = (act && live && i > k) ? cv * invb[b] : 0.0;
-#pragma unroll
-            for (int q = 0; q < EA; ++q) {
-                const int j = j0 + q;
-                const bool upd = (j > k && j < s) || (j >= s && j <= s + k);
-                a[q] = fma(upd ? -l : 0.0, r[q], a[q]);
-            }
-            if (k + 1 < s)
-                publish_pivot<EA>(a, i, j0, w, live, k + 1, rowbuf + (b ^ 1) * (w + E), colbuf + (b ^ 1) * s,
-                                  &invb[b ^ 1]);
-            if (tid == 0) active[k] = act ? 1 : 0;
-            __syncthreads();
-        }
-        if (live) {
-#pragma unroll
-            for (int q = 0; q < EA; ++q)
-                if (j0 + q < w) A[i * w + j0 + q] = a[q];
-        }
+        // Schur complement G22 -= U12^T D1^+ U12, in place
+        small_gemm(
+            32, [&](int i, int k) { return i < s2 ? A[k * w + s1 + i] * dp1[k] : 0.0; },
+            [&](int k, int j) { return j < s2 ? A[k * w + s1 + j] : 0.0; },
+            [&](int i, int j, double v) {
+                if (i < s2 && j < s2) G[(s1 + i) * s + s1 + j] -= v;
+            });
+        __syncthreads();
+        if (tid < 64) wave_eliminate<32>(G + s1 * s + s1, s, s2, rel_thr, A + s1 * w + s1, active + s1, gm, w, s);
+        // T1 = U12^T D1^+ E11 (s2 x s1) into the G11 block, no longer read
+        small_gemm(
+            32, [&](int i, int k) { return i < s2 ? A[k * w + s1 + i] * dp1[k] : 0.0; },
+            [&](int k, int j) { return A[k * w + s + j]; },
+            [&](int i, int j, double v) {
+                if (i < s2) G[i * s + j] = v;
+            });
+        __syncthreads();
+        // E21 = -E22 T1 (E22[i][k] = A[s1 + i][s + s1 + k])
+        small_gemm(
+            32, [&](int i, int k) { return (i < s2 && k < s2) ? A[(s1 + i) * w + s + s1 + k] : 0.0; },
+            [&](int k, int j) { return k < s2 ? G[k * s + j] : 0.0; },
+            [&](int i, int j, double v) {
+                if (i < s2) A[(s1 + i) * w + s + j] = -v;
+            });
     }
     __syncthreads();
     for (int k = tid; k < s; k += kFacThreads)
@@ -875,15 +854,6 @@ __global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__re
         if (inactive == s) ctrl[kAllDeflated] = 1;
         if (notconv == 0 || inactive == s) ctrl[kConverged] = 1;
     }
-}
-
-// Smallest row-segment width E (power of two) with s rows x ceil(2s / E)
-// threads fitting one workgroup.
-inline int factor_segment(int s)
-{
-    int e = 1;
-    while (s * ((2 * s + e - 1) / e) > kFacThreads) e *= 2;
-    return e;
 }
 
 // ------------------------------------------------------------------ block updates
@@ -1961,18 +1931,15 @@ size_t row_kernel_lds(int s, bko_dtype compute)
 bko_status launch_reduce_factor(const Ctx &x, double rel_thr, int mode)
 {
     const int s = x.L->s, ss = s * s;
-    BKO_CHECK(s > 32 && factor_segment(s) >= 16, "the separate factorisation kernel is for s > 32, got s = %d", s);
+    BKO_CHECK(s > 32 && s <= kMaxS, "the separate factorisation kernel is for 32 < s <= 64, got s = %d", s);
     TimedLaunch tl(kSmall, x.st);
     const unsigned rblocks = static_cast<unsigned>(std::min(kRedBlocks, ss));
     hipLaunchKernelGGL(gram_reduce_kernel, dim3(rblocks, static_cast<unsigned>(x.L->nchips)), dim3(kThreads), 0, x.st,
                        x.cds, ss);
     BKO_HIP(hipGetLastError());
-    // A, G, C (each padded by E <= 32), two pivot rows (padded) and columns
-    const size_t lds = sizeof(double) * (4 * ss + 3 * 32 + 2 * (2 * s + 32) + 2 * s);
+    const size_t lds = sizeof(double) * 4 * ss;  // [U | E], the Gram, C
     const dim3 grid(static_cast<unsigned>(x.L->nchips));
-    const int e = factor_segment(s);
-    if (e == 16) hipLaunchKernelGGL((factor_kernel<16>), grid, dim3(kFacThreads), lds, x.st, x.cds, s, rel_thr, mode);
-    else hipLaunchKernelGGL((factor_kernel<32>), grid, dim3(kFacThreads), lds, x.st, x.cds, s, rel_thr, mode);
+    hipLaunchKernelGGL(factor_kernel, grid, dim3(kFacThreads), lds, x.st, x.cds, s, rel_thr, mode);
     BKO_HIP(hipGetLastError());
     return BKO_OK;
 }
