@@ -281,14 +281,15 @@ __global__ __launch_bounds__(kThreads) void normalize_weights_kernel(int s, int6
 // The product is formed transposed, T^T tile = C^T X^T, so that the matrix
 // core's result layout puts 16 consecutive cells of one field in the 16
 // lanes of a lane group: every store instruction writes four full 128-byte
-// lines of T and no LDS staging or barrier is needed.  Each wave owns 16
-// cells (its X rows stay in registers as the B operand); the A operand (C
-// for 16 fields) is read straight from L2/global by each lane.  The k index
+// lines of T, with no staging of the results.  Each wave owns 16 cells (its
+// X rows stay in registers as the B operand); the A operand (C for 16
+// fields) is staged once per workgroup in LDS by coalesced loads, double
+// buffered, one barrier per 16 fields.  The k index
 // of the contraction is laid out so that lane group g holds k = g KS .. g KS
 // + KS - 1 (any bijection of k onto the MFMA slots gives the same sum).
 // kDual: also F = Y C with Y = A X, the operator action of every field
 // formed from the s columns of A X (Sec. III-C applied to Eq. (5)'s sum).
-template <bool kDual, int kMaxKS>
+template <bool kDual, bool kNoise, int kMaxKS>
 __global__ __launch_bounds__(kThreads) void combine_direct_kernel(int64_t n, int s, int64_t m,
                                                                   const double *__restrict__ X, int64_t ldx,
                                                                   const double *__restrict__ Y, int64_t ldy,
@@ -314,20 +315,41 @@ __global__ __launch_bounds__(kThreads) void combine_direct_kernel(int64_t n, int
         xb[t] = ok ? X[static_cast<int64_t>(k) * ldx + cell] : 0.0;
         if constexpr (kDual) yb[t] = ok ? Y[static_cast<int64_t>(k) * ldy + cell] : 0.0;
     }
-    // 16 fields at a time; the next block's C loads are issued before this
-    // block's products and stores
-    double a[kMaxKS], an[kMaxKS];
-    auto load_c = [&](int64_t f0, double (&dst)[kMaxKS]) {
-        const int64_t field = f0 + li;
+    // 16 fields at a time: the workgroup stages C for the block in LDS
+    // (coalesced loads, shared by its four waves), the next block's loads
+    // in flight during this block's products and stores
+    constexpr int kCS = 4 * kMaxKS + 1;                   // LDS row stride (padded)
+    constexpr int kCR = (16 * 4 * kMaxKS + kThreads - 1) / kThreads;
+    __shared__ double cbuf[2][16 * kCS];
+    const int s4 = 4 * ks;
+    double cv[kCR];
+    auto fetch_c = [&](int64_t f0) {
 #pragma unroll
-        for (int t = 0; t < kMaxKS; ++t) {
-            const int k = lg * ks + t;
-            dst[t] = (t < ks && k < s && field < f_end) ? C[field * ldc + k] : 0.0;
+        for (int i = 0; i < kCR; ++i) {
+            const int e = threadIdx.x + i * kThreads;
+            const int r = e / s4, k = e % s4;
+            cv[i] = (e < 16 * s4 && k < s && f0 + r < f_end) ? C[(f0 + r) * ldc + k] : 0.0;
         }
     };
-    if (f_begin < f_end) load_c(f_begin, a);
+    auto stash_c = [&](int b) {
+#pragma unroll
+        for (int i = 0; i < kCR; ++i) {
+            const int e = threadIdx.x + i * kThreads;
+            if (e < 16 * s4) cbuf[b][(e / s4) * kCS + e % s4] = cv[i];
+        }
+    };
+    if (f_begin < f_end) {
+        fetch_c(f_begin);
+        stash_c(0);
+    }
+    __syncthreads();
+    int b = 0;
     for (int64_t f0 = f_begin; f0 < f_end; f0 += 16) {
-        if (f0 + 16 < f_end) load_c(f0 + 16, an);
+        const bool more = f0 + 16 < f_end;
+        if (more) fetch_c(f0 + 16);
+        double a[kMaxKS];
+#pragma unroll
+        for (int t = 0; t < kMaxKS; ++t) a[t] = t < ks ? cbuf[b][li * kCS + lg * ks + t] : 0.0;
         d4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int t = 0; t < kMaxKS; ++t) {
@@ -342,14 +364,15 @@ __global__ __launch_bounds__(kThreads) void combine_direct_kernel(int64_t n, int
                 const int64_t field = f0 + mfma_row<true>(lg, r);
                 if (field < f_end) {
                     double t = acc[r];
-                    if (na.kind != BKO_NOISE_NONE) t += noise_value(na.kind, na.amp, na.seed, na.field_offset + field, cell);
+                    if constexpr (kNoise) t += noise_value(na.kind, na.amp, na.seed, na.field_offset + field, cell);
                     T[field * ldt + cell] = t;
                     if constexpr (kDual) F[field * ldf + cell] = acc2[r];
                 }
             }
         }
-#pragma unroll
-        for (int t = 0; t < kMaxKS; ++t) a[t] = an[t];
+        if (more) stash_c(b ^ 1);
+        __syncthreads();
+        b ^= 1;
     }
 }
 
@@ -378,18 +401,29 @@ bko_status run_direct(int64_t n, int s, int64_t m, const double *X, int64_t ldx,
         return BKO_EINVAL;
     }
     const dim3 grid(static_cast<uint32_t>(nb)), block(kThreads);
-#define BKO_DIRECT(D, KS)                                                                                           \
-    hipLaunchKernelGGL((combine_direct_kernel<D, KS>), grid, block, 0, stream, n, s, m, X, ldx, Y, ldy, C, ldc, T, ldt, \
-                       F, ldf, fields_per_wg, ntiles, na)
+#define BKO_DIRECT(D, E, KS)                                                                                           \
+    hipLaunchKernelGGL((combine_direct_kernel<D, E, KS>), grid, block, 0, stream, n, s, m, X, ldx, Y, ldy, C, ldc, T, \
+                       ldt, F, ldf, fields_per_wg, ntiles, na)
+    // the noise epilogue (Philox state) is compiled only into the noisy
+    // variant, so that the others keep their registers for occupancy
     const int ks = (s + 3) / 4;
+    const bool noisy = na.kind != BKO_NOISE_NONE;
+    if (Y && noisy) {
+        set_error("the one-pass combination takes no noise term");
+        return BKO_EINVAL;
+    }
     if (Y) {
-        if (ks <= 4) BKO_DIRECT(true, 4);
-        else if (ks <= 8) BKO_DIRECT(true, 8);
-        else BKO_DIRECT(true, 16);
+        if (ks <= 4) BKO_DIRECT(true, false, 4);
+        else if (ks <= 8) BKO_DIRECT(true, false, 8);
+        else BKO_DIRECT(true, false, 16);
+    } else if (noisy) {
+        if (ks <= 4) BKO_DIRECT(false, true, 4);
+        else if (ks <= 8) BKO_DIRECT(false, true, 8);
+        else BKO_DIRECT(false, true, 16);
     } else {
-        if (ks <= 4) BKO_DIRECT(false, 4);
-        else if (ks <= 8) BKO_DIRECT(false, 8);
-        else BKO_DIRECT(false, 16);
+        if (ks <= 4) BKO_DIRECT(false, false, 4);
+        else if (ks <= 8) BKO_DIRECT(false, false, 8);
+        else BKO_DIRECT(false, false, 16);
     }
 #undef BKO_DIRECT
     BKO_HIP(hipGetLastError());
