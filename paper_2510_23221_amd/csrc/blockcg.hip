@@ -62,6 +62,7 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
 
 constexpr int kThreads = 256;      // row kernels
 constexpr int kFacThreads = 256;   // factorisation kernel
@@ -242,10 +243,13 @@ template <class T, int NB> __host__ __device__ constexpr size_t spmm_gram_lds()
 // P and AP in LDS; Gram phase: each wave takes a quarter of the staged rows
 // on the FP64 matrix cores.
 constexpr int kSpThreads = 256;  // stencil + Gram kernel (eight-wave workgroups measured slower)
+// For s > 32 the stencil + Gram kernels are held to two waves per SIMD: left
+// to itself the compiler spends registers on one (measured 25 % slower).
 
 template <class T, int NB>
-__global__ __launch_bounds__(kSpThreads) void spmm_gram_kernel(const ChipDev *__restrict__ cds,
-                                                               const uint16_t *__restrict__ tab, int s)
+__global__ __launch_bounds__(kSpThreads, (NB > 2 ? 2 : 1)) void spmm_gram_kernel(const ChipDev *__restrict__ cds,
+                                                                                  const uint16_t *__restrict__ tab,
+                                                                                  int s)
 {
     constexpr int TR = stage_rows<T, NB>();
     constexpr int SP = 16 * NB;
@@ -374,8 +378,9 @@ template <class T> __device__ __forceinline__ typename Vec16<T>::type ld16(gptr<
 // then lies in one x-row).  The x neighbours inside the group come from its
 // own vector, the two outside it from scalar loads.
 template <class T, int NB>
-__global__ __launch_bounds__(kSpThreads) void spmm_gram_vec_kernel(const ChipDev *__restrict__ cds,
-                                                                   const uint16_t *__restrict__ tab, int s)
+__global__ __launch_bounds__(kSpThreads, (NB > 2 ? 2 : 1)) void spmm_gram_vec_kernel(const ChipDev *__restrict__ cds,
+                                                                                      const uint16_t *__restrict__ tab,
+                                                                                      int s)
 {
     using VT = typename Vec16<T>::type;
     constexpr int V = vec_cells<T>();
@@ -1010,6 +1015,121 @@ __global__ __launch_bounds__(kThreads) void update_w_kernel(const ChipDev *__res
     publish_partial<NB, true>(g, s, lds, glb(cd.parts) + static_cast<size_t>(local) * s * s);
 }
 
+// The W update in FP32 for s > 32 (blocks streamed from HBM): a wave takes
+// 32 rows at a time as two interleaved 16-row matrix-core blocks (block q
+// holds rows 2 i + q), so that one 8-byte load gives a lane its operand in
+// both blocks and 16 lanes read a whole 128-byte line of a column; result
+// register r of the two blocks holds 2 consecutive rows (8 g + 2 r, + 1 for
+// lane group g), one 8-byte store.  The W^T W partial takes every row of
+// both blocks as a k slot of the FP64 matrix cores, as in update_w_kernel.
+// (Held to two waves per SIMD it spills; one wave with no spills measured
+// faster.)
+template <int NB>
+__global__ __launch_bounds__(kThreads) void update_w_rows2_kernel(const ChipDev *__restrict__ cds,
+                                                                     const uint16_t *__restrict__ tab, int s, int init)
+{
+    int local;
+    const ChipDev &cd = chip_of(cds, tab, local);
+    const int wgs = cd.wgs;
+    if (glb(cd.ctrl)[kConverged]) return;
+    constexpr int KS = 4 * NB;
+    constexpr int SP = 16 * NB;
+    constexpr int MST = SP + 1;
+    __shared__ float M3s[SP * MST];
+    __shared__ float M2s[SP * MST];  // -M2
+    __shared__ double lds[kMaxS * kMaxS];
+    if (!init) {
+        float *const dst[2] = {M3s, M2s};
+        const gptr<const float> src[2] = {glb(static_cast<const float *>(cd.sm.M3f)),
+                                          glb(static_cast<const float *>(cd.sm.M2f))};
+        const bool neg[2] = {false, true};
+        stage_small<float, SP, MST, 2>(dst, src, s, neg);
+        __syncthreads();
+    }
+    const gptr<float> __restrict__ W = glb(static_cast<float *>(cd.W));
+    const gptr<const float> __restrict__ AP = glb(static_cast<const float *>(cd.AP));
+    const int64_t ldw = cd.ldw;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const f2 zero = {0.f, 0.f};
+    auto ld8 = [](gptr<const float> p) { return *reinterpret_cast<gptr<const f2>>(p); };
+    d4 g[NB * (NB + 1) / 2];
+#pragma unroll
+    for (int q = 0; q < NB * (NB + 1) / 2; ++q) g[q] = d4{0.0, 0.0, 0.0, 0.0};
+    const int64_t ntiles = ldw / kTileRows;
+    for (int64_t tile = local; tile < ntiles; tile += wgs) {
+        for (int h = 0; h < 2; ++h) {
+            const int64_t r0 = tile * kTileRows + wave * 64 + 32 * h;
+            f4 wv[NB][2];
+            if (init) {
+#pragma unroll
+                for (int jb = 0; jb < NB; ++jb) {
+                    const int colj = jb * 16 + li;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const f2 v = colj < s ? ld8(gptr<const float>(W) + colj * ldw + r0 + 8 * lg + 2 * r) : zero;
+                        wv[jb][0][r] = v[0];
+                        wv[jb][1][r] = v[1];
+                    }
+                }
+            } else {
+                f2 wa[KS], aa[KS];
+#pragma unroll
+                for (int t = 0; t < KS; ++t) {
+                    const int col = 4 * t + lg;
+                    wa[t] = col < s ? ld8(gptr<const float>(W) + col * ldw + r0 + 2 * li) : zero;
+                    aa[t] = col < s ? ld8(AP + col * ldw + r0 + 2 * li) : zero;
+                }
+#pragma unroll
+                for (int jb = 0; jb < NB; ++jb) {
+                    const int colj = jb * 16 + li;
+                    f4 acc[2];
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int t = 0; t < KS; ++t) {
+                        const float m3 = M3s[(4 * t + lg) * MST + colj];
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) acc[q] = MF<float>::mma(wa[t][q], m3, acc[q]);
+                    }
+#pragma unroll
+                    for (int t = 0; t < KS; ++t) {
+                        const float m2 = M2s[(4 * t + lg) * MST + colj];
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) acc[q] = MF<float>::mma(aa[t][q], m2, acc[q]);
+                    }
+                    wv[jb][0] = acc[0];
+                    wv[jb][1] = acc[1];
+                }
+                // every lane has read its rows of W: write the new rows
+#pragma unroll
+                for (int jb = 0; jb < NB; ++jb) {
+                    const int colj = jb * 16 + li;
+                    if (colj < s) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const f2 v = {wv[jb][0][r], wv[jb][1][r]};
+                            *reinterpret_cast<gptr<f2>>(W + colj * ldw + r0 + 8 * lg + 2 * r) = v;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int ab = 0; ab < NB; ++ab)
+#pragma unroll
+                        for (int bb = ab; bb < NB; ++bb)
+                            g[ublock<NB>(ab, bb)] = mma64(static_cast<double>(wv[ab][q][r]),
+                                                          static_cast<double>(wv[bb][q][r]), g[ublock<NB>(ab, bb)]);
+        }
+    }
+    static_assert(kMaxS * kMaxS >= publish_lds<kThreads>(4), "publish_partial LDS");
+    publish_partial<NB, true>(g, s, lds, glb(cd.parts) + static_cast<size_t>(local) * s * s);
+}
+
 // D += P M1 ;  P = W M3 + P M4   (matrix cores, storage precision; Q = W M3)
 template <class T, int NB>
 __global__ __launch_bounds__(kThreads) void update_dqp_kernel(const ChipDev *__restrict__ cds,
@@ -1057,8 +1177,9 @@ __global__ __launch_bounds__(kThreads) void update_dqp_kernel(const ChipDev *__r
                 wa[t] = col < s ? W[col * ldw + r0 + li] : T(0);
             }
             // pa holds this wave's rows of every column of P, so the new rows
-            // can be written column block by column block
-#pragma unroll
+            // can be written column block by column block (a loop for s > 32,
+            // which keeps the small-matrix reads of one block in registers)
+#pragma unroll(NB > 2 ? 1 : NB)
             for (int jb = 0; jb < NB; ++jb) {
                 const int colj = jb * 16 + li;
                 V ad, ap;
@@ -1082,6 +1203,99 @@ __global__ __launch_bounds__(kThreads) void update_dqp_kernel(const ChipDev *__r
                         D[idx] = ad[r];
                         P[idx] = ap[r];
                     }
+                }
+            }
+        }
+    }
+}
+
+// The same update in FP32 for s > 32, where the N x s blocks no longer fit
+// the Infinity Cache and come from HBM: a wave takes its 64 rows at once as
+// four interleaved 16-row matrix-core blocks (block q holds rows 4 i + q,
+// i = 0..15), so that one 16-byte load gives a lane its operand in all four
+// blocks and 16 lanes read 256 contiguous bytes of a column; result register
+// r of the four blocks then holds 4 consecutive rows (rows 16 g + 4 r ..
+// + 3 of lane group g), written with one 16-byte store.
+template <int NB>
+__global__ __launch_bounds__(kThreads) void update_dqp_rows4_kernel(const ChipDev *__restrict__ cds,
+                                                                    const uint16_t *__restrict__ tab, int s)
+{
+    int local;
+    const ChipDev &cd = chip_of(cds, tab, local);
+    const int wgs = cd.wgs;
+    if (glb(cd.ctrl)[kStop]) return;
+    constexpr int KS = 4 * NB;
+    constexpr int SP = 16 * NB;
+    constexpr int MST = SP + 1;
+    extern __shared__ __align__(16) double dlds[];
+    float *M1 = reinterpret_cast<float *>(dlds);
+    float *M3 = M1 + SP * MST;
+    float *M4 = M3 + SP * MST;
+    {
+        float *const dst[3] = {M1, M3, M4};
+        const gptr<const float> src[3] = {glb(static_cast<const float *>(cd.sm.M1f)),
+                                          glb(static_cast<const float *>(cd.sm.M3f)),
+                                          glb(static_cast<const float *>(cd.sm.M4f))};
+        const bool neg[3] = {false, false, false};
+        stage_small<float, SP, MST, 3>(dst, src, s, neg);
+    }
+    __syncthreads();
+    const gptr<float> __restrict__ D = glb(static_cast<float *>(cd.Dv));
+    const gptr<float> __restrict__ P = glb(static_cast<float *>(cd.P));
+    const gptr<const float> __restrict__ W = glb(static_cast<const float *>(cd.W));
+    const int64_t ldw = cd.ldw;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t ntiles = ldw / kTileRows;
+    const f4 zero = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t tile = local; tile < ntiles; tile += wgs) {
+        const int64_t r0 = tile * kTileRows + wave * 64;
+        f4 pa[KS], wa[KS];
+#pragma unroll
+        for (int t = 0; t < KS; ++t) {
+            const int col = 4 * t + lg;
+            pa[t] = col < s ? ld16(gptr<const float>(P) + col * ldw + r0 + 4 * li) : zero;
+            wa[t] = col < s ? ld16(W + col * ldw + r0 + 4 * li) : zero;
+        }
+        // every lane has read its rows of P: the new rows are written column
+        // block by column block
+#pragma unroll 1
+        for (int jb = 0; jb < NB; ++jb) {
+            const int colj = jb * 16 + li;
+            f4 ad[4], ap[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const f4 d = colj < s ? ld16(gptr<const float>(D) + colj * ldw + r0 + 16 * lg + 4 * r) : zero;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    ad[q][r] = d[q];
+                    ap[q][r] = 0.f;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+                const int k = 4 * t + lg;
+                const float m1 = M1[k * MST + colj], m3 = M3[k * MST + colj];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    ad[q] = MF<float>::mma(pa[t][q], m1, ad[q]);
+                    ap[q] = MF<float>::mma(wa[t][q], m3, ap[q]);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+                const float m4 = M4[(4 * t + lg) * MST + colj];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ap[q] = MF<float>::mma(pa[t][q], m4, ap[q]);
+            }
+            if (colj < s) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t idx = colj * ldw + r0 + 16 * lg + 4 * r;
+                    const f4 dn = {ad[0][r], ad[1][r], ad[2][r], ad[3][r]};
+                    const f4 pn = {ap[0][r], ap[1][r], ap[2][r], ap[3][r]};
+                    *reinterpret_cast<gptr<f4>>(D + idx) = dn;
+                    *reinterpret_cast<gptr<f4>>(P + idx) = pn;
                 }
             }
         }
@@ -1889,12 +2103,19 @@ bko_status launch_row_kernels(int which, const Ctx &x, int init)
             tl.launch(spmm_gram_kernel<T, NB>, grid, dim3(kSpThreads), spmm_gram_lds<T, NB>(), x.cds, x.tab, s);
     } else if (which == 1) {
         TimedLaunch tl(kUpdate, x.st);
-        tl.launch(update_w_kernel<T, NB>, grid, block, 0, x.cds, x.tab, s, init);
+        if constexpr (sizeof(T) == 4 && NB > 2)
+            tl.launch(update_w_rows2_kernel<NB>, grid, block, 0, x.cds, x.tab, s, init);
+        else
+            tl.launch(update_w_kernel<T, NB>, grid, block, 0, x.cds, x.tab, s, init);
     } else {
         TimedLaunch tl(::bko::kUpdateDQP, x.st);
         const size_t sp = 16 * NB;
-        tl.launch(update_dqp_kernel<T, NB>, grid, block, static_cast<uint32_t>(3 * sizeof(T) * sp * (sp + 1)), x.cds,
-                  x.tab, s);
+        if constexpr (sizeof(T) == 4 && NB > 2)
+            tl.launch(update_dqp_rows4_kernel<NB>, grid, block, static_cast<uint32_t>(3 * sizeof(T) * sp * (sp + 1)),
+                      x.cds, x.tab, s);
+        else
+            tl.launch(update_dqp_kernel<T, NB>, grid, block, static_cast<uint32_t>(3 * sizeof(T) * sp * (sp + 1)),
+                      x.cds, x.tab, s);
     }
     BKO_HIP(hipGetLastError());
     return BKO_OK;
