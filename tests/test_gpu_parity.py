@@ -332,6 +332,24 @@ def test_block_solve_degenerate_columns(ops, dev):
     assert np.abs(X[5]).max() == 0.0
 
 
+@pytest.mark.parametrize("compute", [capi.F64, capi.F32])
+def test_block_solve_degenerate_columns_blocked(ops, dev, compute):
+    """s = 24 (the two-block elimination): duplicates, a combination and a
+    zero column spread over both pivot blocks are deflated; the solve
+    converges and the zero column stays zero."""
+    chip, A, G = ops["2d"]
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((24, A.n))
+    B[20] = B[3]
+    B[17] = 0.0
+    B[22] = 2.0 * B[0] - B[10]
+    B[9] = B[1]
+    tol = 1e-10 if compute == capi.F64 else 1e-8
+    X, info, _ = _solve_check(A, G, B, tol, compute, dev, xerr=1e-6)
+    assert info["deflated"] >= 1
+    assert np.abs(X[17]).max() == 0.0
+
+
 def test_block_solve_initial_guess(ops, dev):
     chip, A, G = ops["2d"]
     rng = np.random.default_rng(5)
