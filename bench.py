@@ -157,8 +157,7 @@ def main():
     cwork = torch.empty(capi_bytes_combine_apply(capi, G, s) + 256, dtype=torch.uint8, device=dev) if fused else None
     noise = capi.Noise(noise_kind, args.noise_amp, 20251021, 0)
 
-    def step():
-        _, info = capi.block_krylov_solve(G, B, w.tol, compute=compute, X=X, work=wview)
+    def outputs():
         if fused:
             capi.combine_apply(G, X, C, T=T, F=F, work=cwork)
         elif noise_kind != capi.NOISE_NONE:
@@ -167,6 +166,10 @@ def main():
         else:
             capi.combine(X, C, out_dtype=t_dtype, compute=comb_compute, T=T)
             capi.apply_operator(G, T, out_dtype=t_dtype, compute=apply_compute, F=F)
+
+    def step():
+        _, info = capi.block_krylov_solve(G, B, w.tol, compute=compute, X=X, work=wview)
+        outputs()
         infos.append(info)
 
     for _ in range(args.warmup):
@@ -269,6 +272,8 @@ def main():
     }
     if args.cg_columns > 0:
         res["per_sample_cg"] = per_sample_cg(G, B, C, w, args.cg_columns, value)
+        res["ablations"] = ablations(G, B, C, X, w, args.cg_columns, value, compute, wview, outputs,
+                                     res["per_sample_cg"]["value"])
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res), flush=True)
@@ -415,6 +420,51 @@ def per_sample_cg(G, B, C, w, cols, value):
             "blockoa_over_cg": round(value / rate, 1)}
 
 
+def ablations(G, B, C, X, w, cols, value, compute, wview, outputs, cg_rate):
+    """The paper's ablation of BlocKOA's two modules (Sec. V, Table 7) on the
+    same GPU and workload, as pairs/s:
+      without block Krylov: the s basis solutions by per-column FP64 CG (same
+        preconditioner), then the same combination and operator action;
+      without operator action: every field's power map b = B c solved by the
+        block solve itself, s columns at a time (timed on the first `cols`
+        maps, rounded to whole blocks, and scaled linearly);
+      without both: per-column CG of every power map (the per-sample CG
+        baseline above)."""
+    import torch
+
+    from paper_2510_23221_amd import capi
+
+    s, m = B.shape[0], C.shape[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Xcg, iters, _ = capi.cg_solve(G, B, w.tol)
+    X.copy_(Xcg)
+    outputs()
+    torch.cuda.synchronize()
+    t_wo_block = time.perf_counter() - t0
+    nb = max(1, min(cols, m) // s)
+    Bc = (C[:nb * s] @ B).contiguous()
+    Xb = torch.empty_like(Bc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = 0
+    for i in range(nb):
+        _, info = capi.block_krylov_solve(G, Bc[i * s:(i + 1) * s], w.tol, compute=compute, X=Xb[i * s:(i + 1) * s],
+                                          work=wview)
+        its += info["iters"]
+    torch.cuda.synchronize()
+    t_wo_op = time.perf_counter() - t0
+    r_block = m / t_wo_block
+    r_op = nb * s / t_wo_op
+    return {"unit": "pairs/s",
+            "blockoa": round(value, 1),
+            "wo_block_krylov": {"value": round(r_block, 1), "cg_mean_iters": round(float(iters.mean()), 1),
+                                "blockoa_over": round(value / r_block, 2)},
+            "wo_operator_action": {"value": round(r_op, 1), "columns": nb * s, "block_solves": nb,
+                                   "mean_block_iters": round(its / nb, 1), "blockoa_over": round(value / r_op, 1)},
+            "wo_all": {"value": cg_rate, "blockoa_over": round(value / cg_rate, 1)}}
+
+
 def cpu_baseline(w, min_seconds=10.0, max_reps=5):
     """The CPU oracle as it stands, on the host cores, over the whole
     workload (no extrapolation): per-column CG for the s basis solves, then
@@ -443,6 +493,7 @@ def cpu_baseline(w, min_seconds=10.0, max_reps=5):
                       f"{float(np.mean(iters_seen)):.0f} iterations, then combination + operator action of all "
                       f"{w.m} fields), median of {len(runs)} runs",
             "seconds_measured": round(float(sum(runs)), 2)}
+
 
 if __name__ == "__main__":
     main()

@@ -241,7 +241,8 @@ template <class T, int NB> __host__ __device__ constexpr size_t spmm_gram_lds()
 // workgroup.  Stencil phase: thread (cell, column class) forms the 7-point
 // product of its cell for every column of its class, writes AP, and stages
 // P and AP in LDS; Gram phase: each wave takes a quarter of the staged rows
-// on the FP64 matrix cores.
+// on the FP64 matrix cores, forming only the upper 16 x 16 blocks (P^T A P
+// is symmetric; the partial is written with its transpose).
 constexpr int kSpThreads = 256;  // stencil + Gram kernel (eight-wave workgroups measured slower)
 // For s > 32 the stencil + Gram kernels are held to two waves per SIMD: left
 // to itself the compiler spends registers on one (measured 25 % slower).
@@ -287,9 +288,9 @@ __global__ __launch_bounds__(kSpThreads, (NB > 2 ? 2 : 1)) void spmm_gram_kernel
     const int64_t plane = static_cast<int64_t>(nx) * ny;
     const int cell = tid % TR, cls = tid / TR;
 
-    d4 acc[NB * NB];
+    d4 acc[NB * (NB + 1) / 2];  // upper blocks of P^T AP (symmetric)
 #pragma unroll
-    for (int q = 0; q < NB * NB; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < NB * (NB + 1) / 2; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
     const int64_t ntiles = ldw / kTileRows;
     for (int64_t tile = local; tile < ntiles; tile += wgs) {
         for (int half = 0; half < kTileRows / TR; ++half) {
@@ -346,14 +347,15 @@ __global__ __launch_bounds__(kSpThreads, (NB > 2 ? 2 : 1)) void spmm_gram_kernel
 #pragma unroll
                     for (int x = 0; x < NB; ++x)
 #pragma unroll
-                        for (int y = 0; y < NB; ++y) acc[x * NB + y] = mma64(u[x][t], v[y][t], acc[x * NB + y]);
+                        for (int y = x; y < NB; ++y)
+                            acc[ublock<NB>(x, y)] = mma64(u[x][t], v[y][t], acc[ublock<NB>(x, y)]);
             }
             __syncthreads();
         }
     }
     static_assert(spmm_gram_lds<T, NB>() >= sizeof(double) * publish_lds<kSpThreads>(NB * NB < 4 ? NB * NB : 4),
                   "publish_partial needs more LDS than the staged tiles");
-    publish_partial<NB, false, NB * NB, kSpThreads>(acc, s, reinterpret_cast<double *>(smem),
+    publish_partial<NB, true, NB * (NB + 1) / 2, kSpThreads>(acc, s, reinterpret_cast<double *>(smem),
                                                     glb(cd.parts) + static_cast<size_t>(local) * s * s);
 }
 
@@ -421,9 +423,9 @@ __global__ __launch_bounds__(kSpThreads, (NB > 2 ? 2 : 1)) void spmm_gram_vec_ke
     const int cell = (tid % TPC) * V, cls = tid / TPC;
     const VT zero = VT(T(0));
 
-    d4 acc[NB * NB];
+    d4 acc[NB * (NB + 1) / 2];  // upper blocks of P^T AP (symmetric)
 #pragma unroll
-    for (int q = 0; q < NB * NB; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < NB * (NB + 1) / 2; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
     const int64_t ntiles = ldw / kTileRows;
     for (int64_t tile = local; tile < ntiles; tile += wgs) {
         for (int half = 0; half < kTileRows / TR; ++half) {
@@ -489,12 +491,13 @@ __global__ __launch_bounds__(kSpThreads, (NB > 2 ? 2 : 1)) void spmm_gram_vec_ke
 #pragma unroll
                     for (int x = 0; x < NB; ++x)
 #pragma unroll
-                        for (int y = 0; y < NB; ++y) acc[x * NB + y] = mma64(u[x][t], v[y][t], acc[x * NB + y]);
+                        for (int y = x; y < NB; ++y)
+                            acc[ublock<NB>(x, y)] = mma64(u[x][t], v[y][t], acc[ublock<NB>(x, y)]);
             }
             __syncthreads();
         }
     }
-    publish_partial<NB, false, NB * NB, kSpThreads>(acc, s, reinterpret_cast<double *>(smem),
+    publish_partial<NB, true, NB * (NB + 1) / 2, kSpThreads>(acc, s, reinterpret_cast<double *>(smem),
                                                     glb(cd.parts) + static_cast<size_t>(local) * s * s);
 }
 
