@@ -31,13 +31,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
+# dense matrix-core peaks of MI355X, TFLOP/s
+MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 
 # HBM bytes per (working) launch of the default workload's kernels:
 # rocprofv3 FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads for
 # a plain device copy of known size (profiles/pmc_traffic_stack128x128x8.md).
-# Valid only for the kernels as profiled there and the default workload.
-TRAFFIC_BYTES = {"combine": 7235.9e6, "apply": 15216.0e6, "update_dqp": 130.3e6, "update_w": 74.6e6, "spmm": 75.7e6}
+# Valid only for the kernels as profiled there and the default workload
+# (the combination in its one-pass form).
+TRAFFIC_BYTES = {"combine": 14474.8e6, "apply": 15174.8e6, "update_dqp": 129.6e6, "update_w": 74.4e6, "spmm": 75.7e6}
 
 # one launch in this many of the dominant block-solve kernel carries events
 # in the timed region
@@ -238,11 +240,21 @@ def main():
         work = working.get(kind) or launches
         # achieved: the family's algorithmic bytes over its kernel time
         gbs = per_launch_bytes[kind] * work / (avg_ms * launches * 1e-3) / 1e9
-        traffic = TRAFFIC_BYTES.get(kind) if default_workload and not (fused and kind == "combine") else None
-        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kind,
-                "launches": launches, "working_launches": work, "timed_launches": timed,
-                "avg_us": round(avg_ms * 1e3, 2), "bytes_per_launch": int(per_launch_bytes[kind])}
+        # the combination's figure is for its one-pass (T and F) form
+        traffic = TRAFFIC_BYTES.get(kind) if default_workload and (kind != "combine" or fused) else None
+        out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kind,
+               "launches": launches, "working_launches": work, "timed_launches": timed,
+               "avg_us": round(avg_ms * 1e3, 2), "bytes_per_launch": int(per_launch_bytes[kind])}
+        if kind == "combine":
+            # the combination's matrix-core rate against the peak of its type
+            # (2 N s M flops per output field block; the one-pass form has two)
+            flops = 2.0 * n * s * m * (2 if fused else 1)
+            mt = "f64" if comb_compute == capi.F64 else ("f32" if comb_compute == capi.F32 else "bf16")
+            tf = flops / (avg_ms * 1e-3) / 1e12
+            out["mfma"] = {"dtype": mt, "tflops": round(tf, 2), "peak_tflops": MFMA_PEAK_TFLOPS[mt],
+                           "frac": round(tf / MFMA_PEAK_TFLOPS[mt], 4)}
+        return out
 
     roofline = roof(dom) if dom in per_launch_bytes else None
     value = m / (ms_per_step * 1e-3)
