@@ -113,8 +113,9 @@ def only_kernel(args, w, G, X, C, T, F, t_dtype, comb_compute, apply_compute):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(the per-chip and per-field work shards without communication, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: this library runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(chips and fields would shard across GPUs without communication; only the one-GPU path is built)",
+              file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
