@@ -283,6 +283,7 @@ def main():
         "solve": {"iters_per_step": it_total / args.steps, "refinements_per_step": ref_total / args.steps,
                   "max_rel_res": max(i["max_rel_res"] for i in infos[-args.steps:])},
     }
+    res["stage_errors"] = stage_errors(G, X, C, T, F)
     if args.cg_columns > 0:
         res["per_sample_cg"] = per_sample_cg(G, B, C, w, args.cg_columns, value)
         res["ablations"] = ablations(G, B, C, X, w, args.cg_columns, value, compute, wview, outputs,
@@ -409,6 +410,39 @@ def capi_bytes_combine_apply(capi, G, s):
     out = ctypes.c_size_t()
     capi._check(capi.load_library().bko_combine_apply_workspace_bytes(G.handle, s, ctypes.byref(out)))
     return out.value
+
+
+def stage_errors(G, X, C, T, F, nsample=64):
+    """Error of each output stage of the last step, on 64 evenly spaced
+    fields (max over them of the relative 2-norm error):
+      T: against X C formed in FP64 from the solve's X (rounding X and C to
+        BF16 alone gives about 2^-8 times T_cancellation);
+      F (stage-local, the pair's consistency): against A T of the T actually
+        written, in FP64;
+      F against the FP64 pipeline, A (X C): for low-precision fields this is
+        large where A cancels (|A||T| >> |A T|), which is why pairs are judged
+        stage-locally."""
+    import torch
+
+    from paper_2510_23221_amd import capi
+
+    m = C.shape[0]
+    idx = torch.linspace(0, m - 1, min(nsample, m), device=C.device).round().long().unique()
+    T64 = C[idx].to(torch.float64) @ X
+    Tw = T[idx].to(torch.float64)
+    Fw = F[idx].to(torch.float64)
+    F_stage = capi.apply_operator(G, Tw.contiguous())
+    F64 = capi.apply_operator(G, T64.contiguous())
+
+    def rel(a, b):
+        return float(((a - b).norm(dim=1) / b.norm(dim=1).clamp_min(1e-300)).max())
+
+    # cancellation in the sums: the error bound of a rounded input or product
+    # scales with || |C| |X| || / || X C ||
+    canc = float(((C[idx].to(torch.float64).abs() @ X.abs()).norm(dim=1) / T64.norm(dim=1).clamp_min(1e-300)).max())
+    return {"fields": int(idx.numel()), "T_vs_XC": rel(Tw, T64), "T_cancellation": round(canc, 2),
+            "F_vs_AT_stage": rel(Fw, F_stage), "F_vs_fp64_pipeline": rel(Fw, F64),
+            "field_dtype": str(T.dtype).replace("torch.", "")}
 
 
 def per_sample_cg(G, B, C, w, cols, value):
