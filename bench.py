@@ -284,6 +284,11 @@ def main():
                   "max_rel_res": max(i["max_rel_res"] for i in infos[-args.steps:])},
     }
     res["stage_errors"] = stage_errors(G, X, C, T, F)
+    if fused:
+        # the operator action on its own (the stencil over the M fields), for
+        # the stencil's HBM rate; the step itself forms F in the one pass
+        res["stencil"] = stencil_rate(G, T, F, t_dtype, apply_compute, per_launch_bytes["apply"],
+                                      TRAFFIC_BYTES.get("apply") if default_workload else None)
     if args.cg_columns > 0:
         res["per_sample_cg"] = per_sample_cg(G, B, C, w, args.cg_columns, value)
         res["ablations"] = ablations(G, B, C, X, w, args.cg_columns, value, compute, wview, outputs,
@@ -443,6 +448,30 @@ def stage_errors(G, X, C, T, F, nsample=64):
     return {"fields": int(idx.numel()), "T_vs_XC": rel(Tw, T64), "T_cancellation": round(canc, 2),
             "F_vs_AT_stage": rel(Fw, F_stage), "F_vs_fp64_pipeline": rel(Fw, F64),
             "field_dtype": str(T.dtype).replace("torch.", "")}
+
+
+def stencil_rate(G, T, F, t_dtype, apply_compute, nbytes, traffic, reps=5):
+    """F = A T over all fields, timed alone with events on the launch stream
+    (two warm-up launches, then `reps`): algorithmic bytes per launch over the
+    average launch time."""
+    import torch
+
+    from paper_2510_23221_amd import capi
+
+    for _ in range(2):
+        capi.apply_operator(G, T, out_dtype=t_dtype, compute=apply_compute, F=F)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        capi.apply_operator(G, T, out_dtype=t_dtype, compute=apply_compute, F=F)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "apply", "avg_us": round(ms * 1e3, 2),
+            "bytes_per_launch": int(nbytes), "launches": reps}
 
 
 def per_sample_cg(G, B, C, w, cols, value):
