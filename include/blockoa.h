@@ -415,6 +415,18 @@ bko_status bko_unet_set_params(bko_net net, void *state, const float *params, vo
 bko_status bko_unet_forward(bko_net net, void *state, void *work, const float *x, int n, float *y, void *stream);
 
 /*
+ * The same network for inference with every convolution on the BF16 matrix
+ * cores: each convolution's input is rounded to BF16 (nearest even) before
+ * the products (the parameters are the BF16 copy, as in bko_unet_forward),
+ * FP32 accumulation, bias and ReLU.  One BF16 rounding per layer (relative
+ * 2^-9 each) makes it differ from bko_unet_forward by about 1e-2 of ||y||
+ * over the fifteen layers; used for the learned start's initial guess, which
+ * the block solve then refines.  Same arguments and errors as
+ * bko_unet_forward.  Asynchronous.
+ */
+bko_status bko_unet_infer(bko_net net, void *state, void *work, const float *x, int n, float *y, void *stream);
+
+/*
  * Forward pass, loss = mean over all n Cout H W outputs of (y - target)^2,
  * and its gradient with respect to every parameter into the state's gradient
  * block.  loss (host, may be NULL) receives the loss and then the call

@@ -149,14 +149,18 @@ def param_count(layers):
     return sum(co * ci * k * k + co for ci, co, k, _ in layers)
 
 
-def unet_forward(params, x, layers):
-    """Forward pass; returns (output, cache of every layer's input and output)."""
+def unet_forward(params, x, layers, round_input=None):
+    """Forward pass; returns (output, cache of every layer's input and output).
+    round_input, if given, maps each convolution's input (after pooling,
+    upsampling and concatenation) to the values the convolution multiplies:
+    the inference variant that feeds the matrix cores BF16 passes a rounding
+    to BF16 here."""
     wb = unpack(np.asarray(params, dtype=np.float64), layers)
     cache = []
 
     def conv(idx, a):
         w, b = wb[idx]
-        y = conv2d(a, w, b)
+        y = conv2d(a if round_input is None else round_input(a), w, b)
         if layers[idx][3]:
             y = relu(y)
         cache.append((idx, a, y))

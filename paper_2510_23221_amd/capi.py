@@ -46,7 +46,7 @@ EXPORTED = ("bko_version", "bko_last_error", "bko_operator_bytes", "bko_assemble
             "bko_cg_solve", "bko_batch_plan_create", "bko_batch_plan_destroy", "bko_batch_workspace_bytes",
             "bko_batch_tune", "bko_batch_solve", "bko_nn_conv2d", "bko_nn_wgrad_work_floats",
             "bko_nn_conv2d_wgrad", "bko_unet_create", "bko_unet_destroy", "bko_unet_sizes", "bko_unet_set_params",
-            "bko_unet_forward", "bko_unet_gradient", "bko_unet_adam_step", "bko_lstart_pack",
+            "bko_unet_forward", "bko_unet_infer", "bko_unet_gradient", "bko_unet_adam_step", "bko_lstart_pack",
             "bko_lstart_pack_target", "bko_lstart_unpack", "bko_jacobi_smooth", "bko_operator_set_precond",
             "bko_operator_get_precond", "bko_timing_set_stride", "bko_combine_apply_workspace_bytes",
             "bko_combine_apply", "bko_combine_noisy", "bko_noise_fill", "bko_normalize_weights",
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bko_unet_sizes": (i32, [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(sz), ctypes.POINTER(sz)]),
         "bko_unet_set_params": (i32, [vp, vp, vp, vp]),
         "bko_unet_forward": (i32, [vp, vp, vp, vp, i32, vp, vp]),
+        "bko_unet_infer": (i32, [vp, vp, vp, vp, i32, vp, vp]),
         "bko_unet_gradient": (i32, [vp, vp, vp, vp, vp, i32, ctypes.POINTER(ctypes.c_float), vp]),
         "bko_unet_adam_step": (i32, [vp, vp, ctypes.c_float, vp]),
         "bko_lstart_pack": (i32, [i32, i32, i32, vp, i32, i32, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
@@ -484,6 +485,16 @@ class UNet:
         _check(load_library().bko_unet_forward(self.handle, ctypes.c_void_p(self._state_ptr),
                                                ctypes.c_void_p(self._work_ptr), _f32(x, "x"), n, _f32(y, "y"),
                                                _stream()))
+        return y
+
+    def infer(self, x: torch.Tensor, y: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """The forward pass with the convolutions on the BF16 matrix cores."""
+        n = x.shape[0]
+        if y is None:
+            y = torch.empty((n, self.cout, self.height, self.width), dtype=torch.float32, device=x.device)
+        _check(load_library().bko_unet_infer(self.handle, ctypes.c_void_p(self._state_ptr),
+                                             ctypes.c_void_p(self._work_ptr), _f32(x, "x"), n, _f32(y, "y"),
+                                             _stream()))
         return y
 
     def gradient(self, x: torch.Tensor, target: torch.Tensor, want_loss: bool = True):

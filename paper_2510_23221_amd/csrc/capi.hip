@@ -883,6 +883,18 @@ bko_status bko_unet_forward(bko_net net, void *state, void *work, const float *x
     BKO_GUARD_END
 }
 
+bko_status bko_unet_infer(bko_net net, void *state, void *work, const float *x, int n, float *y, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(net && state && work && x && y, "NULL argument");
+    const UNet &u = *reinterpret_cast<UNet *>(net);
+    BKO_CHECK(n >= 1 && n <= u.batch, "n = %d outside [1, %d]", n, u.batch);
+    BKO_CHECK(reinterpret_cast<uintptr_t>(state) % 256 == 0 && reinterpret_cast<uintptr_t>(work) % 256 == 0,
+              "state and work must be 256-byte aligned");
+    return u.forward(state, work, x, n, y, static_cast<hipStream_t>(stream), true);
+    BKO_GUARD_END
+}
+
 bko_status bko_unet_gradient(bko_net net, void *state, void *work, const float *x, const float *target, int n,
                              float *loss, void *stream)
 {

@@ -83,6 +83,9 @@ bko_status batch_solve(BatchPlan &p, const double *const *B, const int64_t *ldb,
 // ---- learned start (convolutional encoder-decoder)
 bko_status nn_conv(const float *A, int Ca, const float *B, int Cb, int mode, int N, int H, int W, int Co, int K,
                    const uint16_t *wgt, int transposed, const float *bias, float *out, int relu, hipStream_t st);
+// the forward convolution on the BF16 matrix cores (BF16 inputs, FP32 accumulation)
+bko_status nn_conv_mfma(const float *A, int Ca, const float *B, int Cb, int mode, int N, int H, int W, int Co, int K,
+                        const uint16_t *wgt, const float *bias, float *out, int relu, hipStream_t st);
 size_t nn_wgrad_part_floats(int N, int H, int W, int Ci, int Co, int K);
 bko_status nn_wgrad(const float *A, int Ca, const float *B, int Cb, int mode, const float *g, int N, int H, int W,
                     int Co, int K, float *part, float *gw, float *gb, hipStream_t st);
@@ -124,7 +127,9 @@ struct UNet {
     size_t state_bytes() const;
     State state(void *p) const;
     bko_status set_params(void *state, const float *params, hipStream_t st);
-    bko_status forward(void *state, void *work, const float *x, int n, float *y, hipStream_t st) const;
+    // mfma: the convolutions on the BF16 matrix cores (inference)
+    bko_status forward(void *state, void *work, const float *x, int n, float *y, hipStream_t st,
+                       bool mfma = false) const;
     bko_status gradient(void *state, void *work, const float *x, const float *target, int n, float *loss,
                         hipStream_t st) const;
     bko_status adam(void *state, float lr, hipStream_t st);

@@ -166,6 +166,108 @@ __global__ __launch_bounds__(kNT) void conv_kernel(ConvIn in, int N, int H, int 
     }
 }
 
+// The forward convolution on the BF16 matrix cores, for inference: the
+// same output tiles as conv_kernel (kTH x kTW pixels x kCO output channels
+// per workgroup), as an implicit GEMM over k = (tap, input channel).  Each
+// stage brings kMCI input channels into LDS channel-last in BF16 (inputs
+// rounded to nearest even, the weights are BF16 already), so that a lane's
+// eight k values of one 32-deep matrix-core step (one tap, eight
+// consecutive channels) are one 16-byte LDS read; taps are padded to an even
+// count with zero weights.  Wave w owns tile rows 4w .. 4w + 3 (eight
+// 16-pixel blocks) and both 16-channel blocks; FP32 accumulation, bias and
+// ReLU in the epilogue.
+constexpr int kMCI = 16;  // input channels per LDS stage of the matrix-core convolution
+
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef __bf16 mbf8 __attribute__((ext_vector_type(8)));
+
+template <int K>
+__global__ __launch_bounds__(kNT) void conv_mfma_kernel(ConvIn in, int N, int H, int W, int Ci, int Co,
+                                                        const uint16_t *__restrict__ wgt,
+                                                        const float *__restrict__ bias, float *__restrict__ out,
+                                                        int relu)
+{
+    constexpr int R = K / 2;
+    constexpr int IH = kTH + 2 * R, IW = kTW + 2 * R;
+    constexpr int KK = K * K;
+    constexpr int TP = (KK + 1) / 2 * 2;  // taps padded to pairs: a 32-deep step is two taps x 16 channels
+    static_assert(kTH == 16 && kTW == 32 && kCO == 32 && kNT == 256, "tile mapping of the matrix-core convolution");
+    __shared__ __align__(16) uint16_t sIn[IH * IW * kMCI];  // [row][col][channel]
+    __shared__ __align__(16) uint16_t sW[kCO * TP * kMCI];  // [out channel][tap][channel]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int coTiles = (Co + kCO - 1) / kCO;
+    const int n = blockIdx.z / coTiles, co0 = (blockIdx.z % coTiles) * kCO;
+    const int y0 = blockIdx.y * kTH, x0 = blockIdx.x * kTW;
+    mf4 acc[8][2];
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+        for (int ob = 0; ob < 2; ++ob) acc[b][ob] = mf4{0.f, 0.f, 0.f, 0.f};
+
+    for (int ci0 = 0; ci0 < Ci; ci0 += kMCI) {
+        // a thread takes eight channels of one pixel (each read coalesced
+        // across the threads of a row) and writes them as one 16-byte vector
+        for (int e = tid; e < 2 * IH * IW; e += kNT) {
+            const int g = e / (IH * IW), r = (e / IW) % IH, q = e % IW;
+            uint32_t pk[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int c0 = ci0 + 8 * g + 2 * h;
+                const float v0 = c0 < Ci ? read_in(in, n, c0, y0 + r - R, x0 + q - R, H, W) : 0.0f;
+                const float v1 = c0 + 1 < Ci ? read_in(in, n, c0 + 1, y0 + r - R, x0 + q - R, H, W) : 0.0f;
+                pk[h] = static_cast<uint32_t>(f2bf16(v0)) | (static_cast<uint32_t>(f2bf16(v1)) << 16);
+            }
+            *reinterpret_cast<uint4 *>(&sIn[(r * IW + q) * kMCI + 8 * g]) = uint4{pk[0], pk[1], pk[2], pk[3]};
+        }
+        for (int e = tid; e < kCO * TP * kMCI; e += kNT) {
+            const int o = e / (TP * kMCI), t = (e / kMCI) % TP, c = e % kMCI;
+            const int oo = co0 + o, i = ci0 + c;
+            sW[e] = (oo < Co && i < Ci && t < KK) ? wgt[(static_cast<int64_t>(oo) * Ci + i) * KK + t] : uint16_t(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < TP / 2; ++j) {
+            const int t = 2 * j + (lg >> 1);  // this lane group's tap and channels
+            const int cb = 8 * (lg & 1);
+            const int p = t < KK ? t / K : 0, q = t < KK ? t % K : 0;  // a padding tap reads in bounds (zero weight)
+            mbf8 b[2];
+#pragma unroll
+            for (int ob = 0; ob < 2; ++ob)
+                b[ob] = *reinterpret_cast<const mbf8 *>(&sW[((ob * 16 + li) * TP + t) * kMCI + cb]);
+#pragma unroll
+            for (int pb = 0; pb < 8; ++pb) {
+                const int row = 4 * wave + (pb >> 1), col = 16 * (pb & 1) + li;
+                const mbf8 a = *reinterpret_cast<const mbf8 *>(&sIn[((row + p) * IW + col + q) * kMCI + cb]);
+#pragma unroll
+                for (int ob = 0; ob < 2; ++ob) acc[pb][ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[ob], acc[pb][ob], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // result register r of lane (li, lg): pixel 4 lg + r of the block, output channel li of the channel block
+#pragma unroll
+    for (int pb = 0; pb < 8; ++pb) {
+        const int y = y0 + 4 * wave + (pb >> 1);
+        if (y >= H) continue;
+#pragma unroll
+        for (int ob = 0; ob < 2; ++ob) {
+            const int oo = co0 + ob * 16 + li;
+            if (oo >= Co) continue;
+            const float bv = bias ? bias[oo] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int x = x0 + 16 * (pb & 1) + 4 * lg + r;
+                if (x < W) {
+                    float v = acc[pb][ob][r] + bv;
+                    if (relu) v = fmaxf(v, 0.0f);
+                    out[((static_cast<int64_t>(n) * Co + oo) * H + y) * W + x] = v;
+                }
+            }
+        }
+    }
+}
+
 // Filter and bias gradient partials of one split:
 //   part[split][o][i][p][q] = sum over the split's pixels of g[n,o,y,x] in[n,i,y+p-r,x+q-r]
 //   bpart[split][o]         = sum over the split's pixels of g[n,o,y,x]
@@ -366,6 +468,21 @@ bko_status nn_conv(const float *A, int Ca, const float *B, int Cb, int mode, int
         hipLaunchKernelGGL(conv_kernel<3>, grid, dim3(kNT), 0, st, in, N, H, W, Ci, Co, wgt, transposed, bias, out, relu);
     else
         hipLaunchKernelGGL(conv_kernel<1>, grid, dim3(kNT), 0, st, in, N, H, W, Ci, Co, wgt, transposed, bias, out, relu);
+    BKO_HIP(hipGetLastError());
+    return BKO_OK;
+}
+
+bko_status nn_conv_mfma(const float *A, int Ca, const float *B, int Cb, int mode, int N, int H, int W, int Co, int K,
+                        const uint16_t *wgt, const float *bias, float *out, int relu, hipStream_t st)
+{
+    const ConvIn in{A, B, Ca, Cb, mode};
+    const int Ci = Ca + Cb;
+    const dim3 grid(static_cast<unsigned>((W + kTW - 1) / kTW), static_cast<unsigned>((H + kTH - 1) / kTH),
+                    static_cast<unsigned>(N * ((Co + kCO - 1) / kCO)));
+    if (K == 3)
+        hipLaunchKernelGGL(conv_mfma_kernel<3>, grid, dim3(kNT), 0, st, in, N, H, W, Ci, Co, wgt, bias, out, relu);
+    else
+        hipLaunchKernelGGL(conv_mfma_kernel<1>, grid, dim3(kNT), 0, st, in, N, H, W, Ci, Co, wgt, bias, out, relu);
     BKO_HIP(hipGetLastError());
     return BKO_OK;
 }
@@ -624,7 +741,7 @@ UNet::State UNet::state(void *p) const
     return s;
 }
 
-bko_status UNet::forward(void *state_p, void *work, const float *x, int n, float *y, hipStream_t st) const
+bko_status UNet::forward(void *state_p, void *work, const float *x, int n, float *y, hipStream_t st, bool mfma) const
 {
     const State S = state(state_p);
     float *w = static_cast<float *>(work);
@@ -632,6 +749,9 @@ bko_status UNet::forward(void *state_p, void *work, const float *x, int n, float
     bko_status rc;
     auto conv = [&](int j, const float *A, int Ca, const float *B, int Cb, int mode, float *out) {
         const Layer &l = L[j];
+        if (mfma)
+            return nn_conv_mfma(A, Ca, B, Cb, mode, n, l.h, l.w, l.co, l.k, S.pb + l.woff, S.params + l.boff, out,
+                                l.relu, st);
         return nn_conv(A, Ca, B, Cb, mode, n, l.h, l.w, l.co, l.k, S.pb + l.woff, 0, S.params + l.boff, out, l.relu, st);
     };
     const int w1 = L[1].co, w2 = L[3].co, w3 = L[5].co, w4 = L[7].co;

@@ -145,7 +145,7 @@ def predict_x0(net: capi.UNet, norm: Normalizer, chip: synth.Chip, k: torch.Tens
     for j0 in range(0, s, net.max_batch):
         j1 = min(s, j0 + net.max_batch)
         x, scale = _pack(norm, chip, k, B[j0:j1])
-        y = net.forward(x)
+        y = net.infer(x)
         capi.lstart_unpack(y, scale, norm.gain, X0[j0:j1])
     if smooth > 0:
         capi.jacobi_smooth(G, B, X0, smooth, omega)

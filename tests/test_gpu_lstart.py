@@ -143,6 +143,26 @@ def test_unet_forward_and_gradient_match_oracle(dev):
     assert rel_fro(_np(net.grads), g_ref) <= 1e-3
 
 
+def test_unet_infer_matches_oracle(dev):
+    """The inference forward (convolutions on the BF16 matrix cores): against
+    the oracle network with every convolution input rounded to BF16 it
+    differs only by FP32 accumulation and the order of the sums; against the
+    unrounded network by the fifteen input roundings (2^-9 each, 15 * 2^-9 <
+    3e-2).  Ragged tiles in every direction: 24 x 40 pixels, 3..16
+    channels."""
+    rng = np.random.default_rng(410)
+    layers, p, q = _tiny_net(rng)
+    net = capi.UNet(3, 2, 4, 24, 40, 3)
+    net.set_params(torch.as_tensor(p, dtype=torch.float32, device="cuda"))
+    x = rng.standard_normal((3, 3, 24, 40)).astype(np.float32).astype(np.float64)
+    y = _np(net.infer(_dev(x)))
+    y_rounded, _ = cr.unet_forward(q, x, layers, round_input=_bf16)
+    y_ref, _ = cr.unet_forward(q, x, layers)
+    assert rel_fro(y, y_rounded) <= 1e-3, rel_fro(y, y_rounded)
+    assert rel_fro(y, y_ref) <= 3e-2, rel_fro(y, y_ref)
+    assert rel_fro(y_rounded, y_ref) > 0.0  # the rounding is there to be matched
+
+
 def test_adam_step_matches_oracle(dev):
     rng = np.random.default_rng(500)
     layers, p, q = _tiny_net(rng)
