@@ -18,6 +18,7 @@
 // a contiguous range of work.  The damped Jacobi sweep that smooths an
 // initial guess is the per-cell form with an update.
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -159,7 +160,11 @@ __global__ __launch_bounds__(kThreads) void stencil_tile_kernel(
     const int nvx = nx / VX;  // vectors per row
     const int nv = rows * nvx;
     extern __shared__ __align__(16) unsigned char smem[];
-    Acc *buf0 = reinterpret_cast<Acc *>(smem);
+    // the LDS plane holds the narrower of the field's and the accumulator's
+    // type (exact either way: a field value widened, or the value used), and
+    // is written and read in whole VX-cell vectors
+    using Ls = std::conditional_t<(sizeof(Tin) < sizeof(Acc)), Tin, Acc>;
+    Ls *buf0 = reinterpret_cast<Ls *>(smem);
     const int bufsz = (TY + 2) * nx;
     const Tin *xf = X + field * ldx;
     Tout *yf = Y + field * ldy;
@@ -213,25 +218,27 @@ __global__ __launch_bounds__(kThreads) void stencil_tile_kernel(
             }
         }
         // current plane of the tile into LDS, with the halo rows (zero outside the grid)
-        Acc *buf = buf0 + (l & 1) * bufsz;
+        Ls *buf = buf0 + (l & 1) * bufsz;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (vok[r]) {
+                Vec<Ls, VX> v;
 #pragma unroll
-                for (int e = 0; e < VX; ++e) buf[(vrow[r] + 1) * nx + vx0[r] + e] = cur[r][e];
+                for (int e = 0; e < VX; ++e) v.v[e] = store_from<Ls, Acc>(cur[r][e]);
+                vstore<Ls, VX>(buf + (vrow[r] + 1) * nx + vx0[r], v);
             }
         }
         if (hok) {
-            Acc hv[VX];
-#pragma unroll
-            for (int e = 0; e < VX; ++e) hv[e] = Acc(0);
+            Vec<Ls, VX> hv;
             if (hin) {
                 const Vec<Tin, VX> v = vload<Tin, VX>(xf + pl + static_cast<int64_t>(hy) * nx + hx0);
 #pragma unroll
-                for (int e = 0; e < VX; ++e) hv[e] = load_as<Acc>(&v.v[e]);
-            }
+                for (int e = 0; e < VX; ++e) hv.v[e] = store_from<Ls, Acc>(load_as<Acc>(&v.v[e]));
+            } else {
 #pragma unroll
-            for (int e = 0; e < VX; ++e) buf[hlrow * nx + hx0 + e] = hv[e];
+                for (int e = 0; e < VX; ++e) hv.v[e] = store_from<Ls, Acc>(Acc(0));
+            }
+            vstore<Ls, VX>(buf + hlrow * nx + hx0, hv);
         }
         __syncthreads();
 #pragma unroll
@@ -253,17 +260,18 @@ __global__ __launch_bounds__(kThreads) void stencil_tile_kernel(
                 for (int e = 0; e < VX; ++e) cym[e] = Acc(0);
             }
             const Acc cxm0 = vx0[r] > 0 ? static_cast<Acc>(wx[a - 1]) : Acc(0);
-            const Acc *brow = buf + (vrow[r] + 1) * nx + vx0[r];
-            const Acc left = vx0[r] > 0 ? brow[-1] : Acc(0);
-            const Acc right = vx0[r] + VX < nx ? brow[VX] : Acc(0);
+            const Ls *brow = buf + (vrow[r] + 1) * nx + vx0[r];
+            const Acc left = vx0[r] > 0 ? load_as<Acc>(brow - 1) : Acc(0);
+            const Acc right = vx0[r] + VX < nx ? load_as<Acc>(brow + VX) : Acc(0);
+            const Vec<Ls, VX> upv = vload<Ls, VX>(brow - nx), dnv = vload<Ls, VX>(brow + nx);
             Vec<Tout, VX> out;
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
                 const Acc xm = e > 0 ? cur[r][e - 1] : left;
                 const Acc xp = e < VX - 1 ? cur[r][e + 1] : right;
                 const Acc cxm = e > 0 ? static_cast<Acc>(cx.v[e - 1]) : cxm0;
-                const Acc up = brow[e - nx];
-                const Acc dn = brow[e + nx];
+                const Acc up = load_as<Acc>(&upv.v[e]);
+                const Acc dn = load_as<Acc>(&dnv.v[e]);
                 const Acc nb = cxm * xm + static_cast<Acc>(cx.v[e]) * xp + cym[e] * up +
                                static_cast<Acc>(cy.v[e]) * dn + wzm[r][e] * prev[r][e] +
                                static_cast<Acc>(cz.v[e]) * nxt[r][e];
@@ -314,7 +322,7 @@ bko_status run(const Operator &op, const Tc *diag, const Tc *wx, const Tc *wy, c
             const int ntiles = (op.ny + ty - 1) / ty;
             const uint64_t nb = static_cast<uint64_t>(ntiles) * m;
             if (nb <= 0x7fffffffu) {
-                const size_t lds = 2 * sizeof(Acc) * static_cast<size_t>(ty + 2) * op.nx;
+                const size_t lds = 2 * std::min(sizeof(Acc), sizeof(Tin)) * static_cast<size_t>(ty + 2) * op.nx;
                 hipLaunchKernelGGL((stencil_tile_kernel<Tin, Tout, Tc, Acc, kResidual>), dim3(static_cast<uint32_t>(nb)),
                                    dim3(kThreads), lds, stream, diag, wx, wy, wz, op.nx, op.ny, op.nz,
                                    static_cast<const Tin *>(X), ldx, static_cast<Tout *>(Y), ldy, Bres, ldb, ty, ntiles,
