@@ -39,7 +39,7 @@ MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 # a plain device copy of known size (profiles/pmc_traffic_stack128x128x8.md).
 # Valid only for the kernels as profiled there and the default workload
 # (the combination in its one-pass form).
-TRAFFIC_BYTES = {"combine": 14474.8e6, "apply": 15174.8e6, "update_dqp": 129.6e6, "update_w": 74.4e6, "spmm": 75.7e6}
+TRAFFIC_BYTES = {"combine": 14474.8e6, "apply": 15205.8e6, "update_dqp": 129.6e6, "update_w": 74.4e6, "spmm": 75.7e6}
 
 # one launch in this many of the dominant block-solve kernel carries events
 # in the timed region
