@@ -12,12 +12,17 @@ M = 5000 (the configuration the pairs/s metric is quoted on).
 
 Prints one JSON line.  Extra keys: ``roofline`` (the dominant kernel,
 measured with HIP events around its launches on the launch stream),
-``stencil`` (the operator-action kernel's own roofline), ``census_*`` (one
-instrumented step: per-family milliseconds and launches), ``solve``
-(iterations, refinements, residual), ``per_sample_cg`` (the paper's direct
-method on the same GPU: one FP64 CG per power map, timed on a subset of
-columns and reported per pair), ``cpu_baseline`` (the CPU oracle on the
-host cores).
+``output`` / ``stencil`` (the output kernels' own rooflines), ``copy`` (the
+library's 16-byte vector copy over a field-sized buffer: the achievable HBM
+rate every fraction is also quoted against), ``census_*`` (one instrumented
+step: per-family milliseconds and launches), ``solve`` (iterations,
+refinements, residual), ``stage_errors``, ``per_sample_cg`` (the paper's
+direct method on the same GPU: one FP64 CG per power map, timed on a subset
+of columns and reported per pair), ``ablations`` (Table 7's modules removed
+on the same GPU), ``sub_records`` (the other workloads at a few steps each:
+plain FP64 BlocKOA on the same chip, the 256 x 256 x 16 stack with BF16
+fields, the batch of 64 uneven chips, the learned start against the zero
+start) and ``cpu_baseline`` (the CPU oracle on the host cores).
 """
 from __future__ import annotations
 
@@ -36,10 +41,9 @@ MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 
 # HBM bytes per (working) launch of the default workload's kernels:
 # rocprofv3 FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads for
-# a plain device copy of known size (profiles/pmc_traffic_stack128x128x8.md).
-# Valid only for the kernels as profiled there and the default workload
-# (the combination in its one-pass form).
-TRAFFIC_BYTES = {"combine": 14474.8e6, "apply": 15205.8e6, "update_dqp": 129.6e6, "update_w": 74.4e6, "spmm": 75.7e6}
+# the library's copy kernel over a buffer of known size.  Only kernels whose
+# code has not changed since the counters were taken carry a figure.
+TRAFFIC_BYTES = {}
 
 # one launch in this many of the dominant block-solve kernel carries events
 # in the timed region
@@ -65,9 +69,13 @@ def parse():
     ap.add_argument("--noise", choices=["none", "uniform", "gaussian"], default="none",
                     help="noise term of Eq. (5) added to every field (then the outputs take two passes)")
     ap.add_argument("--noise-amp", type=float, default=0.01, help="noise half-width (uniform) or std (gaussian), K")
-    ap.add_argument("--separate-output", action="store_true",
-                    help="combine and operator action as two passes even when T is FP64 (default: one pass, "
-                         "F = (A X) C)")
+    ap.add_argument("--outputs", choices=["two-pass", "one-pass"], default="two-pass",
+                    help="FP64 fields: combination then operator action of the written T (default), or one pass "
+                         "over the fields for T and F")
+    ap.add_argument("--compute", choices=["auto", "f64", "f32"], default="auto",
+                    help="block-iteration arithmetic (auto: the workload's scheme)")
+    ap.add_argument("--no-sub-records", action="store_true",
+                    help="headline workload only (skip the FP64, large-stack, batch and learned-start records)")
     ap.add_argument("--only", choices=["apply", "combine", "copy"], default=None,
                     help="run one kernel family at the workload's shape (for counter profiles)")
     return ap.parse_args()
@@ -75,8 +83,8 @@ def parse():
 
 def only_kernel(args, w, G, X, C, T, F, t_dtype, comb_compute, apply_compute):
     """Launch one kernel family `steps` times at the workload shape and print
-    its event-timed average.  `copy` is a plain device copy of T into F (the
-    calibration kernel for HBM byte counters)."""
+    its event-timed average.  `copy` is the library's 16-byte vector copy of
+    T into F (the calibration kernel for HBM byte counters)."""
     import torch
 
     from paper_2510_23221_amd import capi
@@ -90,7 +98,7 @@ def only_kernel(args, w, G, X, C, T, F, t_dtype, comb_compute, apply_compute):
         elif args.only == "combine":
             capi.combine(X, C, out_dtype=t_dtype, compute=comb_compute, T=T)
         else:
-            F.copy_(T)
+            capi.copy(F, T)
 
     T.normal_()
     X.normal_()
@@ -110,6 +118,30 @@ def only_kernel(args, w, G, X, C, T, F, t_dtype, comb_compute, apply_compute):
           flush=True)
 
 
+def copy_rate(dst, src, reps=5):
+    """The library's 16-byte vector copy of a field-sized buffer, timed with
+    events on the launch stream: bytes read + written per launch over the
+    average launch time (the achievable HBM rate)."""
+    import torch
+
+    from paper_2510_23221_amd import capi
+
+    for _ in range(2):
+        capi.copy(dst, src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        capi.copy(dst, src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 2 * src.numel() * src.element_size()
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes_per_launch": int(nbytes), "avg_us": round(ms * 1e3, 2), "kernel": "copy16 (library)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -117,20 +149,53 @@ def main():
               "(chips and fields would shard across GPUs without communication; only the one-GPU path is built)",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
+    if args.workload == "batched":
+        print(json.dumps(bench_batched(args, args.steps, args.warmup)), flush=True)
+        return
+    if args.workload == "learned":
+        print(json.dumps(bench_learned(args)), flush=True)
+        return
+    res, w = bench_single(args, args.config, args.steps, args.warmup, headline=True)
+    if res is None:
+        return
+    if not args.no_sub_records and args.config == 1 and args.m is None:
+        sub = {}
+        few = max(1, min(args.steps, 3))
+        sub["fp64_blockoa"], _ = bench_single(args, 1, few, 1, compute_override="f64")
+        note("fp64 BlocKOA done")
+        sub["large_bf16"], _ = bench_single(args, 3, 2, 1)
+        note("256x256x16 BF16 stack done")
+        sub["batch"] = bench_batched(args, 2, 1)
+        note("64-chip batch done")
+        sub["learned"] = bench_learned(args)
+        note("learned start done")
+        res["sub_records"] = sub
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(w, "jacobi" if args.precond == "jacobi" else "none")
+    print(json.dumps(res), flush=True)
+
+
+def note(msg):
+    """Progress on stderr (the JSON line stays the only stdout line)."""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
+def bench_single(args, config, steps, warmup, headline=False, compute_override=None):
+    """One chip of a single-chip workload: `warmup` untimed steps, one
+    instrumented census step, then `steps` timed steps.  Returns the record
+    (and the workload)."""
     import torch
 
     from paper_2510_23221_amd import capi, synth
 
     dev = torch.device("cuda:0")
-    if args.workload == "batched":
-        return bench_batched(args)
-    if args.workload == "learned":
-        return bench_learned(args)
-    w = synth.workload(args.config, m=args.m)
+    w = synth.workload(config, m=args.m if headline else None)
     chip = w.chips[0]
     s, m, n = w.s, w.m, chip.n
     mixed = w.scheme.startswith("mixed")
+    ov = compute_override or (args.compute if headline else "auto")
+    if ov != "auto":
+        mixed = ov == "f32"
     compute = capi.F32 if mixed else capi.F64
     t_dtype = torch.bfloat16 if w.scheme == "mixed_bf16" else torch.float64
     comb_compute = capi.BF16 if w.scheme == "mixed_bf16" else capi.F64
@@ -146,17 +211,20 @@ def main():
     wbytes = capi.workspace_bytes(G, s, compute)
     work = torch.empty(wbytes + 256, dtype=torch.uint8, device=dev)
     wview = work[(-work.data_ptr()) % 256:]
-    if args.only:
+    if headline and args.only:
         only_kernel(args, w, G, X, C, T, F, t_dtype, comb_compute, apply_compute)
-        return
+        return None, w
 
     infos = []
-    # one pass over the fields for both outputs when T and F are FP64 (pairs
-    # stay consistent to FP64 rounding); the BF16 scheme keeps two passes
     noise_kind = {"none": capi.NOISE_NONE, "uniform": capi.NOISE_UNIFORM, "gaussian": capi.NOISE_GAUSSIAN}[args.noise]
+    if not headline:
+        noise_kind = capi.NOISE_NONE
     if noise_kind != capi.NOISE_NONE and t_dtype != torch.float64:
         raise SystemExit("bench.py: --noise needs FP64 fields")
-    fused = t_dtype == torch.float64 and not args.separate_output and noise_kind == capi.NOISE_NONE
+    # one pass over the fields for both outputs only when asked for (FP64
+    # fields, no noise); otherwise the combination, then the operator action
+    # of the T actually written
+    fused = t_dtype == torch.float64 and args.outputs == "one-pass" and noise_kind == capi.NOISE_NONE
     cwork = torch.empty(capi_bytes_combine_apply(capi, G, s) + 256, dtype=torch.uint8, device=dev) if fused else None
     noise = capi.Noise(noise_kind, args.noise_amp, 20251021, 0)
 
@@ -175,7 +243,7 @@ def main():
         outputs()
         infos.append(info)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
 
@@ -203,6 +271,7 @@ def main():
     census = {f: capi.timing_query(f) for f in capi.FAMILY}
     capi.timing_enable(False)
     dom = max(per_launch_bytes, key=lambda k: census[k][1])
+    out_fam = "combine" if fused else "apply"
 
     # timed region: only the reported kernels carry events, one launch in
     # TIMING_STRIDE of the block-solve family (the events' own cost stays
@@ -210,43 +279,49 @@ def main():
     stride = TIMING_STRIDE if dom not in ("apply", "combine") else 1
     capi.timing_reset()
     capi.timing_stride(stride)
-    capi.timing_enable(sorted({dom, "combine" if fused else "apply"}))
+    fams = sorted({dom, out_fam, "combine"})
+    capi.timing_enable(fams)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     capi.timing_enable(False)
     capi.timing_stride(1)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    ms_per_step = (t1 - t0) * 1e3 / steps
     fam = {f: capi.timing_query(f) for f in capi.FAMILY}
-    it_total = sum(i["iters"] for i in infos[-args.steps:])
-    ref_total = sum(i["refinements"] for i in infos[-args.steps:])
-
-    default_workload = args.config == 1 and args.m is None
+    it_total = sum(i["iters"] for i in infos[-steps:])
+    ref_total = sum(i["refinements"] for i in infos[-steps:])
 
     # launches that move their full algorithmic bytes: one spmm, update_w and
     # update_dqp per block iteration, one more update_dqp per inner solve (its
     # first QR); the rest of a convergence-check chunk exits at once
     working = {"spmm": it_total, "update_w": it_total, "update_dqp": it_total + ref_total,
-               "apply": args.steps, "combine": args.steps, "resid": None}
+               "apply": steps, "combine": steps, "resid": None}
+    # the copy reference writes into a scratch buffer: T and F stay as the step left them
+    copy_ref = None
+    if headline:
+        scratch = torch.empty_like(T)
+        copy_ref = copy_rate(scratch, T)
+        del scratch
 
-    def roof(kind):
+    def roof(kind, strided):
         timed, tot = fam[kind]
         if timed == 0 or kind not in per_launch_bytes:
             return None
         avg_ms = tot / timed
-        launches = census[kind][0] * args.steps  # every launch of the timed steps
+        launches = census[kind][0] * steps  # every launch of the timed steps
         work = working.get(kind) or launches
         # achieved: the family's algorithmic bytes over its kernel time
         gbs = per_launch_bytes[kind] * work / (avg_ms * launches * 1e-3) / 1e9
-        # the combination's figure is for its one-pass (T and F) form
-        traffic = TRAFFIC_BYTES.get(kind) if default_workload and (kind != "combine" or fused) else None
+        key = (w.name, kind, "one-pass" if (kind == "combine" and fused) else "")
         out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-               "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kind,
+               "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": TRAFFIC_BYTES.get(key), "kernel": kind,
                "launches": launches, "working_launches": work, "timed_launches": timed,
                "avg_us": round(avg_ms * 1e3, 2), "bytes_per_launch": int(per_launch_bytes[kind])}
+        if copy_ref:
+            out["frac_of_copy"] = round(gbs / copy_ref["achieved"], 4)
         if kind == "combine":
             # the combination's matrix-core rate against the peak of its type
             # (2 N s M flops per output field block; the one-pass form has two)
@@ -254,51 +329,60 @@ def main():
             mt = "f64" if comb_compute == capi.F64 else ("f32" if comb_compute == capi.F32 else "bf16")
             tf = flops / (avg_ms * 1e-3) / 1e12
             out["mfma"] = {"dtype": mt, "tflops": round(tf, 2), "peak_tflops": MFMA_PEAK_TFLOPS[mt],
-                           "frac": round(tf / MFMA_PEAK_TFLOPS[mt], 4)}
+                           "frac": round(tf / MFMA_PEAK_TFLOPS[mt], 4),
+                           "intensity_cap_frac": round(min(1.0, (2.0 * s / wt) / (MFMA_PEAK_TFLOPS[mt] * 1e12 /
+                                                                               (HBM_PEAK_GBS * 1e9))), 4)}
         return out
 
-    roofline = roof(dom) if dom in per_launch_bytes else None
     value = m / (ms_per_step * 1e-3)
+    scheme = "f32+f64" if mixed else "f64"
     res = {
         "metric": "data pairs/s at rel residual <=1e-8 (BlocKOA: block solve + combine + operator action)",
         "value": round(value, 1),
         "unit": "pairs/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if mixed else "f64",
+        "dtype": scheme if t_dtype == torch.float64 else scheme + "+bf16",
         "data": "synthetic",
         "config": {"workload": w.name, "grid": list(chip.dims), "s": s, "M": m, "tol": w.tol,
-                   "scheme": w.scheme, "T_F_dtype": str(t_dtype).replace("torch.", ""), "precond": args.precond,
+                   "scheme": w.scheme if compute_override is None else f"{w.scheme} with {compute_override} iteration",
+                   "block_iteration": "f32" if mixed else "f64",
+                   "T_F_dtype": str(t_dtype).replace("torch.", ""), "precond": args.precond,
                    "outputs": "one pass (T = X C, F = (A X) C)" if fused else "two passes (T = X C, F = A T)",
                    "noise": args.noise if noise_kind == capi.NOISE_NONE else f"{args.noise} {args.noise_amp}"},
-        "roofline": roofline,
-        "output": roof("combine") if fused else roof("apply"),
+        "roofline": roof(dom, True),
+        "output": roof(out_fam, False),
         "census_ms_per_step": {k: round(v[1], 4) for k, v in census.items()},
         "census_launches_per_step": {k: v[0] for k, v in census.items()},
-        "solve": {"iters_per_step": it_total / args.steps, "refinements_per_step": ref_total / args.steps,
-                  "max_rel_res": max(i["max_rel_res"] for i in infos[-args.steps:])},
+        "solve": {"iters_per_step": it_total / steps, "refinements_per_step": ref_total / steps,
+                  "max_rel_res": max(i["max_rel_res"] for i in infos[-steps:])},
     }
+    if not fused:
+        res["combine"] = roof("combine", False)
+    if copy_ref:
+        res["copy"] = copy_ref
     res["stage_errors"] = stage_errors(G, X, C, T, F)
     if fused:
         # the operator action on its own (the stencil over the M fields), for
         # the stencil's HBM rate; the step itself forms F in the one pass
-        res["stencil"] = stencil_rate(G, T, F, t_dtype, apply_compute, per_launch_bytes["apply"],
-                                      TRAFFIC_BYTES.get("apply") if default_workload else None)
-    if args.cg_columns > 0:
+        res["stencil"] = stencil_rate(G, T, F, t_dtype, apply_compute, per_launch_bytes["apply"], None)
+    else:
+        res["stencil"] = res["output"]
+    if headline and args.cg_columns > 0:
         res["per_sample_cg"] = per_sample_cg(G, B, C, w, args.cg_columns, value)
         res["ablations"] = ablations(G, B, C, X, w, args.cg_columns, value, compute, wview, outputs,
                                      res["per_sample_cg"]["value"])
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(w)
-    print(json.dumps(res), flush=True)
+    del T, F, work
+    torch.cuda.empty_cache()
+    return res, w
 
 
-def bench_batched(args):
+def bench_batched(args, steps, warmup):
     """Batch of uneven chips (64 stacks, 32^2..256^2 x 4..12 layers, s = 16,
     M = 500 each): one batch plan solves every chip with grouped launches
     and graph-captured iteration chunks on a side stream, then each chip's
@@ -320,9 +404,9 @@ def bench_batched(args):
     plan = capi.BatchPlan(Gs, w.s, capi.F32)
     stream = torch.cuda.Stream()
     infos = []
-    fused = not args.separate_output
+    fused = args.outputs == "one-pass"
     cwork = torch.empty(capi_bytes_combine_apply(capi, max(Gs, key=lambda G: G.n), w.s) + 256, dtype=torch.uint8,
-                        device=dev)
+                        device=dev) if fused else None
     with torch.cuda.stream(stream):
         tpw = plan.tune(dev, stream=stream)
 
@@ -337,19 +421,19 @@ def bench_batched(args):
                     capi.apply_operator(G, T[:, :n], F=F[:, :n], stream=stream)
             infos.append(inf)
 
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             step()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
+    ms = (t1 - t0) * 1e3 / steps
     pairs = w.m * len(w.chips)
     last = infos[-1]
     res = {"metric": "data pairs/s at rel residual <=1e-8, batch of uneven chips", "value": round(pairs / (ms * 1e-3), 1),
-           "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+           "unit": "pairs/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": w.name, "nchips": len(w.chips), "cells_total": int(sum(c.n for c in w.chips)),
                       "s": w.s, "M_per_chip": w.m, "tol": w.tol, "scheme": "mixed", "T_F_dtype": "float64",
@@ -359,7 +443,8 @@ def bench_batched(args):
                      "mean": sum(i["iters"] for i in last) / len(last)},
            "max_rel_res": max(i["max_rel_res"] for i in last),
            "all_ok": all(i["status"] == capi.OK for i in last)}
-    print(json.dumps(res), flush=True)
+    plan.close()
+    return res
 
 
 def bench_learned(args):
@@ -407,7 +492,7 @@ def bench_learned(args):
            "learned_fewer_than_zero_smoothed": int((ln < zs).sum()),
            "rejected_columns": int(sum(r["rejected"] for r in recs)),
            "max_rel_res": {"zero": max(r["zero_res"] for r in recs), "learned": max(r["learned_res"] for r in recs)}}
-    print(json.dumps(res), flush=True)
+    return res
 
 
 def capi_bytes_combine_apply(capi, G, s):
@@ -541,34 +626,52 @@ def ablations(G, B, C, X, w, cols, value, compute, wview, outputs, cg_rate):
             "wo_all": {"value": cg_rate, "blockoa_over": round(value / cg_rate, 1)}}
 
 
-def cpu_baseline(w, min_seconds=10.0, max_reps=5):
-    """The CPU oracle as it stands, on the host cores, over the whole
-    workload (no extrapolation): per-column CG for the s basis solves, then
-    combination and operator action of all M fields in chunks of 500.
-    Repeated until min_seconds have elapsed; the median run is reported."""
+def cpu_baseline(w, precond="jacobi", min_seconds=10.0, max_reps=5):
+    """The CPU oracle as it stands, built -O3 -march=native on the host that
+    runs it, over the whole workload (no extrapolation): per-column CG for the
+    s basis solves (with the GPU path's preconditioner: Jacobi PCG, or plain
+    CG), then combination and operator action of all M fields in chunks of
+    500.  Repeated until min_seconds have elapsed; the median run is
+    reported.  The other preconditioner's run is reported beside it."""
     import numpy as np
 
     import oracle
 
+    oracle.select_build(native=True)
     chip = w.chips[0]
     A = oracle.assemble_chip(chip)
     cores = oracle.max_threads()
-    runs, iters_seen = [], None
-    t_start = time.perf_counter()
-    while len(runs) < max_reps and (time.perf_counter() - t_start < min_seconds or not runs):
+
+    def run(solver):
         t0 = time.perf_counter()
-        X, iters, _ = oracle.cg_many(A, w.B[0], w.tol)
+        X, iters, _ = solver(A, w.B[0], w.tol)
+        t1 = time.perf_counter()
         for c0 in range(0, w.m, 500):
             T = oracle.gemm(X, w.C[0][c0:c0 + 500])
             oracle.apply_many(A, T)
-        runs.append(time.perf_counter() - t0)
-        iters_seen = iters
+        t2 = time.perf_counter()
+        return t2 - t0, t1 - t0, iters
+
+    main_solver = oracle.pcg_many if precond == "jacobi" else oracle.cg_many
+    other_solver = oracle.cg_many if precond == "jacobi" else oracle.pcg_many
+    runs, iters_seen, t_solve = [], None, []
+    t_start = time.perf_counter()
+    while len(runs) < max_reps and (time.perf_counter() - t_start < min_seconds or not runs):
+        t, ts, iters_seen = run(main_solver)
+        runs.append(t)
+        t_solve.append(ts)
+    t_other, ts_other, iters_other = run(other_solver)
+    oracle.select_build(native=False)
     t = float(np.median(runs))
     return {"value": round(w.m / t, 2), "unit": "pairs/s", "cores": cores, "kind": "oracle",
-            "sample": f"whole workload ({w.s} basis CG solves to rel res {w.tol:g}, mean "
-                      f"{float(np.mean(iters_seen)):.0f} iterations, then combination + operator action of all "
-                      f"{w.m} fields), median of {len(runs)} runs",
-            "seconds_measured": round(float(sum(runs)), 2)}
+            "sample": f"whole workload ({w.s} basis solves by {'Jacobi PCG' if precond == 'jacobi' else 'CG'} to "
+                      f"rel res {w.tol:g}, mean {float(np.mean(iters_seen)):.0f} iterations, then combination + "
+                      f"operator action of all {w.m} fields), median of {len(runs)} runs, gcc -O3 -march=native",
+            "seconds_measured": round(float(sum(runs)), 2), "solve_seconds": round(float(np.median(t_solve)), 3),
+            "other_preconditioner": {"solver": "CG" if precond == "jacobi" else "Jacobi PCG",
+                                     "value": round(w.m / t_other, 2),
+                                     "mean_iters": round(float(np.mean(iters_other)), 1),
+                                     "solve_seconds": round(ts_other, 3)}}
 
 
 if __name__ == "__main__":

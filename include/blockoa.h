@@ -372,6 +372,27 @@ bko_status bko_apply_operator(bko_op A, int m, const void *T, int ldt, bko_dtype
                               int ldf, bko_dtype f_t, bko_dtype compute, void *stream);
 
 /*
+ * dst = src, `bytes` bytes of device memory, with 16-byte vector loads and
+ * stores (the library's reference for achievable HBM bandwidth: every
+ * HBM-bound kernel of the path reads and writes whole fields the same way).
+ * Both pointers 16-byte aligned, bytes a multiple of 16, no overlap;
+ * otherwise BKO_EINVAL.  Asynchronous.
+ */
+bko_status bko_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+/*
+ * Which operator-action kernel bko_apply_operator would run for these
+ * arguments (pointers are compared for alignment only, never read):
+ * *tile_rows = the rows per tile of the z-marching LDS-tiled kernel
+ * (full-width row tiles with a one-row halo, 16-byte vector access), or 0
+ * when the per-cell kernel takes the call (rows that are not a whole number
+ * of 16-byte vectors, views not 16-byte aligned, or tiles too short to pay
+ * for their halo).  Host only, no launch.
+ */
+bko_status bko_apply_operator_tiling(bko_op A, int m, const void *T, int ldt, bko_dtype t_t, const void *F, int ldf,
+                                     bko_dtype f_t, int *tile_rows);
+
+/*
  * Fused residual form used by the correction loop: R = B - A X in FP64
  * (B, X, R n x m, FP64).  R may alias B.  Asynchronous.
  */

@@ -19,6 +19,8 @@ Everything here is plain FP64:
   S = diag(A)^(-1/2) and the symmetrically scaled S A S, and preconditioned
   CG with M = diag(A) (the paper leaves the preconditioner unstated; these
   define the optional Jacobi mode of the solves).
+* :func:`pcg_many` -- the same in C, one column per thread (the timed CPU
+  baseline with the GPU path's preconditioner).
 * :func:`gemm` -- T = X C by plain loops (Sec. III-B, Eq. (5), raw weights).
 * :func:`apply_many` -- F = A T by CSR products (Sec. III-C, Eq. (6)).
 * :mod:`oracle.conv_ref` -- FP64 convolution encoder-decoder forward and
@@ -38,24 +40,41 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_NATIVE = os.path.join(_HERE, "liboracle_native.so")
 _lib = None
+_native = False
+_native_fresh = False  # the native build is recompiled once per process, for the host it runs on
 
 
-def build(force: bool = False) -> str:
-    """Compile the C oracle with gcc (portable flags: the library may run on
-    another host)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force: bool = False, native: bool = False) -> str:
+    """Compile the C oracle with gcc.  The default build uses portable flags
+    (the tests may run on another host); ``native=True`` builds the copy the
+    CPU baseline times, with -O3 -march=native for the host it runs on (the
+    same source, compiled for speed, not changed)."""
+    lib = _LIB_NATIVE if native else _LIB
+    flags = ["-O3", "-march=native"] if native else ["-O2"]
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", *flags, "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, lib)
+    return lib
+
+
+def select_build(native: bool) -> None:
+    """Route later oracle calls to the native (-O3 -march=native) or the
+    portable build; the native one is compiled on first use."""
+    global _lib, _native
+    if native != _native:
+        _lib = None
+        _native = native
 
 
 def _load():
-    global _lib
+    global _lib, _native_fresh
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(_LIB)
+        path = build(force=_native and not _native_fresh, native=_native)
+        _native_fresh = _native_fresh or _native
+        lib = ctypes.CDLL(path)
         i64, i32, dbl, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
         lib.orc_nnz_bound.restype = i64
         lib.orc_nnz_bound.argtypes = [i32, i32, i32]
@@ -67,6 +86,8 @@ def _load():
         lib.orc_cg.argtypes = [i64, vp, vp, vp, vp, vp, dbl, i32, vp, vp]
         lib.orc_cg_many.restype = None
         lib.orc_cg_many.argtypes = [i64, vp, vp, vp, i32, vp, i64, vp, i64, dbl, i32, vp, vp, i32]
+        lib.orc_pcg_many.restype = None
+        lib.orc_pcg_many.argtypes = [i64, vp, vp, vp, i32, vp, i64, vp, i64, dbl, i32, vp, vp, i32]
         lib.orc_gemm.restype = None
         lib.orc_gemm.argtypes = [i64, i32, i64, vp, i64, vp, i64, vp, i64, i32]
         lib.orc_apply_many.restype = None
@@ -147,6 +168,20 @@ def cg_many(A: CSR, B: np.ndarray, tol: float, maxit: int = 100000, nthreads: in
     relres = np.zeros(s)
     lib.orc_cg_many(A.n, _p(A.rowptr), _p(A.col), _p(A.val), s, _p(B), A.n, _p(X), A.n, tol, maxit,
                     _p(iters), _p(relres), nthreads)
+    return X, iters, relres
+
+
+def pcg_many(A: CSR, B: np.ndarray, tol: float, maxit: int = 100000, nthreads: int = 0):
+    """Jacobi-preconditioned CG (M = diag(A)) per row of B (shape (s, N)),
+    the stopping rule of :func:`pcg`.  Returns (X, iters, relres)."""
+    lib = _load()
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    s = B.shape[0]
+    X = np.empty_like(B)
+    iters = np.zeros(s, dtype=np.int32)
+    relres = np.zeros(s)
+    lib.orc_pcg_many(A.n, _p(A.rowptr), _p(A.col), _p(A.val), s, _p(B), A.n, _p(X), A.n, tol, maxit,
+                     _p(iters), _p(relres), nthreads)
     return X, iters, relres
 
 

@@ -14,6 +14,9 @@
  *   - X = A^{-1} B by unpreconditioned conjugate gradients, one right-hand side
  *     at a time, from x0 = 0 (the paper's direct solution method, Sec. II-D,
  *     and its CG baseline, Sec. V-A);
+ *   - the same with diagonal (Jacobi) preconditioning, M = diag(A), stopping
+ *     on the unpreconditioned residual (the paper leaves the preconditioner
+ *     unstated; this defines the optional Jacobi mode of the baseline);
  *   - T = X C by plain loops (Sec. III-B, Eq. (5) with raw weights);
  *   - F = A T by CSR matrix-vector products (Sec. III-C, Eq. (6)).
  *
@@ -192,6 +195,70 @@ void orc_cg_many(int64_t n, const int64_t *rowptr, const int32_t *col, const dou
                               &relres[j], scratch);
         free(scratch);
     }
+    (void)nthreads;
+}
+
+/*
+ * Preconditioned CG with M^{-1} = diag(minv) for one right-hand side from
+ * x = 0: z = M^{-1} r, rho = r.z, alpha = rho / p.Ap, x += alpha p,
+ * r -= alpha Ap, p = z' + (rho' / rho) p; stops when the unpreconditioned
+ * recurrence residual satisfies ||r|| <= tol ||b|| or after maxit
+ * iterations.  relres and the return value as for orc_cg.  scratch must
+ * hold 4n doubles.
+ */
+int orc_pcg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, const double *minv,
+            const double *b, double *x, double tol, int maxit, double *relres, double *scratch)
+{
+    double *r = scratch, *p = scratch + n, *q = scratch + 2 * n, *z = scratch + 3 * n;
+    for (int64_t i = 0; i < n; ++i) { x[i] = 0.0; r[i] = b[i]; z[i] = minv[i] * r[i]; p[i] = z[i]; }
+    const double bnorm = sqrt(dot(n, b, b));
+    int it = 0;
+    if (bnorm == 0.0) { *relres = 0.0; return 0; }
+    double rho = dot(n, r, z);
+    while (it < maxit && sqrt(dot(n, r, r)) > tol * bnorm) {
+        orc_spmv(n, rowptr, col, val, p, q);
+        const double alpha = rho / dot(n, p, q);
+        for (int64_t i = 0; i < n; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; z[i] = minv[i] * r[i]; }
+        const double rho_new = dot(n, r, z);
+        const double beta = rho_new / rho;
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        rho = rho_new;
+        ++it;
+    }
+    orc_spmv(n, rowptr, col, val, x, q);
+    double res = 0.0;
+    for (int64_t i = 0; i < n; ++i) { const double e = b[i] - q[i]; res += e * e; }
+    *relres = sqrt(res) / bnorm;
+    return it;
+}
+
+/* Jacobi-preconditioned CG (M = diag(A)) per column, one column per thread. */
+void orc_pcg_many(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                  int s, const double *B, int64_t ldb, double *X, int64_t ldx,
+                  double tol, int maxit, int *iters, double *relres, int nthreads)
+{
+    double *minv = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int64_t r = 0; r < n; ++r) {
+        double d = 0.0;
+        for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p)
+            if (col[p] == r) d += val[p];
+        minv[r] = 1.0 / d;
+    }
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel num_threads(nthreads)
+#endif
+    {
+        double *scratch = (double *)malloc(sizeof(double) * 4 * (size_t)n);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int j = 0; j < s; ++j)
+            iters[j] = orc_pcg(n, rowptr, col, val, minv, B + j * ldb, X + j * ldx, tol, maxit,
+                               &relres[j], scratch);
+        free(scratch);
+    }
+    free(minv);
     (void)nthreads;
 }
 

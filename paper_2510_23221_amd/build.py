@@ -3,7 +3,8 @@
     python -m paper_2510_23221_amd.build
 
 Every HIP source is compiled for gfx950 only, with packed FP32 instructions
-disabled, into ``paper_2510_23221_amd/libblockoa.so``.
+disabled, to its own object (in parallel, under ``_build/``) and linked into
+``paper_2510_23221_amd/libblockoa.so``.
 """
 from __future__ import annotations
 
@@ -11,10 +12,12 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libblockoa.so")
+OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["capi.hip", "stencil.hip", "combine.hip", "blockcg.hip", "cg.hip", "nn.hip"]
 ARCH = "gfx950"
 
@@ -36,16 +39,35 @@ def build_library(force: bool = True, verbose: bool = False) -> str:
     deps.append(os.path.join(os.path.dirname(HERE), "include", "blockoa.h"))
     if not force and os.path.exists(LIB) and all(os.path.getmtime(LIB) >= os.path.getmtime(d) for d in deps):
         return LIB
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-command-line-argument", *srcs, "-o", tmp]
+    flags = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wno-unused-command-line-argument"]
+    os.makedirs(OBJDIR, exist_ok=True)
+    tag = os.getpid()
+
+    def compile_one(src):
+        obj = os.path.join(OBJDIR, os.path.basename(src) + f".{tag}.o")
+        cmd = [hipcc(), *flags, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError(f"hipcc failed on {os.path.basename(src)} with status {res.returncode}")
+        return obj
+
+    with ThreadPoolExecutor(max_workers=min(len(srcs), 8)) as pool:
+        objs = list(pool.map(compile_one, srcs))
+    tmp = LIB + f".tmp{tag}"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-fPIC", "-shared", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
+    for o in objs:
+        os.remove(o)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError(f"hipcc failed with status {res.returncode}")
+        raise RuntimeError(f"hipcc link failed with status {res.returncode}")
     os.replace(tmp, LIB)
     return LIB
 

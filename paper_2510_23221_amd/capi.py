@@ -50,7 +50,8 @@ EXPORTED = ("bko_version", "bko_last_error", "bko_operator_bytes", "bko_assemble
             "bko_lstart_pack_target", "bko_lstart_unpack", "bko_jacobi_smooth", "bko_operator_set_precond",
             "bko_operator_get_precond", "bko_timing_set_stride", "bko_combine_apply_workspace_bytes",
             "bko_combine_apply", "bko_combine_noisy", "bko_noise_fill", "bko_normalize_weights",
-            "bko_boundary_source", "bko_add_column")
+            "bko_boundary_source", "bko_add_column", "bko_apply_operator_tiling",
+            "bko_copy")
 
 
 class BlockoaError(RuntimeError):
@@ -133,6 +134,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bko_normalize_weights": (i32, [i32, i32, vp, i32, dbl, vp, vp]),
         "bko_boundary_source": (i32, [vp, vp, ctypes.POINTER(dbl), vp, vp]),
         "bko_add_column": (i32, [i32, i32, vp, i32, vp, dbl, vp]),
+        "bko_apply_operator_tiling": (i32, [vp, i32, vp, i32, i32, vp, i32, i32, ctypes.POINTER(i32)]),
+        "bko_copy": (i32, [vp, vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -710,6 +713,29 @@ def apply_operator(A: HeatOperator, T: torch.Tensor, out_dtype=torch.float64, co
     fp, ldf, ft = _block(F, "F")
     _check(load_library().bko_apply_operator(A.handle, m, tp, ldt, tt, fp, ldf, ft, compute, _stream(stream)))
     return F
+
+
+def apply_operator_tiling(A: HeatOperator, T: torch.Tensor, F: torch.Tensor) -> int:
+    """Rows per tile of the LDS-tiled operator-action kernel that
+    apply_operator(A, T, F=F) runs, or 0 for the per-cell kernel."""
+    tp, ldt, tt = _block(T, "T")
+    fp, ldf, ft = _block(F, "F")
+    out = ctypes.c_int()
+    _check(load_library().bko_apply_operator_tiling(A.handle, T.shape[0], tp, ldt, tt, fp, ldf, ft,
+                                                    ctypes.byref(out)))
+    return out.value
+
+
+def copy(dst: torch.Tensor, src: torch.Tensor, stream=None) -> torch.Tensor:
+    """dst = src by the library's 16-byte vector copy kernel (contiguous
+    tensors of equal byte size)."""
+    if not (dst.is_cuda and src.is_cuda and dst.is_contiguous() and src.is_contiguous()):
+        raise ValueError("copy needs contiguous GPU tensors")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("copy needs tensors of equal byte size")
+    _check(load_library().bko_copy(_ptr(dst), _ptr(src), nbytes, _stream(stream)))
+    return dst
 
 
 def residual(A: HeatOperator, B: torch.Tensor, X: torch.Tensor, R: Optional[torch.Tensor] = None,

@@ -287,6 +287,42 @@ __global__ void zero_kernel(uint32_t *p, size_t words)
     for (size_t w = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words; w += stride) p[w] = 0u;
 }
 
+// Device copy with 16-byte vector accesses: each workgroup moves 16 KB per
+// round (four vectors per thread, all four loads issued before the stores),
+// rounds spread over the grid; the last partial round vector by vector.
+// The achievable-bandwidth reference of the HBM-bound kernels.
+constexpr int kCopyVecs = 4;
+__global__ __launch_bounds__(256) void copy16_kernel(uint4 *__restrict__ dst, const uint4 *__restrict__ src,
+                                                     size_t nvec)
+{
+    constexpr size_t per_round = 256 * kCopyVecs;
+    const size_t rounds = nvec / per_round;
+    for (size_t r = blockIdx.x; r < rounds; r += gridDim.x) {
+        const size_t base = r * per_round + threadIdx.x;
+        uint4 v[kCopyVecs];
+#pragma unroll
+        for (int i = 0; i < kCopyVecs; ++i) v[i] = src[base + i * 256];
+#pragma unroll
+        for (int i = 0; i < kCopyVecs; ++i) dst[base + i * 256] = v[i];
+    }
+    for (size_t e = rounds * per_round + static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; e < nvec;
+         e += static_cast<size_t>(gridDim.x) * 256)
+        dst[e] = src[e];
+}
+
+bko_status launch_copy16(void *dst, const void *src, size_t bytes, hipStream_t stream)
+{
+    if (bytes == 0) return BKO_OK;
+    const size_t nvec = bytes / 16;
+    const size_t rounds = nvec / (256 * kCopyVecs);
+    // a few workgroups per CU resident at once, each looping over rounds
+    const size_t blocks = std::max<size_t>(1, std::min<size_t>(rounds, 256 * 8));
+    hipLaunchKernelGGL(copy16_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
+                       static_cast<uint4 *>(dst), static_cast<const uint4 *>(src), nvec);
+    BKO_HIP(hipGetLastError());
+    return BKO_OK;
+}
+
 bko_status launch_zero(void *p, size_t bytes, hipStream_t stream)
 {
     if (bytes == 0) return BKO_OK;
@@ -526,6 +562,33 @@ bko_status bko_apply_operator(bko_op A, int m, const void *T, int ldt, bko_dtype
     TimedLaunch tl(kApply, static_cast<hipStream_t>(stream));
     return launch_stencil(op, m, T, ldt, t_t, F, ldf, f_t, compute, nullptr, 0,
                           static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+bko_status bko_copy(void *dst, const void *src, size_t bytes, void *stream)
+{
+    BKO_GUARD_BEGIN
+    if (bytes == 0) return BKO_OK;
+    BKO_CHECK(dst != nullptr && src != nullptr, "NULL array");
+    BKO_CHECK(bytes % 16 == 0 && reinterpret_cast<uintptr_t>(dst) % 16 == 0 &&
+                  reinterpret_cast<uintptr_t>(src) % 16 == 0,
+              "copy of %zu bytes needs 16-byte aligned pointers and a multiple of 16 bytes", bytes);
+    const char *s0 = static_cast<const char *>(src), *d0 = static_cast<const char *>(dst);
+    BKO_CHECK(s0 + bytes <= d0 || d0 + bytes <= s0, "source and destination overlap");
+    return launch_copy16(dst, src, bytes, static_cast<hipStream_t>(stream));
+    BKO_GUARD_END
+}
+
+bko_status bko_apply_operator_tiling(bko_op A, int m, const void *T, int ldt, bko_dtype t_t, const void *F, int ldf,
+                                     bko_dtype f_t, int *tile_rows)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(A != nullptr && tile_rows != nullptr, "NULL argument");
+    const Operator &op = *reinterpret_cast<const Operator *>(A);
+    BKO_CHECK(m >= 0 && ldt >= op.n && ldf >= op.n, "bad sizes");
+    BKO_CHECK(valid_dtype(t_t) && valid_dtype(f_t), "bad dtype");
+    *tile_rows = stencil_tile_rows(op, m, T, ldt, t_t, F, ldf, f_t);
+    return BKO_OK;
     BKO_GUARD_END
 }
 

@@ -15,6 +15,9 @@ bko_status launch_stencil(const Operator &op, int m, const void *X, int64_t ldx,
                           void *Y, int64_t ldy, bko_dtype t_out, bko_dtype compute,
                           const double *Bres, int64_t ldb, hipStream_t stream, const int *skip = nullptr,
                           int *stop = nullptr);
+// Rows per tile the operator action takes for these fields (0: per-cell kernel).
+int stencil_tile_rows(const Operator &op, int m, const void *X, int64_t ldx, bko_dtype t_in, const void *Y,
+                      int64_t ldy, bko_dtype t_out);
 
 // `sweeps` damped Jacobi sweeps X <- X + omega (B - A X) / diag(A) in FP64
 // over m columns; work is an n x m FP64 block (ldw >= n).

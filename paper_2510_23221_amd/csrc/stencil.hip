@@ -302,35 +302,44 @@ inline int tile_rows(int nx, int ny, int m, int vx)
     return ty;
 }
 
+// Rows per tile of stencil_tile_kernel for these fields, or 0 when the
+// per-cell kernel takes them: rows not a whole number of 16-byte vectors,
+// views not 16-byte aligned, or tiles too short to pay for their halo.
+int tile_plan(const Operator &op, int m, size_t win, size_t wout, uintptr_t X, int64_t ldx, uintptr_t Y, int64_t ldy)
+{
+    const int vx = static_cast<int>(16 / win);
+    const size_t ya = std::min<size_t>(16, vx * wout);
+    // one halo vector per thread: two halo rows of nx / vx vectors each
+    const bool aligned = op.nx % vx == 0 && 2 * (op.nx / vx) <= kThreads && X % 16 == 0 &&
+                         (ldx * win) % 16 == 0 && Y % ya == 0 && (ldy * wout) % ya == 0;
+    if (!aligned || m <= 0) return 0;
+    const int ty = tile_rows(op.nx, op.ny, m, vx);
+    // short tiles waste the halo and most threads: the per-cell kernel is
+    // better there (e.g. the few-column products inside the block solve)
+    if (!(ty >= 8 || ty == op.ny)) return 0;
+    if (static_cast<int64_t>(ty) * op.nx > static_cast<int64_t>(kThreads) * vx * kTileVecs) return 0;
+    const int ntiles = (op.ny + ty - 1) / ty;
+    if (static_cast<uint64_t>(ntiles) * m > 0x7fffffffu) return 0;
+    return ty;
+}
+
 template <class Tin, class Tout, class Tc, class Acc, bool kResidual>
 bko_status run(const Operator &op, const Tc *diag, const Tc *wx, const Tc *wy, const Tc *wz, int m,
                const void *X, int64_t ldx, void *Y, int64_t ldy, const double *Bres, int64_t ldb,
                hipStream_t stream, const int *skip, int *stop)
 {
-    constexpr int VX = 16 / sizeof(Tin);
-    // one halo vector per thread: two halo rows of nx / VX vectors each
-    const bool tiled = op.nx % VX == 0 && 2 * (op.nx / VX) <= kThreads &&
-                       reinterpret_cast<uintptr_t>(X) % 16 == 0 && (ldx * sizeof(Tin)) % 16 == 0 &&
-                       reinterpret_cast<uintptr_t>(Y) % (VX * sizeof(Tout) >= 16 ? 16 : VX * sizeof(Tout)) == 0 &&
-                       (ldy * sizeof(Tout)) % (VX * sizeof(Tout) >= 16 ? 16 : VX * sizeof(Tout)) == 0;
-    if (tiled) {
-        const int ty = tile_rows(op.nx, op.ny, m, VX);
-        // short tiles waste the halo and most threads: the per-cell kernel is
-        // better there (e.g. the few-column products inside the block solve)
-        if ((ty >= 8 || ty == op.ny) &&
-            static_cast<int64_t>(ty) * op.nx <= static_cast<int64_t>(kThreads) * VX * kTileVecs) {
-            const int ntiles = (op.ny + ty - 1) / ty;
-            const uint64_t nb = static_cast<uint64_t>(ntiles) * m;
-            if (nb <= 0x7fffffffu) {
-                const size_t lds = 2 * std::min(sizeof(Acc), sizeof(Tin)) * static_cast<size_t>(ty + 2) * op.nx;
-                hipLaunchKernelGGL((stencil_tile_kernel<Tin, Tout, Tc, Acc, kResidual>), dim3(static_cast<uint32_t>(nb)),
-                                   dim3(kThreads), lds, stream, diag, wx, wy, wz, op.nx, op.ny, op.nz,
-                                   static_cast<const Tin *>(X), ldx, static_cast<Tout *>(Y), ldy, Bres, ldb, ty, ntiles,
-                                   static_cast<uint32_t>(nb), skip, stop);
-                BKO_HIP(hipGetLastError());
-                return BKO_OK;
-            }
-        }
+    const int ty = tile_plan(op, m, sizeof(Tin), sizeof(Tout), reinterpret_cast<uintptr_t>(X), ldx,
+                             reinterpret_cast<uintptr_t>(Y), ldy);
+    if (ty > 0) {
+        const int ntiles = (op.ny + ty - 1) / ty;
+        const uint64_t nb = static_cast<uint64_t>(ntiles) * m;
+        const size_t lds = 2 * std::min(sizeof(Acc), sizeof(Tin)) * static_cast<size_t>(ty + 2) * op.nx;
+        hipLaunchKernelGGL((stencil_tile_kernel<Tin, Tout, Tc, Acc, kResidual>), dim3(static_cast<uint32_t>(nb)),
+                           dim3(kThreads), lds, stream, diag, wx, wy, wz, op.nx, op.ny, op.nz,
+                           static_cast<const Tin *>(X), ldx, static_cast<Tout *>(Y), ldy, Bres, ldb, ty, ntiles,
+                           static_cast<uint32_t>(nb), skip, stop);
+        BKO_HIP(hipGetLastError());
+        return BKO_OK;
     }
     const uint32_t ntiles = static_cast<uint32_t>((op.n + kThreads - 1) / kThreads);
     // enough column groups to fill the chip, few enough that each thread
@@ -422,6 +431,13 @@ bko_status launch_stencil(const Operator &op, int m, const void *X, int64_t ldx,
     case BKO_F32: return dispatch_out<float>(op, m, X, ldx, Y, ldy, t_out, compute, stream, skip, stop);
     default: return dispatch_out<bf16>(op, m, X, ldx, Y, ldy, t_out, compute, stream, skip, stop);
     }
+}
+
+int stencil_tile_rows(const Operator &op, int m, const void *X, int64_t ldx, bko_dtype t_in, const void *Y,
+                      int64_t ldy, bko_dtype t_out)
+{
+    return tile_plan(op, m, dtype_size(t_in), dtype_size(t_out), reinterpret_cast<uintptr_t>(X), ldx,
+                     reinterpret_cast<uintptr_t>(Y), ldy);
 }
 
 bko_status launch_jacobi(const Operator &op, int m, const double *B, int64_t ldb, double *X, int64_t ldx,

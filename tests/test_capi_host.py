@@ -97,3 +97,13 @@ def test_no_cpu_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(capi, "_lib", None)
     with pytest.raises(ImportError):
         capi.load_library(str(tmp_path / "missing.so"))
+
+
+def test_copy_rejects_before_launch():
+    lib = capi.load_library()
+    a, b = ctypes.c_void_p(4096), ctypes.c_void_p(1 << 20)  # never dereferenced
+    assert lib.bko_copy(b, a, 24, None) == capi.EINVAL  # not a multiple of 16 bytes
+    assert lib.bko_copy(ctypes.c_void_p(4104), a, 32, None) == capi.EINVAL  # misaligned
+    assert lib.bko_copy(ctypes.c_void_p(4096 + 16), a, 64, None) == capi.EINVAL  # overlap
+    assert b"overlap" in lib.bko_last_error()
+    assert lib.bko_copy(b, a, 0, None) == capi.OK  # nothing to do

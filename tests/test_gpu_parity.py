@@ -582,3 +582,16 @@ def test_block_solve_wide_blocks(ops, dev, s, compute):
     X, info, it_ref = _solve_check(A, G, B, tol, compute, dev, xerr=(1e-7 if compute == capi.F64 else None))
     assert info["status"] == capi.OK
     assert info["iters"] < it_ref.mean()
+
+
+# ------------------------------------------------------------------ copy reference kernel
+
+@pytest.mark.parametrize("nbytes", [16, 16 * 1000 + 16 * 7, 16 * 1024 * 40 + 48, 3 * (1 << 24)])
+def test_copy_kernel_is_exact(dev, nbytes):
+    """The 16-byte vector copy (the bandwidth reference) moves every byte,
+    including a partial last round, and nothing past the end."""
+    src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device=dev)
+    dst = torch.zeros(nbytes + 64, dtype=torch.uint8, device=dev)
+    capi.copy(dst[:nbytes], src)
+    assert torch.equal(dst[:nbytes], src)
+    assert int(dst[nbytes:].sum()) == 0

@@ -87,3 +87,36 @@ def test_pcg_solution_and_iteration_gain_on_stack():
     assert res <= 1e-12 * 1.01
     assert np.linalg.norm(x - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
     assert it_p < it_c
+
+
+def test_c_pcg_matches_dense_solve_and_numpy_pcg():
+    """The C Jacobi-PCG (the timed CPU baseline): LAPACK's solution on a
+    high-contrast stack, the iteration count of the numpy PCG above (same
+    recurrences and stopping rule), one exact step on a diagonal operator,
+    and the same results from the -O3 -march=native build."""
+    rng = np.random.default_rng(6)
+    chip = synth.chip_stack(rng, 12, 10, 5)
+    A = oracle.assemble_chip(chip)
+    B = rng.standard_normal((3, A.n))
+    X, iters, rel = oracle.pcg_many(A, B, 1e-12)
+    Xd = np.linalg.solve(A.to_dense(), B.T).T
+    assert np.linalg.norm(X - Xd) <= 1e-8 * np.linalg.norm(Xd)
+    assert (rel <= 1e-12 * 1.01).all()
+    sc, _ = oracle.jacobi_scaling(A)
+    for j in range(3):
+        _, it_np, _ = oracle.pcg(A, B[j], 1e-12, minv=sc * sc)
+        assert abs(int(iters[j]) - it_np) <= 1
+    n = 12
+    d = rng.uniform(1.0, 50.0, size=n)
+    Dm = oracle.CSR(n, np.arange(n + 1, dtype=np.int64), np.arange(n, dtype=np.int32), d.copy())
+    x1, it1, _ = oracle.pcg_many(Dm, B[:1, :n], 1e-14)
+    assert it1[0] == 1 and np.allclose(x1[0], B[0, :n] / d, rtol=1e-15, atol=0)
+    oracle.select_build(native=True)
+    try:
+        Xn, itn, _ = oracle.pcg_many(A, B, 1e-12)
+        Xc, itc, _ = oracle.cg_many(A, B, 1e-12)
+    finally:
+        oracle.select_build(native=False)
+    Xp, itp, _ = oracle.cg_many(A, B, 1e-12)
+    assert np.abs(itn - iters).max() <= 1 and np.abs(itc - itp).max() <= 1
+    assert np.linalg.norm(Xn - X) <= 1e-9 * np.linalg.norm(X)
