@@ -262,6 +262,24 @@ bko_status bko_batch_solve(bko_batch plan, const double *const *B, const int *ld
 
 /* ------------------------------------------- per-sample CG (the baseline) */
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * block solve as bko_block_krylov_solve, same arguments and results, with
+ * the workspace taken from scratch memory the library holds itself
+ * (BKO_NOALLOC_SCRATCH_BYTES per device, held until the process ends).
+ * Calls no hipMalloc or hipFree.  A solve whose workspace
+ * (bko_block_krylov_workspace_bytes) exceeds the scratch returns BKO_EINVAL
+ * and launches nothing.  Every call on one GPU shares that GPU's scratch:
+ * calls that overlap on one GPU (other threads, other streams) race and must
+ * be serialised by the caller.  The scratch keeps the last call's contents;
+ * the solve initialises everything it reads.  Synchronises the stream.
+ */
+#define BKO_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+bko_status bko_block_krylov_solve_noalloc(bko_op A, int s, const double *B, int ldb, double *X, int ldx,
+                                          const double *X0, int ldx0, bko_dtype compute, double tol, int max_iter,
+                                          bko_solve_info *info, void *stream);
+
 /* Workspace bytes for bko_cg_solve with m right-hand sides. */
 bko_status bko_cg_workspace_bytes(bko_op A, int m, size_t *bytes);
 

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libblockoa.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["capi.hip", "stencil.hip", "combine.hip", "blockcg.hip", "cg.hip", "nn.hip"]
+SOURCES = ["capi.hip", "stencil.hip", "combine.hip", "blockcg.hip", "cg.hip", "nn.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 

@@ -51,7 +51,7 @@ EXPORTED = ("bko_version", "bko_last_error", "bko_operator_bytes", "bko_assemble
             "bko_operator_get_precond", "bko_timing_set_stride", "bko_combine_apply_workspace_bytes",
             "bko_combine_apply", "bko_combine_noisy", "bko_noise_fill", "bko_normalize_weights",
             "bko_boundary_source", "bko_add_column", "bko_apply_operator_tiling",
-            "bko_copy")
+            "bko_copy", "bko_block_krylov_solve_noalloc")
 
 
 class BlockoaError(RuntimeError):
@@ -136,6 +136,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bko_add_column": (i32, [i32, i32, vp, i32, vp, dbl, vp]),
         "bko_apply_operator_tiling": (i32, [vp, i32, vp, i32, i32, vp, i32, i32, ctypes.POINTER(i32)]),
         "bko_copy": (i32, [vp, vp, sz, vp]),
+        "bko_block_krylov_solve_noalloc": (i32, [vp, i32, vp, i32, vp, i32, vp, i32, i32, dbl, i32,
+                                                 ctypes.POINTER(SolveInfo), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -300,6 +302,37 @@ def block_krylov_solve(A: HeatOperator, B: torch.Tensor, tol: float, compute: in
     st = load_library().bko_block_krylov_solve(A.handle, s, bp, ldb, xp, ldx, x0p, ldx0, compute, tol,
                                                max_iter, ctypes.c_void_p(wptr), nbytes, ctypes.byref(info),
                                                _stream(stream))
+    if check and st != OK:
+        _check(st)
+    d = info.as_dict()
+    d["status_name"] = STATUS_NAMES.get(st, str(st))
+    return X, d
+
+
+#: device scratch bytes of block_krylov_solve_noalloc (include/blockoa.h)
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def block_krylov_solve_noalloc(A: HeatOperator, B: torch.Tensor, tol: float, compute: int = F64,
+                               max_iter: int = 100000, X0: Optional[torch.Tensor] = None,
+                               X: Optional[torch.Tensor] = None, stream=None, check: bool = True):
+    """block_krylov_solve on the library's own scratch memory (no workspace
+    argument; the C entry point allocates nothing).  Returns (X, info)."""
+    s = B.shape[0]
+    bp, ldb, bt = _block(B, "B")
+    if bt != F64:
+        raise ValueError("B must be float64")
+    if X is None:
+        X = torch.empty_like(B)
+    xp, ldx, _ = _block(X, "X")
+    x0p, ldx0 = (ctypes.c_void_p(0), 0)
+    if X0 is not None:
+        x0p, ldx0, x0t = _block(X0, "X0")
+        if x0t != F64:
+            raise ValueError("X0 must be float64")
+    info = SolveInfo()
+    st = load_library().bko_block_krylov_solve_noalloc(A.handle, s, bp, ldb, xp, ldx, x0p, ldx0, compute, tol,
+                                                       max_iter, ctypes.byref(info), _stream(stream))
     if check and st != OK:
         _check(st)
     d = info.as_dict()
