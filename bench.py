@@ -39,11 +39,19 @@ HBM_PEAK_GBS = 8000.0
 # dense matrix-core peaks of MI355X, TFLOP/s
 MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 
-# HBM bytes per (working) launch of the default workload's kernels:
-# rocprofv3 FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads for
-# the library's copy kernel over a buffer of known size.  Only kernels whose
-# code has not changed since the counters were taken carry a figure.
-TRAFFIC_BYTES = {}
+# HBM bytes per (working) launch: rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1
+# (the factors that make the counters read the known bytes of the library's
+# copy kernel), per (workload, kernel family, output route, block-iteration
+# type).  Only kernels
+# whose code has not changed since the counters were taken carry a figure
+# (profiles/pmc_traffic_stack128x128x8.md).
+TRAFFIC_BYTES = {
+    ("stack-128x128x8-s32-m5000", "update_dqp", "", "f32"): 97.9e6,
+    ("stack-128x128x8-s32-m5000", "update_w", "", "f32"): 55.7e6,
+    ("stack-128x128x8-s32-m5000", "spmm", "", "f32"): 56.8e6,
+    ("stack-128x128x8-s32-m5000", "apply", "", "f32"): 11497.2e6,
+    ("stack-128x128x8-s32-m5000", "combine", "", "f32"): 5409.7e6,
+}
 
 # one launch in this many of the dominant block-solve kernel carries events
 # in the timed region
@@ -315,7 +323,7 @@ def bench_single(args, config, steps, warmup, headline=False, compute_override=N
         work = working.get(kind) or launches
         # achieved: the family's algorithmic bytes over its kernel time
         gbs = per_launch_bytes[kind] * work / (avg_ms * launches * 1e-3) / 1e9
-        key = (w.name, kind, "one-pass" if (kind == "combine" and fused) else "")
+        key = (w.name, kind, "one-pass" if (kind == "combine" and fused) else "", "f32" if mixed else "f64")
         out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": TRAFFIC_BYTES.get(key), "kernel": kind,
                "launches": launches, "working_launches": work, "timed_launches": timed,
