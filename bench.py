@@ -392,9 +392,11 @@ def bench_single(args, config, steps, warmup, headline=False, compute_override=N
 
 def bench_batched(args, steps, warmup):
     """Batch of uneven chips (64 stacks, 32^2..256^2 x 4..12 layers, s = 16,
-    M = 500 each): one batch plan solves every chip with grouped launches
-    and graph-captured iteration chunks on a side stream, then each chip's
-    combination and operator action.  value = all pairs / step time."""
+    M = 500 each): one batch run per step -- every chip's block solve with
+    grouped launches and graph-captured iteration chunks on a side stream,
+    then one grouped combination and one grouped operator action over all
+    chips (FP64 T and F, F = A T of the T written).  value = all pairs /
+    step time."""
     import torch
 
     from paper_2510_23221_amd import capi, synth
@@ -406,31 +408,28 @@ def bench_batched(args, steps, warmup):
     Bs = [torch.as_tensor(B, device=dev) for B in w.B]
     Cs = [torch.as_tensor(C, device=dev) for C in w.C]
     Xs = [torch.empty_like(B) for B in Bs]
-    nmax = max(c.n for c in w.chips)
-    T = torch.empty((w.m, nmax), dtype=torch.float64, device=dev)
-    F = torch.empty((w.m, nmax), dtype=torch.float64, device=dev)
-    plan = capi.BatchPlan(Gs, w.s, capi.F32)
+    Ts = [torch.empty((w.m, G.n), dtype=torch.float64, device=dev) for G in Gs]
+    Fs = [torch.empty((w.m, G.n), dtype=torch.float64, device=dev) for G in Gs]
+    plan = capi.BatchPlan(Gs, w.s, capi.F32, m=[w.m] * len(Gs))
     stream = torch.cuda.Stream()
     infos = []
-    fused = args.outputs == "one-pass"
-    cwork = torch.empty(capi_bytes_combine_apply(capi, max(Gs, key=lambda G: G.n), w.s) + 256, dtype=torch.uint8,
-                        device=dev) if fused else None
     with torch.cuda.stream(stream):
         tpw = plan.tune(dev, stream=stream)
 
         def step():
-            _, inf = plan.solve(Bs, w.tol, Xs=Xs, stream=stream)
-            for G, X, C in zip(Gs, Xs, Cs):
-                n = G.n
-                if fused:
-                    capi.combine_apply(G, X, C, T=T[:, :n], F=F[:, :n], work=cwork, stream=stream)
-                else:
-                    capi.combine(X, C, T=T[:, :n], stream=stream)
-                    capi.apply_operator(G, T[:, :n], F=F[:, :n], stream=stream)
+            _, _, _, inf = plan.run(Bs, Cs, w.tol, Xs=Xs, Ts=Ts, Fs=Fs, stream=stream)
             infos.append(inf)
 
         for _ in range(warmup):
             step()
+        torch.cuda.synchronize()
+        # census step: every kernel family timed
+        capi.timing_reset()
+        capi.timing_enable(None)
+        step()
+        torch.cuda.synchronize()
+        census = {f: capi.timing_query(f) for f in capi.FAMILY}
+        capi.timing_enable(False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -440,18 +439,37 @@ def bench_batched(args, steps, warmup):
     ms = (t1 - t0) * 1e3 / steps
     pairs = w.m * len(w.chips)
     last = infos[-1]
+    cells = sum(G.n for G in Gs)
+    out_bytes = {"combine": cells * w.m * 8 + cells * w.s * 8 + len(Gs) * w.s * w.m * 8,
+                 "apply": cells * w.m * 16 + cells * 4 * 8}
+
+    def out_roof(kind):
+        n_l, tot = census[kind]
+        if n_l == 0:
+            return None
+        gbs = out_bytes[kind] / (tot / n_l * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "kernel": kind + " (grouped over all chips)",
+                "avg_us": round(tot / n_l * 1e3, 2), "bytes_per_launch": int(out_bytes[kind]), "launches": n_l}
+
+    ty, fpw = plan.output_tuning()
     res = {"metric": "data pairs/s at rel residual <=1e-8, batch of uneven chips", "value": round(pairs / (ms * 1e-3), 1),
            "unit": "pairs/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-           "config": {"workload": w.name, "nchips": len(w.chips), "cells_total": int(sum(c.n for c in w.chips)),
+           "config": {"workload": w.name, "nchips": len(w.chips), "cells_total": int(cells),
                       "s": w.s, "M_per_chip": w.m, "tol": w.tol, "scheme": "mixed", "T_F_dtype": "float64",
-                      "precond": args.precond, "outputs": "one pass" if fused else "two passes"},
-           "autotuned_tiles_per_workgroup": tpw,
+                      "precond": args.precond, "outputs": "grouped: one combination, then F = A T of the T written"},
+           "autotuned": {"tiles_per_workgroup": tpw, "tile_rows_cap": ty, "fields_per_workgroup": fpw},
+           "census_ms_per_step": {k: round(v[1], 3) for k, v in census.items()},
+           "census_launches_per_step": {k: v[0] for k, v in census.items()},
+           "output": out_roof("apply"), "combine": out_roof("combine"),
            "iters": {"min": min(i["iters"] for i in last), "max": max(i["iters"] for i in last),
                      "mean": sum(i["iters"] for i in last) / len(last)},
            "max_rel_res": max(i["max_rel_res"] for i in last),
            "all_ok": all(i["status"] == capi.OK for i in last)}
     plan.close()
+    del Ts, Fs
+    torch.cuda.empty_cache()
     return res
 
 

@@ -221,18 +221,27 @@ typedef struct bko_batch_plan *bko_batch;
 /*
  * A batch of chips solved together: the chip index j of Eq. (4) (Sec. III-A)
  * runs over the batch, each chip with its own operator and grid, all with
- * the same s and inner compute dtype.  Every kernel of a block iteration
- * covers all chips in one launch (a workgroup table maps workgroups to
- * chips), chips that have converged drop out at the next launch, and the
- * iteration chunks between convergence checks are captured into HIP graphs
- * and replayed when the stream is not the null stream.
+ * the same s.  Every kernel of a block iteration covers all chips in one
+ * launch (a workgroup table maps workgroups to chips), chips that have
+ * converged drop out at the next launch, and the iteration chunks between
+ * convergence checks are captured into HIP graphs and replayed when the
+ * stream is not the null stream.
  *   ops   host array of nchips operator handles (they must outlive the plan).
+ *   m     host array of nchips field counts M_c for bko_batch_run (0: no
+ *         fields for that chip), or NULL for a plan that only solves.
+ *   dt    host array of four dtypes: dt[0] the block iteration (BKO_F64, or
+ *         BKO_F32 with FP64 Gram matrices, factorisations and refinement),
+ *         dt[1] the combination's arithmetic (as bko_combine's compute),
+ *         dt[2] the storage type of T, dt[3] that of F.  The operator action
+ *         computes in FP64 when T and F are both FP64, else with FP32
+ *         coefficients and accumulation.
  * The plan holds host metadata only.
  */
-bko_status bko_batch_plan_create(int nchips, const bko_op *ops, int s, bko_dtype compute, bko_batch *out);
+bko_status bko_batch_plan_create(int nchips, const bko_op *ops, int s, const int *m, const bko_dtype dt[4],
+                                 bko_batch *out);
 bko_status bko_batch_plan_destroy(bko_batch plan);
 
-/* Workspace bytes of a batch solve (caller-owned, 256-byte aligned). */
+/* Workspace bytes of a batch solve or run (caller-owned, 256-byte aligned). */
 bko_status bko_batch_workspace_bytes(bko_batch plan, size_t *bytes);
 
 /*
@@ -260,7 +269,33 @@ bko_status bko_batch_solve(bko_batch plan, const double *const *B, const int *ld
                            int max_iter, void *work, size_t work_bytes, bko_solve_info *infos,
                            void *stream);
 
-/* ------------------------------------------- per-sample CG (the baseline) */
+/*
+ * The whole path for every chip of the plan (Sec. III): the basis solutions
+ * A_c X_c = B_c (as bko_batch_solve, zero start), then T_c = X_c C_c
+ * (Sec. III-B, Eq. (5)) for every chip in one grouped combination launch,
+ * then F_c = A_c T_c of the T written (Sec. III-C, Eq. (6)) for every chip
+ * in one grouped operator-action launch (chips whose rows are not a whole
+ * number of 16-byte vectors, or whose views are not 16-byte aligned, get an
+ * operator-action launch of their own).  Host arrays of nchips device
+ * pointers: B, X (n_c x s FP64, ldb, ldx >= n_c), C (s x M_c FP64,
+ * ldc >= s: column j holds field j's weights), T (n_c x M_c of dt[2],
+ * ldt >= n_c), F (n_c x M_c of dt[3], ldf >= n_c, not overlapping T).  On
+ * the plan's first run the grouped launches' knobs (the combination's fields
+ * per workgroup, the operator action's tile height) are chosen by timing a
+ * few candidates on these outputs, and cached for the device architecture
+ * and batch shape.  The outputs are written even when a chip does not
+ * converge (its X is the last iterate); the return value is the solve's.
+ * infos as for bko_batch_solve.  Synchronises the stream.
+ */
+bko_status bko_batch_run(bko_batch plan, const double *const *B, const int *ldb, double *const *X, const int *ldx,
+                         const double *const *C, const int *ldc, void *const *T, const int *ldt, void *const *F,
+                         const int *ldf, double tol, int max_iter, void *work, size_t work_bytes,
+                         bko_solve_info *infos, void *stream);
+
+/* The output knobs bko_batch_run chose (host; -1 before the first run): the
+ * cap on the operator action's tile height (0: the kernel's full height)
+ * and the combination's fields per workgroup (0: the launcher's rule). */
+bko_status bko_batch_output_tuning(bko_batch plan, int *tile_rows_cap, int64_t *fields_per_wg);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph
@@ -279,6 +314,8 @@ bko_status bko_batch_solve(bko_batch plan, const double *const *B, const int *ld
 bko_status bko_block_krylov_solve_noalloc(bko_op A, int s, const double *B, int ldb, double *X, int ldx,
                                           const double *X0, int ldx0, bko_dtype compute, double tol, int max_iter,
                                           bko_solve_info *info, void *stream);
+
+/* ------------------------------------------- per-sample CG (the baseline) */
 
 /* Workspace bytes for bko_cg_solve with m right-hand sides. */
 bko_status bko_cg_workspace_bytes(bko_op A, int m, size_t *bytes);

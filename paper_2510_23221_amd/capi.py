@@ -51,7 +51,7 @@ EXPORTED = ("bko_version", "bko_last_error", "bko_operator_bytes", "bko_assemble
             "bko_operator_get_precond", "bko_timing_set_stride", "bko_combine_apply_workspace_bytes",
             "bko_combine_apply", "bko_combine_noisy", "bko_noise_fill", "bko_normalize_weights",
             "bko_boundary_source", "bko_add_column", "bko_apply_operator_tiling",
-            "bko_copy", "bko_block_krylov_solve_noalloc")
+            "bko_copy", "bko_block_krylov_solve_noalloc", "bko_batch_run", "bko_batch_output_tuning")
 
 
 class BlockoaError(RuntimeError):
@@ -99,7 +99,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bko_timing_query": (i32, [i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
         "bko_timing_reset": (i32, []),
         "bko_cg_workspace_bytes": (i32, [vp, i32, ctypes.POINTER(sz)]),
-        "bko_batch_plan_create": (i32, [i32, ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp)]),
+        "bko_batch_plan_create": (i32, [i32, ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                        ctypes.POINTER(vp)]),
+        "bko_batch_run": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(i32),
+                                ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(i32),
+                                ctypes.POINTER(vp), ctypes.POINTER(i32), dbl, i32, vp, sz, ctypes.POINTER(SolveInfo),
+                                vp]),
+        "bko_batch_output_tuning": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]),
         "bko_batch_plan_destroy": (i32, [vp]),
         "bko_nn_conv2d": (i32, [vp, i32, vp, i32, i32, i32, i32, i32, i32, i32, vp, i32, vp, vp, i32, vp]),
         "bko_nn_wgrad_work_floats": (sz, [i32, i32, i32, i32, i32, i32]),
@@ -341,18 +347,27 @@ def block_krylov_solve_noalloc(A: HeatOperator, B: torch.Tensor, tol: float, com
 
 
 class BatchPlan:
-    """A batch of chips solved together (one s and compute dtype for all):
-    grouped launches over every chip, graph-captured iteration chunks on a
-    non-null stream, per-chip workgroup counts chosen by the autotuner."""
+    """A batch of chips solved together (one s for all): grouped launches
+    over every chip, graph-captured iteration chunks on a non-null stream,
+    per-chip workgroup counts chosen by the autotuner.  With per-chip field
+    counts ``m`` the plan also runs the outputs (``run``): one grouped
+    combination and one grouped operator action over all chips, in the
+    dtypes ``comb_compute`` (arithmetic of T = X C), ``t_dtype`` and
+    ``f_dtype`` (storage of T and F)."""
 
-    def __init__(self, ops: Sequence[HeatOperator], s: int, compute: int = F64):
+    def __init__(self, ops: Sequence[HeatOperator], s: int, compute: int = F64, m: Optional[Sequence[int]] = None,
+                 comb_compute: int = F64, t_dtype=torch.float64, f_dtype=torch.float64):
         lib = load_library()
         self.ops = list(ops)
         self.s = s
         self.compute = compute
+        self.m = None if m is None else [int(v) for v in m]
+        self.t_dtype, self.f_dtype = t_dtype, f_dtype
         arr = (ctypes.c_void_p * len(self.ops))(*[o.handle.value for o in self.ops])
+        marr = None if self.m is None else (ctypes.c_int * len(self.ops))(*self.m)
+        dt = (ctypes.c_int * 4)(compute, comb_compute, DTYPE_CODE[t_dtype], DTYPE_CODE[f_dtype])
         h = ctypes.c_void_p()
-        _check(lib.bko_batch_plan_create(len(self.ops), arr, s, compute, ctypes.byref(h)))
+        _check(lib.bko_batch_plan_create(len(self.ops), arr, s, marr, dt, ctypes.byref(h)))
         self.handle = h
         self._work = None
 
@@ -419,6 +434,65 @@ class BatchPlan:
             d["status_name"] = STATUS_NAMES.get(d["status"], str(d["status"]))
             out.append(d)
         return Xs, out
+
+    def run(self, Bs: Sequence[torch.Tensor], Cs: Sequence[torch.Tensor], tol: float, Xs=None, Ts=None, Fs=None,
+            max_iter: int = 100000, stream=None, check: bool = True):
+        """The whole path for every chip: Bs (s, N_c) FP64, Cs (M_c, s) FP64
+        (row j holds field j's weights); returns (Xs, Ts, Fs, infos) with
+        T, F of shape (M_c, N_c)."""
+        nc = len(self.ops)
+        if self.m is None:
+            raise ValueError("the plan was created without field counts")
+        if len(Bs) != nc or len(Cs) != nc:
+            raise ValueError("one right-hand-side block and one weight block per chip")
+        dev = Bs[0].device
+        if Xs is None:
+            Xs = [torch.empty_like(b) for b in Bs]
+        if Ts is None:
+            Ts = [torch.empty((mc, o.n), dtype=self.t_dtype, device=dev) for mc, o in zip(self.m, self.ops)]
+        if Fs is None:
+            Fs = [torch.empty((mc, o.n), dtype=self.f_dtype, device=dev) for mc, o in zip(self.m, self.ops)]
+        cols = {k: ([], []) for k in "BXCTF"}
+        for k, arrs, name in (("B", Bs, "B"), ("X", Xs, "X"), ("T", Ts, "T"), ("F", Fs, "F")):
+            for t in arrs:
+                if t.shape[0] == 0:
+                    cols[k][0].append(None)
+                    cols[k][1].append(t.shape[1])
+                    continue
+                p, ld, _ = _block(t, name)
+                cols[k][0].append(p.value)
+                cols[k][1].append(ld)
+        for c, mc in zip(Cs, self.m):
+            if mc == 0:  # no fields: C is not read
+                cols["C"][0].append(None)
+                cols["C"][1].append(self.s)
+                continue
+            if c.dtype != torch.float64 or c.dim() != 2 or tuple(c.shape) != (mc, self.s) or c.stride(1) != 1 \
+                    or not c.is_cuda:
+                raise ValueError("C must be an (M_c, s) float64 GPU tensor with contiguous rows")
+            cols["C"][0].append(c.data_ptr())
+            cols["C"][1].append(max(c.stride(0), self.s))
+        VP, I32 = ctypes.c_void_p * nc, ctypes.c_int * nc
+        arg = {k: (VP(*v[0]), I32(*v[1])) for k, v in cols.items()}
+        ptr, nbytes = self._workspace(dev)
+        infos = (SolveInfo * nc)()
+        st = load_library().bko_batch_run(self.handle, *arg["B"], *arg["X"], *arg["C"], *arg["T"], *arg["F"], tol,
+                                          max_iter, ctypes.c_void_p(ptr), nbytes, infos, _stream(stream))
+        if check and st != OK:
+            _check(st)
+        out = []
+        for i in infos:
+            d = i.as_dict()
+            d["status_name"] = STATUS_NAMES.get(d["status"], str(d["status"]))
+            out.append(d)
+        return Xs, Ts, Fs, out
+
+    def output_tuning(self):
+        """(tile height cap, fields per workgroup) chosen on the first run
+        (-1, -1 before it)."""
+        ty, fpw = ctypes.c_int(), ctypes.c_int64()
+        _check(load_library().bko_batch_output_tuning(self.handle, ctypes.byref(ty), ctypes.byref(fpw)))
+        return ty.value, fpw.value
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -2568,9 +2568,20 @@ bko_status block_solve(const Operator &op, int s, const double *B, int64_t ldb, 
     return batch_solve_t<float>(L, work, Bs, lb, Xs, lx, X0s, lx0, tol, max_iter, info, st, nullptr);
 }
 
-size_t batch_workspace_bytes(const BatchPlan &p)
+size_t batch_solve_bytes(const BatchPlan &p)
 {
     return make_layout(p.ops.data(), static_cast<int>(p.ops.size()), p.s, p.compute, 1).bytes;
+}
+
+size_t batch_workspace_bytes(const BatchPlan &p)
+{
+    size_t b = batch_solve_bytes(p);
+    if (!p.m.empty()) {
+        const int nc = static_cast<int>(p.ops.size());
+        b = align_up(b + stencil_group_job_bytes(nc), 256);
+        b = align_up(b + combine_group_job_bytes(nc), 256);
+    }
+    return b;
 }
 
 namespace {

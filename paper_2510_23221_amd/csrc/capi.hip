@@ -771,19 +771,28 @@ bko_status bko_cg_solve(bko_op A, int m, const double *B, int ldb, double *X, in
     BKO_GUARD_END
 }
 
-bko_status bko_batch_plan_create(int nchips, const bko_op *ops, int s, bko_dtype compute, bko_batch *out)
+bko_status bko_batch_plan_create(int nchips, const bko_op *ops, int s, const int *m, const bko_dtype dt[4],
+                                 bko_batch *out)
 {
     BKO_GUARD_BEGIN
-    BKO_CHECK(out != nullptr && ops != nullptr, "NULL argument");
+    BKO_CHECK(out != nullptr && ops != nullptr && dt != nullptr, "NULL argument");
     *out = nullptr;
     BKO_CHECK(nchips >= 1 && nchips <= 65535, "nchips = %d outside [1, 65535]", nchips);
     BKO_CHECK(s >= 1 && s <= 64, "s = %d outside [1, 64]", s);
-    BKO_CHECK(compute == BKO_F64 || compute == BKO_F32, "compute must be BKO_F64 or BKO_F32");
+    BKO_CHECK(dt[0] == BKO_F64 || dt[0] == BKO_F32, "dt[0] (block iteration) must be BKO_F64 or BKO_F32");
+    BKO_CHECK(valid_dtype(dt[1]) && valid_dtype(dt[2]) && valid_dtype(dt[3]), "bad output dtype");
     for (int c = 0; c < nchips; ++c) BKO_CHECK(ops[c] != nullptr, "operator %d is NULL", c);
+    if (m)
+        for (int c = 0; c < nchips; ++c) BKO_CHECK(m[c] >= 0, "m of chip %d is negative", c);
     BatchPlan *p = new BatchPlan();
     p->s = s;
-    p->compute = compute;
+    p->compute = dt[0];
+    p->comb_compute = dt[1];
+    p->t_dtype = dt[2];
+    p->f_dtype = dt[3];
+    p->apply_compute = (dt[2] == BKO_F64 && dt[3] == BKO_F64) ? BKO_F64 : BKO_F32;
     for (int c = 0; c < nchips; ++c) p->ops.push_back(reinterpret_cast<const Operator *>(ops[c]));
+    if (m) p->m.assign(m, m + nchips);
     *out = reinterpret_cast<bko_batch>(p);
     return BKO_OK;
     BKO_GUARD_END
@@ -859,6 +868,209 @@ bko_status bko_batch_solve(bko_batch plan, const double *const *B, const int *ld
     return batch_solve(p, B, lb.data(), X, lx.data(), X0, lx0.data(), tol, max_iter, work, infos,
                        static_cast<hipStream_t>(stream));
     BKO_GUARD_END
+}
+
+}  // extern "C"
+
+// Output knobs chosen by timing, per device architecture and batch shape
+// bucket (chips, total cells to a power of two, largest field count, s and
+// the dtypes), shared by every plan of the process.
+static std::mutex g_out_tune_mu;
+static std::map<std::string, std::pair<int, int64_t>> g_out_tune_cache;
+
+static std::string out_tune_key(const BatchPlan &p)
+{
+    hipDeviceProp_t prop{};
+    int dev = 0;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    int64_t cells = 0;
+    int mmax = 0;
+    for (size_t c = 0; c < p.ops.size(); ++c) {
+        cells += p.ops[c]->n;
+        mmax = std::max(mmax, p.m[c]);
+    }
+    int lg = 0;
+    while ((int64_t(1) << lg) < cells) ++lg;
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s|%zu|%d|%d|%d|%d%d%d", arch.c_str(), p.ops.size(), lg, mmax, p.s,
+                  static_cast<int>(p.comb_compute), static_cast<int>(p.t_dtype), static_cast<int>(p.f_dtype));
+    return buf;
+}
+
+namespace {
+
+struct OutArgs {
+    std::vector<int64_t> n, lx, lc, lt, lf;
+    const double *const *X;
+    const double *const *C;
+    void *const *T;
+    void *const *F;
+    void *sjobs, *cjobs;
+    std::vector<unsigned char> hs, hc;  // host job tables, alive until the stream has passed the launches
+};
+
+bko_status out_combine(BatchPlan &p, OutArgs &a, int64_t fpw, hipStream_t st)
+{
+    return launch_combine_group(static_cast<int>(p.ops.size()), a.n.data(), p.s, p.m.data(), a.X, a.lx.data(), a.C,
+                                a.lc.data(), a.T, a.lt.data(), p.t_dtype, p.comb_compute, fpw, a.cjobs, a.hc, st);
+}
+
+bko_status out_apply(BatchPlan &p, OutArgs &a, int ty_cap, hipStream_t st)
+{
+    return launch_stencil_group(p.ops.data(), static_cast<int>(p.ops.size()), p.m.data(),
+                                reinterpret_cast<const void *const *>(a.T), a.lt.data(), p.t_dtype, a.F, a.lf.data(),
+                                p.f_dtype, p.apply_compute, ty_cap, a.sjobs, a.hs, st);
+}
+
+// Milliseconds of one launch of fn (after one untimed launch).
+template <class Fn>
+bko_status time_once(Fn fn, hipStream_t st, float &ms)
+{
+    bko_status rc = fn();
+    if (rc != BKO_OK) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BKO_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(hipErrorOutOfMemory, "hipEventCreate");
+    }
+    bool ok = hipEventRecord(e0, st) == hipSuccess;
+    rc = fn();
+    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != BKO_OK) return rc;
+    if (!ok) return hip_fail(hipErrorUnknown, "output timing events");
+    return BKO_OK;
+}
+
+// First run of a plan: the tile height cap of the grouped operator action
+// and the fields per workgroup of the grouped combination, each picked
+// from a few candidates by timing them on the call's own outputs (every
+// candidate writes the same T and F).
+bko_status tune_outputs(BatchPlan &p, OutArgs &a, hipStream_t st)
+{
+    const std::string key = out_tune_key(p);
+    {
+        std::lock_guard<std::mutex> lock(g_out_tune_mu);
+        auto it = g_out_tune_cache.find(key);
+        if (it != g_out_tune_cache.end()) {
+            p.out_ty_cap = it->second.first;
+            p.out_fields_per_wg = it->second.second;
+            p.out_tuned = true;
+            return BKO_OK;
+        }
+    }
+    p.out_tune_ms.clear();
+    bko_status rc;
+    float best = 0.f;
+    int64_t best_fpw = 0;
+    for (int64_t fpw : {int64_t(0), int64_t(64), int64_t(256)}) {
+        float ms = 0.f;
+        if ((rc = time_once([&] { return out_combine(p, a, fpw, st); }, st, ms)) != BKO_OK) return rc;
+        p.out_tune_ms.emplace_back("fields_per_wg=" + std::to_string(fpw), ms);
+        if (fpw == 0 || ms < best) best = ms, best_fpw = fpw;
+    }
+    int best_ty = 0;
+    for (int ty : {0, 16, 8}) {
+        float ms = 0.f;
+        if ((rc = time_once([&] { return out_apply(p, a, ty, st); }, st, ms)) != BKO_OK) return rc;
+        p.out_tune_ms.emplace_back("tile_rows_cap=" + std::to_string(ty), ms);
+        if (ty == 0 || ms < best) best = ms, best_ty = ty;
+    }
+    p.out_ty_cap = best_ty;
+    p.out_fields_per_wg = best_fpw;
+    p.out_tuned = true;
+    std::lock_guard<std::mutex> lock(g_out_tune_mu);
+    g_out_tune_cache[key] = {best_ty, best_fpw};
+    return BKO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bko_status bko_batch_run(bko_batch plan, const double *const *B, const int *ldb, double *const *X, const int *ldx,
+                         const double *const *C, const int *ldc, void *const *T, const int *ldt, void *const *F,
+                         const int *ldf, double tol, int max_iter, void *work, size_t work_bytes,
+                         bko_solve_info *infos, void *stream)
+{
+    BKO_GUARD_BEGIN
+    BKO_CHECK(plan != nullptr, "NULL plan");
+    BatchPlan &p = *reinterpret_cast<BatchPlan *>(plan);
+    const int nc = static_cast<int>(p.ops.size());
+    BKO_CHECK(!p.m.empty(), "the plan was created without field counts (m = NULL): use bko_batch_solve");
+    BKO_CHECK(B && ldb && X && ldx && C && ldc && T && ldt && F && ldf, "NULL array table");
+    BKO_CHECK(tol > 0.0 && std::isfinite(tol), "tol must be positive");
+    BKO_CHECK(max_iter >= 1, "max_iter must be >= 1");
+    OutArgs a;
+    a.n.resize(nc);
+    a.lx.resize(nc);
+    a.lc.resize(nc);
+    a.lt.resize(nc);
+    a.lf.resize(nc);
+    std::vector<int64_t> lb(nc), lx0(nc, 0);
+    const size_t wt = dtype_size(p.t_dtype), wf = dtype_size(p.f_dtype);
+    for (int c = 0; c < nc; ++c) {
+        const int64_t n = p.ops[c]->n;
+        const int mc = p.m[c];
+        BKO_CHECK(B[c] && X[c], "NULL array of chip %d", c);
+        BKO_CHECK(ldb[c] >= n && ldx[c] >= n, "leading dimensions of chip %d must be >= n", c);
+        if (mc > 0) {
+            BKO_CHECK(C[c] && T[c] && F[c], "NULL output array of chip %d", c);
+            BKO_CHECK(ldc[c] >= p.s && ldt[c] >= n && ldf[c] >= n, "output leading dimensions of chip %d", c);
+            const char *t0 = static_cast<const char *>(T[c]), *f0 = static_cast<const char *>(F[c]);
+            const char *t1 = t0 + wt * (static_cast<size_t>(ldt[c]) * (mc - 1) + n);
+            const char *f1 = f0 + wf * (static_cast<size_t>(ldf[c]) * (mc - 1) + n);
+            BKO_CHECK(t1 <= f0 || f1 <= t0, "T and F of chip %d overlap", c);
+        }
+        a.n[c] = n;
+        lb[c] = ldb[c];
+        a.lx[c] = ldx[c];
+        a.lc[c] = ldc[c];
+        a.lt[c] = ldt[c];
+        a.lf[c] = ldf[c];
+    }
+    bko_status rc = check_batch_work(p, work, work_bytes);
+    if (rc != BKO_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // basis solutions of every chip (Sec. III-A, Eq. (4))
+    const bko_status solved = batch_solve(p, B, lb.data(), X, a.lx.data(), nullptr, lx0.data(), tol, max_iter, work,
+                                          infos, st);
+    if (solved != BKO_OK && solved != BKO_ENOCONV && solved != BKO_EBREAKDOWN) return solved;
+    // T = X C (Sec. III-B, Eq. (5)) and F = A T (Sec. III-C, Eq. (6)) of
+    // every chip: one grouped combination, then one grouped operator action
+    // of the T written
+    char *tables = static_cast<char *>(work) + batch_solve_bytes(p);
+    a.sjobs = tables;
+    a.cjobs = tables + align_up(stencil_group_job_bytes(nc), 256);
+    a.X = X;
+    a.C = C;
+    a.T = T;
+    a.F = F;
+    if (!p.out_tuned && (rc = tune_outputs(p, a, st)) != BKO_OK) return rc;
+    {
+        TimedLaunch tl(kCombine, st);
+        if ((rc = out_combine(p, a, p.out_fields_per_wg, st)) != BKO_OK) return rc;
+    }
+    {
+        TimedLaunch tl(kApply, st);
+        if ((rc = out_apply(p, a, p.out_ty_cap, st)) != BKO_OK) return rc;
+    }
+    BKO_HIP(hipStreamSynchronize(st));
+    return solved;  // the solve's message stays the last error when it is not BKO_OK
+    BKO_GUARD_END
+}
+
+bko_status bko_batch_output_tuning(bko_batch plan, int *tile_rows_cap, int64_t *fields_per_wg)
+{
+    BKO_CHECK(plan != nullptr, "NULL plan");
+    const BatchPlan &p = *reinterpret_cast<const BatchPlan *>(plan);
+    if (tile_rows_cap) *tile_rows_cap = p.out_tuned ? p.out_ty_cap : -1;
+    if (fields_per_wg) *fields_per_wg = p.out_tuned ? p.out_fields_per_wg : -1;
+    return BKO_OK;
 }
 
 // ------------------------------------------------------------------ learned start

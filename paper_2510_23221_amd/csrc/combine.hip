@@ -15,7 +15,9 @@
 // L / 16; its four results are D[mfma_row(L / 16, r)][L % 16] (see
 // common.hpp: the FP64 shape interleaves the rows).
 #include <algorithm>
+#include <cstring>
 #include <type_traits>
+#include <vector>
 
 #include "kernels.hpp"
 
@@ -53,11 +55,9 @@ template <> struct ModeTraits<kBF16> {
 __device__ inline __bf16 bits_to_bf(uint16_t b) { return __builtin_bit_cast(__bf16, b); }
 
 template <int kMode, class Tx, class Tc, class Tt>
-__global__ __launch_bounds__(kThreads) void combine_kernel(int64_t n, int s, int64_t m,
-                                                           const Tx *__restrict__ X, int64_t ldx,
-                                                           const Tc *__restrict__ C, int64_t ldc,
-                                                           Tt *__restrict__ T, int64_t ldt,
-                                                           int64_t fields_per_wg, uint32_t ntiles, int vec_ok)
+__device__ __forceinline__ void combine_body(uint32_t bid, int64_t n, int s, int64_t m, const Tx *__restrict__ X,
+                                             int64_t ldx, const Tc *__restrict__ C, int64_t ldc, Tt *__restrict__ T,
+                                             int64_t ldt, int64_t fields_per_wg, uint32_t ntiles, int vec_ok)
 {
     using TR = ModeTraits<kMode>;
     using Acc = typename TR::Acc;
@@ -75,8 +75,8 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(int64_t n, int s, int
     Stage *Cs = reinterpret_cast<Stage *>(smem);
     Acc *Os = reinterpret_cast<Acc *>(smem);
 
-    const uint32_t tile = blockIdx.x % ntiles;
-    const uint32_t split = blockIdx.x / ntiles;
+    const uint32_t tile = bid % ntiles;
+    const uint32_t split = bid / ntiles;
     const int64_t cell0 = static_cast<int64_t>(tile) * kTM;
     const int64_t f_begin = static_cast<int64_t>(split) * fields_per_wg;
     const int64_t f_end = min(m, f_begin + fields_per_wg);
@@ -190,6 +190,47 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(int64_t n, int s, int
     }
 }
 
+template <int kMode, class Tx, class Tc, class Tt>
+__global__ __launch_bounds__(kThreads) void combine_kernel(int64_t n, int s, int64_t m,
+                                                           const Tx *__restrict__ X, int64_t ldx,
+                                                           const Tc *__restrict__ C, int64_t ldc,
+                                                           Tt *__restrict__ T, int64_t ldt,
+                                                           int64_t fields_per_wg, uint32_t ntiles, int vec_ok)
+{
+    combine_body<kMode, Tx, Tc, Tt>(blockIdx.x, n, s, m, X, ldx, C, ldc, T, ldt, fields_per_wg, ntiles, vec_ok);
+}
+
+// One chip's share of a grouped combination: workgroups [block0, block0 +
+// ntiles * splits) of the grid.
+struct CombineJob {
+    const double *X;
+    const double *C;
+    void *T;
+    int64_t ldx, ldc, ldt, n, m, fields_per_wg;
+    uint32_t ntiles, block0;
+    int vec_ok, pad;
+};
+
+__device__ __forceinline__ const CombineJob &find_job(const CombineJob *__restrict__ jobs, int njobs, uint32_t g)
+{
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (jobs[mid].block0 <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return jobs[lo];
+}
+
+// The combination of every chip of a batch in one grid (FP32 / BF16 modes).
+template <int kMode, class Tt>
+__global__ __launch_bounds__(kThreads) void combine_group_kernel(const CombineJob *__restrict__ jobs, int njobs, int s)
+{
+    const CombineJob &j = find_job(jobs, njobs, blockIdx.x);
+    combine_body<kMode, double, double, Tt>(blockIdx.x - j.block0, j.n, s, j.m, j.X, j.ldx, j.C, j.ldc,
+                                            static_cast<Tt *>(j.T), j.ldt, j.fields_per_wg, j.ntiles, j.vec_ok);
+}
+
 // ---------------------------------------------------------------- noise
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
@@ -290,17 +331,16 @@ __global__ __launch_bounds__(kThreads) void normalize_weights_kernel(int s, int6
 // kDual: also F = Y C with Y = A X, the operator action of every field
 // formed from the s columns of A X (Sec. III-C applied to Eq. (5)'s sum).
 template <bool kDual, bool kNoise, int kMaxKS>
-__global__ __launch_bounds__(kThreads) void combine_direct_kernel(int64_t n, int s, int64_t m,
-                                                                  const double *__restrict__ X, int64_t ldx,
-                                                                  const double *__restrict__ Y, int64_t ldy,
-                                                                  const double *__restrict__ C, int64_t ldc,
-                                                                  double *__restrict__ T, int64_t ldt,
-                                                                  double *__restrict__ F, int64_t ldf,
-                                                                  int64_t fields_per_wg, uint32_t ntiles, NoiseArgs na)
+__device__ __forceinline__ void combine_direct_body(uint32_t bid, int64_t n, int s, int64_t m,
+                                                    const double *__restrict__ X, int64_t ldx,
+                                                    const double *__restrict__ Y, int64_t ldy,
+                                                    const double *__restrict__ C, int64_t ldc,
+                                                    double *__restrict__ T, int64_t ldt, double *__restrict__ F,
+                                                    int64_t ldf, int64_t fields_per_wg, uint32_t ntiles, NoiseArgs na)
 {
     const int ks = (s + 3) / 4;  // <= kMaxKS
-    const uint32_t tile = blockIdx.x % ntiles;
-    const uint32_t split = blockIdx.x / ntiles;
+    const uint32_t tile = bid % ntiles;
+    const uint32_t split = bid / ntiles;
     const int64_t f_begin = static_cast<int64_t>(split) * fields_per_wg;
     const int64_t f_end = min(m, f_begin + fields_per_wg);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -374,6 +414,30 @@ __global__ __launch_bounds__(kThreads) void combine_direct_kernel(int64_t n, int
         __syncthreads();
         b ^= 1;
     }
+}
+
+template <bool kDual, bool kNoise, int kMaxKS>
+__global__ __launch_bounds__(kThreads) void combine_direct_kernel(int64_t n, int s, int64_t m,
+                                                                  const double *__restrict__ X, int64_t ldx,
+                                                                  const double *__restrict__ Y, int64_t ldy,
+                                                                  const double *__restrict__ C, int64_t ldc,
+                                                                  double *__restrict__ T, int64_t ldt,
+                                                                  double *__restrict__ F, int64_t ldf,
+                                                                  int64_t fields_per_wg, uint32_t ntiles, NoiseArgs na)
+{
+    combine_direct_body<kDual, kNoise, kMaxKS>(blockIdx.x, n, s, m, X, ldx, Y, ldy, C, ldc, T, ldt, F, ldf,
+                                               fields_per_wg, ntiles, na);
+}
+
+// The FP64 combination of every chip of a batch in one grid.
+template <int kMaxKS>
+__global__ __launch_bounds__(kThreads) void combine_direct_group_kernel(const CombineJob *__restrict__ jobs, int njobs,
+                                                                        int s)
+{
+    const CombineJob &j = find_job(jobs, njobs, blockIdx.x);
+    combine_direct_body<false, false, kMaxKS>(blockIdx.x - j.block0, j.n, s, j.m, j.X, j.ldx, nullptr, 0, j.C, j.ldc,
+                                              static_cast<double *>(j.T), j.ldt, nullptr, 0, j.fields_per_wg, j.ntiles,
+                                              NoiseArgs{BKO_NOISE_NONE, 0.0, 0, 0});
 }
 
 // Grid of the combination kernels: 64-cell tiles, the fields split so that
@@ -493,6 +557,33 @@ bko_status by_x(int64_t n, int s, int64_t m, const void *X, int64_t ldx, bko_dty
     }
 }
 
+template <int kMode, class Tt>
+bko_status run_group(const std::vector<CombineJob> &jobs, uint32_t total, int s, const void *jobs_dev,
+                     hipStream_t stream)
+{
+    using TR = ModeTraits<kMode>;
+    const int ksteps = (s + TR::kK - 1) / TR::kK;
+    const int s_pad = ksteps * TR::kK;
+    const int cstride = kMode == kBF16 ? s_pad + 8 : s_pad + 1;
+    const int ostride = kTM + (sizeof(typename TR::Acc) == 8 ? 2 : 4);
+    const size_t smem = std::max(sizeof(typename TR::Stage) * kTN * cstride, sizeof(typename TR::Acc) * kTN * ostride);
+    hipLaunchKernelGGL((combine_group_kernel<kMode, Tt>), dim3(total), dim3(kThreads), smem, stream,
+                       static_cast<const CombineJob *>(jobs_dev), static_cast<int>(jobs.size()), s);
+    BKO_HIP(hipGetLastError());
+    return BKO_OK;
+}
+
+template <int kMode>
+bko_status group_by_out(const std::vector<CombineJob> &jobs, uint32_t total, int s, const void *jobs_dev,
+                        bko_dtype t_t, hipStream_t stream)
+{
+    switch (t_t) {
+    case BKO_F64: return run_group<kMode, double>(jobs, total, s, jobs_dev, stream);
+    case BKO_F32: return run_group<kMode, float>(jobs, total, s, jobs_dev, stream);
+    default: return run_group<kMode, bf16>(jobs, total, s, jobs_dev, stream);
+    }
+}
+
 }  // namespace
 
 bko_status launch_combine(int64_t n, int s, int64_t m, const void *X, int64_t ldx, bko_dtype x_t, const void *C,
@@ -543,6 +634,79 @@ bko_status launch_normalize_weights(int s, int64_t m, double *C, int64_t ldc, do
                        dim3(kThreads), 0, stream, s, m, C, ldc, min_abs, flags);
     BKO_HIP(hipGetLastError());
     return BKO_OK;
+}
+
+size_t combine_group_job_bytes(int nchips) { return sizeof(CombineJob) * static_cast<size_t>(nchips); }
+
+bko_status launch_combine_group(int nchips, const int64_t *n, int s, const int *m, const double *const *X,
+                                const int64_t *ldx, const double *const *C, const int64_t *ldc, void *const *T,
+                                const int64_t *ldt, bko_dtype t_t, bko_dtype compute, int64_t fields_per_wg,
+                                void *jobs_dev, std::vector<unsigned char> &host_jobs, hipStream_t stream)
+{
+    int64_t mmax = 0, tiles = 0;
+    for (int c = 0; c < nchips; ++c) {
+        mmax = std::max<int64_t>(mmax, m[c]);
+        if (m[c] > 0) tiles += (n[c] + kTM - 1) / kTM;
+    }
+    if (mmax == 0) return BKO_OK;
+    // fields per workgroup: all of a chip's fields in one workgroup per
+    // tile, halved (in whole 64-field steps) until the grid has a few
+    // thousand workgroups; fields_per_wg > 0 fixes it
+    int64_t fpw = fields_per_wg;
+    if (fpw <= 0) {
+        fpw = (mmax + kTN - 1) / kTN * kTN;
+        while (fpw > kTN) {
+            int64_t total = 0;
+            for (int c = 0; c < nchips; ++c)
+                if (m[c] > 0) total += ((n[c] + kTM - 1) / kTM) * ((m[c] + fpw - 1) / fpw);
+            if (total >= 8192) break;
+            fpw = std::max<int64_t>(kTN, (fpw / 2 + kTN - 1) / kTN * kTN);
+        }
+    }
+    std::vector<CombineJob> jobs;
+    uint64_t total = 0;
+    for (int c = 0; c < nchips; ++c) {
+        if (m[c] <= 0) continue;
+        CombineJob j{};
+        j.X = X[c];
+        j.C = C[c];
+        j.T = T[c];
+        j.ldx = ldx[c];
+        j.ldc = ldc[c];
+        j.ldt = ldt[c];
+        j.n = n[c];
+        j.m = m[c];
+        j.fields_per_wg = fpw;
+        j.ntiles = static_cast<uint32_t>((n[c] + kTM - 1) / kTM);
+        j.block0 = static_cast<uint32_t>(total);
+        j.vec_ok = (reinterpret_cast<uintptr_t>(T[c]) % 16 == 0) && ((ldt[c] * dtype_size(t_t)) % 16 == 0);
+        total += static_cast<uint64_t>(j.ntiles) * ((m[c] + fpw - 1) / fpw);
+        jobs.push_back(j);
+    }
+    if (total > 0x7fffffffu) {
+        set_error("grouped combination of %llu workgroups too large", (unsigned long long)total);
+        return BKO_EINVAL;
+    }
+    const size_t bytes = sizeof(CombineJob) * jobs.size();
+    host_jobs.resize(bytes);
+    std::memcpy(host_jobs.data(), jobs.data(), bytes);
+    BKO_HIP(hipMemcpyAsync(jobs_dev, host_jobs.data(), bytes, hipMemcpyHostToDevice, stream));
+    const uint32_t tot = static_cast<uint32_t>(total);
+    const auto *jd = static_cast<const CombineJob *>(jobs_dev);
+    const int njobs = static_cast<int>(jobs.size());
+    if (compute == BKO_F64 && t_t == BKO_F64) {
+        const int ks = (s + 3) / 4;
+        if (ks <= 4) hipLaunchKernelGGL((combine_direct_group_kernel<4>), dim3(tot), dim3(kThreads), 0, stream, jd, njobs, s);
+        else if (ks <= 8) hipLaunchKernelGGL((combine_direct_group_kernel<8>), dim3(tot), dim3(kThreads), 0, stream, jd, njobs, s);
+        else hipLaunchKernelGGL((combine_direct_group_kernel<16>), dim3(tot), dim3(kThreads), 0, stream, jd, njobs, s);
+        BKO_HIP(hipGetLastError());
+        return BKO_OK;
+    }
+    switch (compute) {
+    case BKO_F64: return group_by_out<kF64>(jobs, tot, s, jobs_dev, t_t, stream);
+    case BKO_F32: return group_by_out<kF32>(jobs, tot, s, jobs_dev, t_t, stream);
+    default: return group_by_out<kBF16>(jobs, tot, s, jobs_dev, t_t, stream);
+    }
 }
 
 }  // namespace bko

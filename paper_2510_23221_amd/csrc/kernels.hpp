@@ -2,6 +2,7 @@
 #pragma once
 
 #include <map>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -15,6 +16,16 @@ bko_status launch_stencil(const Operator &op, int m, const void *X, int64_t ldx,
                           void *Y, int64_t ldy, bko_dtype t_out, bko_dtype compute,
                           const double *Bres, int64_t ldb, hipStream_t stream, const int *skip = nullptr,
                           int *stop = nullptr);
+// The operator action of several chips in one grouped launch (chips whose
+// rows or views do not suit the tiled kernel get a launch of their own).
+// m[c] fields of chip c; jobs_dev: stencil_group_job_bytes(nchips) bytes of
+// device memory for the job table, copied from host_jobs (which must live
+// until the stream has passed the launch).  ty_cap > 0 caps the tile height.
+size_t stencil_group_job_bytes(int nchips);
+bko_status launch_stencil_group(const Operator *const *ops, int nchips, const int *m, const void *const *X,
+                                const int64_t *ldx, bko_dtype t_in, void *const *Y, const int64_t *ldy,
+                                bko_dtype t_out, bko_dtype compute, int ty_cap, void *jobs_dev,
+                                std::vector<unsigned char> &host_jobs, hipStream_t stream);
 // Rows per tile the operator action takes for these fields (0: per-cell kernel).
 int stencil_tile_rows(const Operator &op, int m, const void *X, int64_t ldx, bko_dtype t_in, const void *Y,
                       int64_t ldy, bko_dtype t_out);
@@ -41,6 +52,16 @@ bko_status launch_normalize_weights(int s, int64_t m, double *C, int64_t ldc, do
 bko_status launch_combine_dual(int64_t n, int s, int64_t m, const double *X, int64_t ldx, const double *Y, int64_t ldy,
                                const double *C, int64_t ldc, double *T, int64_t ldt, double *F, int64_t ldf,
                                hipStream_t stream);
+
+// T = X C for several chips in one grouped launch (X, C FP64; T of t_t),
+// m[c] fields of chip c; fields_per_wg > 0 fixes the fields per workgroup.
+// jobs_dev: combine_group_job_bytes(nchips) bytes of device memory, copied
+// from host_jobs (which must live until the stream has passed the launch).
+size_t combine_group_job_bytes(int nchips);
+bko_status launch_combine_group(int nchips, const int64_t *n, int s, const int *m, const double *const *X,
+                                const int64_t *ldx, const double *const *C, const int64_t *ldc, void *const *T,
+                                const int64_t *ldt, bko_dtype t_t, bko_dtype compute, int64_t fields_per_wg,
+                                void *jobs_dev, std::vector<unsigned char> &host_jobs, hipStream_t stream);
 
 // zero-fill bytes (a kernel, never a memset node, so it is safe in graphs)
 bko_status launch_zero(void *p, size_t bytes, hipStream_t stream);
@@ -75,8 +96,21 @@ struct BatchPlan {
     bool tuned = false;
     std::vector<std::pair<int, float>> tune_ms;  // (tiles per workgroup, ms of the timed passes)
     GraphCache graphs;
+    // outputs (bko_batch_run): fields per chip (empty: the plan only solves),
+    // combination arithmetic, T and F storage types, the operator action's
+    // arithmetic, and the two output knobs (0 = the launcher's default),
+    // chosen by timing on the first run
+    std::vector<int> m;
+    bko_dtype comb_compute = BKO_F64, t_dtype = BKO_F64, f_dtype = BKO_F64, apply_compute = BKO_F64;
+    int out_ty_cap = 0;
+    int64_t out_fields_per_wg = 0;
+    bool out_tuned = false;
+    std::vector<std::pair<std::string, float>> out_tune_ms;  // (candidate, ms)
 };
 
+// Bytes of the solve's part of a batch workspace, and of the whole
+// workspace (the solve's part, then the output job tables).
+size_t batch_solve_bytes(const BatchPlan &p);
 size_t batch_workspace_bytes(const BatchPlan &p);
 bko_status batch_tune(BatchPlan &p, void *work, hipStream_t stream);
 bko_status batch_solve(BatchPlan &p, const double *const *B, const int64_t *ldb, double *const *X,

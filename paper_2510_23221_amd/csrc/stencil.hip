@@ -18,7 +18,9 @@
 // a contiguous range of work.  The damped Jacobi sweep that smooths an
 // initial guess is the per-cell form with an update.
 #include <algorithm>
+#include <cstring>
 #include <type_traits>
+#include <vector>
 
 #include "kernels.hpp"
 
@@ -134,20 +136,18 @@ constexpr int kTileVecs = 4;  // 16-byte vectors per thread and plane
 // so the coefficients of a tile (as many bytes per cell as the field itself,
 // or twice as many) are read from HBM about once and served from that XCD's
 // L2 to every field.
+//
+// The body takes the workgroup's logical index lb in [0, nblocks) of one
+// operator's launch; stencil_tile_kernel runs one operator,
+// stencil_tile_group_kernel the operators of a batch of chips in one grid.
 template <class Tin, class Tout, class Tc, class Acc, bool kResidual>
-__global__ __launch_bounds__(kThreads) void stencil_tile_kernel(
-    const Tc *__restrict__ diag, const Tc *__restrict__ wx, const Tc *__restrict__ wy, const Tc *__restrict__ wz,
-    int nx, int ny, int nz, const Tin *__restrict__ X, int64_t ldx, Tout *__restrict__ Y, int64_t ldy,
-    const double *__restrict__ Bres, int64_t ldb, int TY, int ntiles, uint32_t nblocks, const int *__restrict__ skip,
-    int *stop)
+__device__ __forceinline__ void stencil_tile_body(
+    uint32_t lb, uint32_t nblocks, const Tc *__restrict__ diag, const Tc *__restrict__ wx,
+    const Tc *__restrict__ wy, const Tc *__restrict__ wz, int nx, int ny, int nz, const Tin *__restrict__ X,
+    int64_t ldx, Tout *__restrict__ Y, int64_t ldy, const double *__restrict__ Bres, int64_t ldb, int TY, int ntiles)
 {
     constexpr int VX = 16 / sizeof(Tin);
     constexpr int R = kTileVecs;
-    if (skip && *skip) {
-        if (stop && blockIdx.x == 0 && threadIdx.x == 0) *stop = 1;
-        return;
-    }
-    const uint32_t lb = remap_block(blockIdx.x, nblocks);
     // fields fastest: the workgroups an XCD runs together share one tile's
     // coefficients (reused from L2); the halo rows of neighbouring tiles are
     // the only re-reads
@@ -293,6 +293,54 @@ __global__ __launch_bounds__(kThreads) void stencil_tile_kernel(
     }
 }
 
+template <class Tin, class Tout, class Tc, class Acc, bool kResidual>
+__global__ __launch_bounds__(kThreads) void stencil_tile_kernel(
+    const Tc *__restrict__ diag, const Tc *__restrict__ wx, const Tc *__restrict__ wy, const Tc *__restrict__ wz,
+    int nx, int ny, int nz, const Tin *__restrict__ X, int64_t ldx, Tout *__restrict__ Y, int64_t ldy,
+    const double *__restrict__ Bres, int64_t ldb, int TY, int ntiles, uint32_t nblocks, const int *__restrict__ skip,
+    int *stop)
+{
+    if (skip && *skip) {
+        if (stop && blockIdx.x == 0 && threadIdx.x == 0) *stop = 1;
+        return;
+    }
+    stencil_tile_body<Tin, Tout, Tc, Acc, kResidual>(remap_block(blockIdx.x, nblocks), nblocks, diag, wx, wy, wz, nx,
+                                                     ny, nz, X, ldx, Y, ldy, Bres, ldb, TY, ntiles);
+}
+
+// One chip's share of a grouped operator action: workgroups
+// [block0, block0 + ntiles * m) of the grid.
+struct StencilJob {
+    const void *diag, *wx, *wy, *wz;
+    const void *X;
+    void *Y;
+    int64_t ldx, ldy;
+    int nx, ny, nz, ty, ntiles, m;
+    uint32_t block0;
+    uint32_t pad;
+};
+
+// The operator action of every chip of a batch in one grid: each XCD walks
+// a contiguous range of the (chip, tile, field) order; a workgroup finds
+// its chip by binary search over the jobs' first blocks.
+template <class Tin, class Tout, class Tc, class Acc>
+__global__ __launch_bounds__(kThreads) void stencil_tile_group_kernel(const StencilJob *__restrict__ jobs, int njobs)
+{
+    const uint32_t g = remap_block(blockIdx.x, gridDim.x);
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (jobs[mid].block0 <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const StencilJob &j = jobs[lo];
+    const uint32_t nb = static_cast<uint32_t>(j.ntiles) * static_cast<uint32_t>(j.m);
+    stencil_tile_body<Tin, Tout, Tc, Acc, false>(
+        g - j.block0, nb, static_cast<const Tc *>(j.diag), static_cast<const Tc *>(j.wx), static_cast<const Tc *>(j.wy),
+        static_cast<const Tc *>(j.wz), j.nx, j.ny, j.nz, static_cast<const Tin *>(j.X), j.ldx, static_cast<Tout *>(j.Y),
+        j.ldy, nullptr, 0, j.ty, j.ntiles);
+}
+
 // Tile height: about kThreads * VX * kTileVecs cells per plane, lowered until
 // the launch has enough workgroups to fill the chip.
 inline int tile_rows(int nx, int ny, int m, int vx)
@@ -414,6 +462,35 @@ bko_status dispatch_out(const Operator &op, int m, const void *X, int64_t ldx, v
     }
 }
 
+template <class Tin, class Tout, class Tc, class Acc>
+bko_status run_group(const std::vector<StencilJob> &jobs, uint32_t total, size_t lds, const void *jobs_dev,
+                     hipStream_t stream)
+{
+    hipLaunchKernelGGL((stencil_tile_group_kernel<Tin, Tout, Tc, Acc>), dim3(total), dim3(kThreads), lds, stream,
+                       static_cast<const StencilJob *>(jobs_dev), static_cast<int>(jobs.size()));
+    BKO_HIP(hipGetLastError());
+    return BKO_OK;
+}
+
+template <class Tin, class Tout>
+bko_status group_by_compute(const std::vector<StencilJob> &jobs, uint32_t total, size_t lds, const void *jobs_dev,
+                            bko_dtype compute, hipStream_t stream)
+{
+    if (compute == BKO_F64) return run_group<Tin, Tout, double, double>(jobs, total, lds, jobs_dev, stream);
+    return run_group<Tin, Tout, float, float>(jobs, total, lds, jobs_dev, stream);
+}
+
+template <class Tin>
+bko_status group_by_out(const std::vector<StencilJob> &jobs, uint32_t total, size_t lds, const void *jobs_dev,
+                        bko_dtype t_out, bko_dtype compute, hipStream_t stream)
+{
+    switch (t_out) {
+    case BKO_F64: return group_by_compute<Tin, double>(jobs, total, lds, jobs_dev, compute, stream);
+    case BKO_F32: return group_by_compute<Tin, float>(jobs, total, lds, jobs_dev, compute, stream);
+    default: return group_by_compute<Tin, bf16>(jobs, total, lds, jobs_dev, compute, stream);
+    }
+}
+
 }  // namespace
 
 bko_status launch_stencil(const Operator &op, int m, const void *X, int64_t ldx, bko_dtype t_in, void *Y,
@@ -431,6 +508,82 @@ bko_status launch_stencil(const Operator &op, int m, const void *X, int64_t ldx,
     case BKO_F32: return dispatch_out<float>(op, m, X, ldx, Y, ldy, t_out, compute, stream, skip, stop);
     default: return dispatch_out<bf16>(op, m, X, ldx, Y, ldy, t_out, compute, stream, skip, stop);
     }
+}
+
+size_t stencil_group_job_bytes(int nchips) { return sizeof(StencilJob) * static_cast<size_t>(nchips); }
+
+bko_status launch_stencil_group(const Operator *const *ops, int nchips, const int *m, const void *const *X,
+                                const int64_t *ldx, bko_dtype t_in, void *const *Y, const int64_t *ldy,
+                                bko_dtype t_out, bko_dtype compute, int ty_cap, void *jobs_dev,
+                                std::vector<unsigned char> &host_jobs, hipStream_t stream)
+{
+    const size_t win = dtype_size(t_in), wout = dtype_size(t_out);
+    const int vx = static_cast<int>(16 / win);
+    const size_t ya = std::min<size_t>(16, vx * wout);
+    const size_t ls = std::min(win, compute == BKO_F64 ? sizeof(double) : sizeof(float));
+    std::vector<StencilJob> jobs;
+    std::vector<int> rest;
+    uint64_t total = 0;
+    size_t lds = 0;
+    for (int c = 0; c < nchips; ++c) {
+        if (m[c] <= 0) continue;
+        const Operator &op = *ops[c];
+        const uintptr_t xa = reinterpret_cast<uintptr_t>(X[c]), ya_p = reinterpret_cast<uintptr_t>(Y[c]);
+        const bool aligned = op.nx % vx == 0 && 2 * (op.nx / vx) <= kThreads && xa % 16 == 0 &&
+                             (ldx[c] * win) % 16 == 0 && ya_p % ya == 0 && (ldy[c] * wout) % ya == 0;
+        if (!aligned) {
+            rest.push_back(c);
+            continue;
+        }
+        // the batch fills the chip: full-height tiles of about kThreads * vx
+        // * kTileVecs cells per plane (or at most ty_cap rows)
+        int ty = std::max(1, std::min(op.ny, kThreads * vx * kTileVecs / op.nx));
+        if (ty_cap > 0) ty = std::min(ty, ty_cap);
+        StencilJob j{};
+        const bool f64 = compute == BKO_F64;
+        j.diag = f64 ? static_cast<const void *>(op.diag64) : static_cast<const void *>(op.diag32);
+        j.wx = f64 ? static_cast<const void *>(op.wx64) : static_cast<const void *>(op.wx32);
+        j.wy = f64 ? static_cast<const void *>(op.wy64) : static_cast<const void *>(op.wy32);
+        j.wz = f64 ? static_cast<const void *>(op.wz64) : static_cast<const void *>(op.wz32);
+        j.X = X[c];
+        j.Y = Y[c];
+        j.ldx = ldx[c];
+        j.ldy = ldy[c];
+        j.nx = op.nx;
+        j.ny = op.ny;
+        j.nz = op.nz;
+        j.ty = ty;
+        j.ntiles = (op.ny + ty - 1) / ty;
+        j.m = m[c];
+        j.block0 = static_cast<uint32_t>(total);
+        total += static_cast<uint64_t>(j.ntiles) * m[c];
+        lds = std::max(lds, 2 * ls * static_cast<size_t>(ty + 2) * op.nx);
+        jobs.push_back(j);
+    }
+    if (total > 0x7fffffffu) {
+        set_error("grouped operator action of %llu workgroups too large", (unsigned long long)total);
+        return BKO_EINVAL;
+    }
+    bko_status rc = BKO_OK;
+    if (!jobs.empty()) {
+        const size_t bytes = sizeof(StencilJob) * jobs.size();
+        host_jobs.resize(bytes);
+        std::memcpy(host_jobs.data(), jobs.data(), bytes);
+        BKO_HIP(hipMemcpyAsync(jobs_dev, host_jobs.data(), bytes, hipMemcpyHostToDevice, stream));
+        const uint32_t tot = static_cast<uint32_t>(total);
+        switch (t_in) {
+        case BKO_F64: rc = group_by_out<double>(jobs, tot, lds, jobs_dev, t_out, compute, stream); break;
+        case BKO_F32: rc = group_by_out<float>(jobs, tot, lds, jobs_dev, t_out, compute, stream); break;
+        default: rc = group_by_out<bf16>(jobs, tot, lds, jobs_dev, t_out, compute, stream); break;
+        }
+        if (rc != BKO_OK) return rc;
+    }
+    // chips whose rows or views do not suit the tiled kernel: one launch each
+    for (int c : rest)
+        if ((rc = launch_stencil(*ops[c], m[c], X[c], ldx[c], t_in, Y[c], ldy[c], t_out, compute, nullptr, 0, stream)) !=
+            BKO_OK)
+            return rc;
+    return BKO_OK;
 }
 
 int stencil_tile_rows(const Operator &op, int m, const void *X, int64_t ldx, bko_dtype t_in, const void *Y,

@@ -267,8 +267,9 @@ def test_config4_bf16_stages_sampled(dev):
 
 def test_batch_extreme_chips(dev):
     """The largest and smallest chips of the uneven-chip workload in one
-    batch plan (s = 16, FP32 iteration, FP64 refinement to 1e-8, Jacobi):
-    residuals by the oracle, and sampled pairs of both chips."""
+    batch run (s = 16, M = 500, FP32 iteration, FP64 refinement to 1e-8,
+    Jacobi, FP64 T and F from the grouped launches): residuals by the
+    oracle, and sampled pairs of both chips."""
     rng = np.random.default_rng(2024)
     chips = [synth.chip_stack(rng, 256, 256, 12), synth.chip_stack(rng, 32, 32, 4)]
     s, m = 16, 500
@@ -276,22 +277,18 @@ def test_batch_extreme_chips(dev):
     Gs = [capi.HeatOperator.from_chip(c, dev, precond=capi.PRECOND_JACOBI) for c in chips]
     Bs = [synth.power_blocky(rng, c, s) for c in chips]
     Cs = [synth.combo_weights(rng, s, m) for _ in chips]
-    plan = capi.BatchPlan(Gs, s, capi.F32)
+    plan = capi.BatchPlan(Gs, s, capi.F32, m=[m, m])
     plan.tune(dev)
-    Xs, infos = plan.solve([torch.as_tensor(B, device=dev) for B in Bs], 1e-8)
-    for A, G, B, C, X, info in zip(As, Gs, Bs, Cs, Xs, infos):
+    Xs, Ts, Fs, infos = plan.run([torch.as_tensor(B, device=dev) for B in Bs],
+                                 [torch.as_tensor(C, device=dev) for C in Cs], 1e-8)
+    idx = np.arange(0, m, 37)
+    for A, B, C, X, T, F, info in zip(As, Bs, Cs, Xs, Ts, Fs, infos):
         assert info["status"] == capi.OK, info
         Xn = to_np(X)
         rel, floor, _ = _rel_res(A, B, Xn)
         assert (rel <= 1e-8 * 1.0001 + floor).all(), (rel.max(), info)
-        T, F = capi.combine_apply(G, X, torch.as_tensor(C, device=dev))
-        T2 = capi.combine(X, torch.as_tensor(C, device=dev))
-        F2 = capi.apply_operator(G, T2)
-        idx = np.arange(0, m, 37)
-        for Tg, Fg in ((T, F), (T2, F2)):
-            Tw, Fw = to_np(Tg[idx]), to_np(Fg[idx])
-            T_ref = oracle.gemm(Xn, C[idx])
-            assert (np.abs(Tw - T_ref) <= (s + 1) * U64 * (np.abs(C[idx]) @ np.abs(Xn)) * 1.01 + 1e-300).all()
-        # two-pass pairs: F = A T of the written T to FP64 rounding
-        Tw, Fw = to_np(T2[idx]), to_np(F2[idx])
+        Tw, Fw = to_np(T[idx]), to_np(F[idx])
+        T_ref = oracle.gemm(Xn, C[idx])
+        assert (np.abs(Tw - T_ref) <= (s + 1) * U64 * (np.abs(C[idx]) @ np.abs(Xn)) * 1.01 + 1e-300).all()
+        # pairs: F = A T of the written T to FP64 rounding
         assert (np.abs(Fw - oracle.apply_many(A, Tw)) <= stage_bound_apply(A, Tw, U64) * 1.01 + 1e-300).all()

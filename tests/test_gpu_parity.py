@@ -595,3 +595,64 @@ def test_copy_kernel_is_exact(dev, nbytes):
     capi.copy(dst[:nbytes], src)
     assert torch.equal(dst[:nbytes], src)
     assert int(dst[nbytes:].sum()) == 0
+
+
+# ------------------------------------------------------------------ batch run (solve + outputs)
+
+@pytest.mark.parametrize("compute,comb,tdt,fdt", [(capi.F64, capi.F64, torch.float64, torch.float64),
+                                                   (capi.F32, capi.F64, torch.float64, torch.float64),
+                                                   (capi.F32, capi.BF16, torch.bfloat16, torch.float32)])
+def test_batch_run_matches_oracle(dev, compute, comb, tdt, fdt):
+    """bko_batch_run: every chip's basis solve, then one grouped combination
+    and one grouped operator action over all chips (Sec. III, Eqs. (4)-(6)).
+    Chips of different grids and field counts, one with no fields and one
+    whose rows are not a whole number of 16-byte vectors (its operator
+    action takes a launch of its own); each chip's T against X C of the
+    solve's X and its F against A T of the T written, on the oracle."""
+    chips = _batch_chips()  # ragged 37x23x5, 2-D 64x64, 24x20x5, 1-D 300, 48x48x4
+    As = [oracle.assemble_chip(c) for c in chips]
+    Gs = [capi.HeatOperator.from_chip(c, dev) for c in chips]
+    rng = np.random.default_rng(61)
+    s = 8
+    ms = [70, 130, 0, 9, 257]
+    Bs = [rng.standard_normal((s, A.n)) for A in As]
+    Cs = [rng.standard_normal((mc, s)) for mc in ms]
+    plan = capi.BatchPlan(Gs, s, compute, m=ms, comb_compute=comb, t_dtype=tdt, f_dtype=fdt)
+    assert plan.output_tuning() == (-1, -1)
+    tol = 1e-10 if compute == capi.F64 else 1e-8
+    Xs, Ts, Fs, infos = plan.run([torch.as_tensor(B, device=dev) for B in Bs],
+                                 [torch.as_tensor(C, device=dev) for C in Cs], tol)
+    ty, fpw = plan.output_tuning()
+    assert ty in (0, 16, 8) and fpw in (0, 64, 256)
+    torch.cuda.synchronize()
+    u_acc = U64 if comb == capi.F64 else U32
+    u_t = {torch.float64: 0.0, torch.float32: U32, torch.bfloat16: UBF}[tdt]
+    u_f = {torch.float64: 0.0, torch.float32: U32, torch.bfloat16: UBF}[fdt]
+    for k, (A, B, C, X, T, F, info) in enumerate(zip(As, Bs, Cs, Xs, Ts, Fs, infos)):
+        assert info["status"] == capi.OK, (k, info)
+        Xn = to_np(X)
+        R = B - oracle.apply_many(A, Xn)
+        rel = np.linalg.norm(R, axis=1) / np.linalg.norm(B, axis=1)
+        floor = 8 * U64 * np.linalg.norm(oracle.apply_many(abs_csr(A), np.abs(Xn)) + np.abs(B), axis=1) \
+            / np.linalg.norm(B, axis=1)
+        assert (rel <= tol * 1.0001 + floor).all(), (k, rel.max())
+        if ms[k] == 0:
+            continue
+        rnd = (lambda v: v) if comb == capi.F64 else bf16_round
+        Xr, Cr = rnd(Xn), rnd(C)
+        T_ref = oracle.gemm(Xr, Cr)
+        bt = (s + 1) * u_acc * (np.abs(Cr) @ np.abs(Xr))
+        bt += u_t * (np.abs(T_ref) + bt)
+        Tn = to_np(T)
+        assert (np.abs(Tn - T_ref) <= bt * 1.01 + 1e-300).all(), k
+        F_ref = oracle.apply_many(A, Tn)
+        AT = oracle.apply_many(abs_csr(A), np.abs(Tn))
+        bf = 8 * U64 * AT if (tdt == torch.float64 and fdt == torch.float64) else 10 * U32 * AT
+        bf += u_f * (np.abs(F_ref) + bf)
+        assert (np.abs(to_np(F) - F_ref) <= bf * 1.01 + 1e-300).all(), k
+    # a second run keeps the tuned knobs and reproduces the outputs exactly
+    Xs2, Ts2, Fs2, _ = plan.run([torch.as_tensor(B, device=dev) for B in Bs],
+                                [torch.as_tensor(C, device=dev) for C in Cs], tol)
+    assert plan.output_tuning() == (ty, fpw)
+    for T, F, T2, F2 in zip(Ts, Fs, Ts2, Fs2):
+        assert torch.equal(T, T2) and torch.equal(F, F2)
