@@ -231,6 +231,158 @@ __global__ __launch_bounds__(kThreads) void combine_group_kernel(const CombineJo
                                             static_cast<Tt *>(j.T), j.ldt, j.fields_per_wg, j.ntiles, j.vec_ok);
 }
 
+// ---------------------------------------------------------------- wide BF16 tiles
+
+// The BF16 combination with wide cell tiles, for BF16 or FP32 fields: a
+// workgroup of eight waves owns 1024 consecutive cells (each wave 128 of
+// them, as eight 16-cell blocks of matrix-core A operands rounded to BF16
+// and held in registers for the whole launch).  C is rounded to BF16 and
+// staged in LDS 128 fields at a time (one barrier per 128 fields; the next
+// chunk is fetched into registers meanwhile); each wave then runs 16 fields
+// at a time on v_mfma_f32_16x16x32_bf16 (FP32 accumulation), stages its own
+// 16 x 128 results in a wave-private LDS slice and writes every field's 128
+// cells (256 bytes for BF16 fields) with 16-byte stores, without waiting for
+// the other waves.
+constexpr int kWideWaves = 8;
+constexpr int kWideThreads = 64 * kWideWaves;
+constexpr int kWideRB = 8;                          // 16-cell blocks per wave
+constexpr int kWideWC = kWideRB * 16;               // 128 cells per wave
+constexpr int kWideTM = kWideWaves * kWideWC;       // 1024 cells per workgroup
+constexpr int kWideF = 16;                          // fields per matrix-core block
+constexpr int kWideChunk = 128;                     // fields per staged C chunk
+constexpr int kWideCS = 64 + 8;                     // LDS row of C (BF16, padded)
+constexpr int kWideOS = kWideWC + 8;                // LDS row of a wave's output slice (padded)
+
+template <class Tx, class Tc, class Tt>
+__global__ __launch_bounds__(kWideThreads) void combine_wide_kernel(int64_t n, int s, int64_t m,
+                                                                    const Tx *__restrict__ X, int64_t ldx,
+                                                                    const Tc *__restrict__ C, int64_t ldc,
+                                                                    Tt *__restrict__ T, int64_t ldt,
+                                                                    int64_t fields_per_wg, uint32_t ntiles, int vec_ok)
+{
+    const uint32_t tile = blockIdx.x % ntiles;
+    const uint32_t split = blockIdx.x / ntiles;
+    const int64_t cell0 = static_cast<int64_t>(tile) * kWideTM;
+    const int64_t f_begin = static_cast<int64_t>(split) * fields_per_wg;
+    const int64_t f_end = min(m, f_begin + fields_per_wg);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t wcell0 = cell0 + wave * kWideWC;
+    __shared__ __align__(16) uint16_t cs[2][kWideChunk * kWideCS];
+    __shared__ __align__(16) Tt os[kWideWaves][kWideF * kWideOS];
+    Tt *myos = os[wave];
+
+    // A operands: cell wcell0 + rb 16 + li, k = 32 t + 8 lg + e; every load
+    // is issued (at a clamped index) and the padding zeroed afterwards, so
+    // the loads are in flight together
+    bf8 xa[kWideRB][2];
+#pragma unroll
+    for (int rb = 0; rb < kWideRB; ++rb) {
+        const int64_t cell = wcell0 + rb * 16 + li;
+        const int64_t cellc = cell < n ? cell : n - 1;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            bf8 v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = 32 * t + 8 * lg + e;
+                const int kc = k < s ? k : s - 1;
+                const float x = load_as<float>(X + static_cast<int64_t>(kc) * ldx + cellc);
+                v[e] = bits_to_bf(f32_to_bf16((k < s && cell < n) ? x : 0.f));
+            }
+            xa[rb][t] = v;
+        }
+    }
+    // C chunk [128 fields][64 k] in BF16, 16 elements per thread, fetched
+    // into registers one chunk ahead
+    constexpr int kCE = kWideChunk * 64 / kWideThreads;
+    uint16_t cv[kCE];
+    auto fetch_c = [&](int64_t f0) {
+#pragma unroll
+        for (int i = 0; i < kCE; ++i) {
+            const int e = tid + i * kWideThreads;
+            const int f = e / 64, k = e % 64;
+            const int64_t field = f0 + f;
+            const int64_t fc = field < f_end ? field : f_end - 1;
+            const int kc = k < s ? k : s - 1;
+            const float c = load_as<float>(C + fc * ldc + kc);
+            cv[i] = f32_to_bf16((k < s && field < f_end) ? c : 0.f);
+        }
+    };
+    auto stash_c = [&](int b) {
+#pragma unroll
+        for (int i = 0; i < kCE; ++i) {
+            const int e = tid + i * kWideThreads;
+            cs[b][(e / 64) * kWideCS + e % 64] = cv[i];
+        }
+    };
+    constexpr int kVec = 16 / sizeof(Tt);
+    constexpr int kVPF = kWideWC / kVec;  // 16-byte vectors per field of the wave's slice
+    if (f_begin < f_end) {
+        fetch_c(f_begin);
+        stash_c(0);
+    }
+    int b = 0;
+    for (int64_t c0 = f_begin; c0 < f_end; c0 += kWideChunk) {
+        const bool more = c0 + kWideChunk < f_end;
+        if (more) fetch_c(c0 + kWideChunk);
+        __syncthreads();  // chunk b staged; every wave is done with chunk b ^ 1
+        const int64_t c1 = min(f_end, c0 + kWideChunk);
+        for (int64_t f0 = c0; f0 < c1; f0 += kWideF) {
+            const int fb = static_cast<int>(f0 - c0);
+            bf8 cb[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                cb[t] = *reinterpret_cast<const bf8 *>(&cs[b][(fb + li) * kWideCS + 32 * t + 8 * lg]);
+#pragma unroll
+            for (int rb = 0; rb < kWideRB; ++rb) {
+                // the second k step multiplies zeros when s <= 32
+                f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[rb][0], cb[0], f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[rb][1], cb[1], acc, 0, 0, 0);
+                // acc[r] = T[cell wcell0 + rb 16 + 4 lg + r][field f0 + li]:
+                // four consecutive cells, one 8- or 16-byte LDS store
+                Tt *dst = &myos[li * kWideOS + rb * 16 + 4 * lg];
+                if constexpr (sizeof(Tt) == 2) {
+                    uint2 pk;
+                    pk.x = static_cast<uint32_t>(f32_to_bf16(acc[0])) | (static_cast<uint32_t>(f32_to_bf16(acc[1])) << 16);
+                    pk.y = static_cast<uint32_t>(f32_to_bf16(acc[2])) | (static_cast<uint32_t>(f32_to_bf16(acc[3])) << 16);
+                    *reinterpret_cast<uint2 *>(dst) = pk;
+                } else {
+                    *reinterpret_cast<float4 *>(dst) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+                }
+            }
+            // the slice is the wave's own: its lanes' stores are visible to
+            // the wave once they have completed
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int q = 0; q < kWideF * kVPF / 64; ++q) {
+                const int v = lane + q * 64;
+                const int f = v / kVPF, cvi = v % kVPF;
+                const int64_t field = f0 + f;
+                const int64_t cell = wcell0 + static_cast<int64_t>(cvi) * kVec;
+                if (field >= c1 || cell >= n) continue;
+                const Tt *src = &myos[f * kWideOS + cvi * kVec];
+                Tt *dst = T + field * ldt + cell;
+                if (vec_ok && cell + kVec <= n) {
+                    *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
+                } else {
+                    for (int e = 0; e < kVec && cell + e < n; ++e) dst[e] = src[e];
+                }
+            }
+            // the slice is rewritten by the next block only after every
+            // lane has read it
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (more) stash_c(b ^ 1);
+        b ^= 1;
+    }
+}
+
 // ---------------------------------------------------------------- noise
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
@@ -494,10 +646,35 @@ bko_status run_direct(int64_t n, int s, int64_t m, const double *X, int64_t ldx,
     return BKO_OK;
 }
 
+template <class Tx, class Tc, class Tt>
+bko_status run_wide(int64_t n, int s, int64_t m, const void *X, int64_t ldx, const void *C, int64_t ldc, void *T,
+                    int64_t ldt, hipStream_t stream)
+{
+    const uint32_t ntiles = static_cast<uint32_t>((n + kWideTM - 1) / kWideTM);
+    const int64_t fblocks = (m + kWideF - 1) / kWideF;
+    // split the fields so that the grid has a few thousand workgroups
+    int64_t splits = std::max<int64_t>(1, std::min<int64_t>(fblocks, (2048 + ntiles - 1) / ntiles));
+    const int64_t fields_per_wg = ((fblocks + splits - 1) / splits) * kWideF;
+    splits = (m + fields_per_wg - 1) / fields_per_wg;
+    const uint64_t nb = static_cast<uint64_t>(ntiles) * splits;
+    if (nb > 0x7fffffffu) {
+        set_error("combine grid too large");
+        return BKO_EINVAL;
+    }
+    const int vec_ok = (reinterpret_cast<uintptr_t>(T) % 16 == 0) && ((ldt * sizeof(Tt)) % 16 == 0);
+    hipLaunchKernelGGL((combine_wide_kernel<Tx, Tc, Tt>), dim3(static_cast<uint32_t>(nb)), dim3(kWideThreads), 0,
+                       stream, n, s, m, static_cast<const Tx *>(X), ldx, static_cast<const Tc *>(C), ldc,
+                       static_cast<Tt *>(T), ldt, fields_per_wg, ntiles, vec_ok);
+    BKO_HIP(hipGetLastError());
+    return BKO_OK;
+}
+
 template <int kMode, class Tx, class Tc, class Tt>
 bko_status run(int64_t n, int s, int64_t m, const void *X, int64_t ldx, const void *C, int64_t ldc, void *T,
                int64_t ldt, hipStream_t stream)
 {
+    if constexpr (kMode == kBF16 && !std::is_same<Tt, double>::value)
+        return run_wide<Tx, Tc, Tt>(n, s, m, X, ldx, C, ldc, T, ldt, stream);
     using TR = ModeTraits<kMode>;
     const uint32_t ntiles = static_cast<uint32_t>((n + kTM - 1) / kTM);
     const int64_t ftiles = (m + kTN - 1) / kTN;

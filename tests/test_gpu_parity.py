@@ -656,3 +656,28 @@ def test_batch_run_matches_oracle(dev, compute, comb, tdt, fdt):
     assert plan.output_tuning() == (ty, fpw)
     for T, F, T2, F2 in zip(Ts, Fs, Ts2, Fs2):
         assert torch.equal(T, T2) and torch.equal(F, F2)
+
+
+@pytest.mark.parametrize("s,m,tdt,offset", [(64, 50, torch.bfloat16, 0), (17, 33, torch.float32, 0),
+                                            (32, 16, torch.bfloat16, 3), (5, 70, torch.float32, 1)])
+def test_combine_bf16_wide_tiles(dev, s, m, tdt, offset):
+    """BF16 combination with 1024-cell tiles: a ragged last tile, s not a
+    multiple of the 32-wide matrix-core step, a field count not a multiple of
+    the 16-field block, and output views whose rows are not 16-byte aligned
+    (scalar stores); against the oracle product of the BF16-rounded inputs."""
+    rng = np.random.default_rng(300 + s)
+    n = 3 * 1024 + 77
+    X = rng.standard_normal((s, n))
+    C = rng.standard_normal((m, s))
+    Tb = torch.zeros((m, n + 8), dtype=tdt, device=dev)
+    T = Tb[:, offset:offset + n]
+    capi.combine(torch.as_tensor(X, device=dev), torch.as_tensor(C, device=dev), out_dtype=tdt, compute=capi.BF16,
+                 T=T)
+    Xr, Cr = bf16_round(X), bf16_round(C)
+    T_ref = oracle.gemm(Xr, Cr)
+    u_out = UBF if tdt == torch.bfloat16 else U32
+    bound = (s + 1) * U32 * (np.abs(Cr) @ np.abs(Xr))
+    bound += u_out * (np.abs(T_ref) + bound)
+    assert (np.abs(to_np(T) - T_ref) <= bound * 1.01 + 1e-30).all()
+    # nothing outside the view was written
+    assert (to_np(Tb[:, :offset]) == 0).all() and (to_np(Tb[:, offset + n:]) == 0).all()
