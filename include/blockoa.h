@@ -437,7 +437,8 @@ bko_status bko_copy(void *dst, const void *src, size_t bytes, void *stream);
 
 /*
  * Which operator-action kernel bko_apply_operator would run for these
- * arguments (pointers are compared for alignment only, never read):
+ * arguments, compute included (pointers are compared for alignment only,
+ * never read):
  * *tile_rows = the rows per tile of the z-marching LDS-tiled kernel
  * (full-width row tiles with a one-row halo, 16-byte vector access), or 0
  * when the per-cell kernel takes the call (rows that are not a whole number
@@ -445,7 +446,7 @@ bko_status bko_copy(void *dst, const void *src, size_t bytes, void *stream);
  * for their halo).  Host only, no launch.
  */
 bko_status bko_apply_operator_tiling(bko_op A, int m, const void *T, int ldt, bko_dtype t_t, const void *F, int ldf,
-                                     bko_dtype f_t, int *tile_rows);
+                                     bko_dtype f_t, bko_dtype compute, int *tile_rows);
 
 /*
  * Fused residual form used by the correction loop: R = B - A X in FP64

@@ -140,7 +140,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bko_normalize_weights": (i32, [i32, i32, vp, i32, dbl, vp, vp]),
         "bko_boundary_source": (i32, [vp, vp, ctypes.POINTER(dbl), vp, vp]),
         "bko_add_column": (i32, [i32, i32, vp, i32, vp, dbl, vp]),
-        "bko_apply_operator_tiling": (i32, [vp, i32, vp, i32, i32, vp, i32, i32, ctypes.POINTER(i32)]),
+        "bko_apply_operator_tiling": (i32, [vp, i32, vp, i32, i32, vp, i32, i32, i32, ctypes.POINTER(i32)]),
         "bko_copy": (i32, [vp, vp, sz, vp]),
         "bko_block_krylov_solve_noalloc": (i32, [vp, i32, vp, i32, vp, i32, vp, i32, i32, dbl, i32,
                                                  ctypes.POINTER(SolveInfo), vp]),
@@ -822,13 +822,14 @@ def apply_operator(A: HeatOperator, T: torch.Tensor, out_dtype=torch.float64, co
     return F
 
 
-def apply_operator_tiling(A: HeatOperator, T: torch.Tensor, F: torch.Tensor) -> int:
+def apply_operator_tiling(A: HeatOperator, T: torch.Tensor, F: torch.Tensor, compute: int = F64) -> int:
     """Rows per tile of the LDS-tiled operator-action kernel that
-    apply_operator(A, T, F=F) runs, or 0 for the per-cell kernel."""
+    apply_operator(A, T, F=F, compute=compute) runs, or 0 for the per-cell
+    kernel."""
     tp, ldt, tt = _block(T, "T")
     fp, ldf, ft = _block(F, "F")
     out = ctypes.c_int()
-    _check(load_library().bko_apply_operator_tiling(A.handle, T.shape[0], tp, ldt, tt, fp, ldf, ft,
+    _check(load_library().bko_apply_operator_tiling(A.handle, T.shape[0], tp, ldt, tt, fp, ldf, ft, compute,
                                                     ctypes.byref(out)))
     return out.value
 

@@ -580,14 +580,14 @@ bko_status bko_copy(void *dst, const void *src, size_t bytes, void *stream)
 }
 
 bko_status bko_apply_operator_tiling(bko_op A, int m, const void *T, int ldt, bko_dtype t_t, const void *F, int ldf,
-                                     bko_dtype f_t, int *tile_rows)
+                                     bko_dtype f_t, bko_dtype compute, int *tile_rows)
 {
     BKO_GUARD_BEGIN
     BKO_CHECK(A != nullptr && tile_rows != nullptr, "NULL argument");
     const Operator &op = *reinterpret_cast<const Operator *>(A);
     BKO_CHECK(m >= 0 && ldt >= op.n && ldf >= op.n, "bad sizes");
-    BKO_CHECK(valid_dtype(t_t) && valid_dtype(f_t), "bad dtype");
-    *tile_rows = stencil_tile_rows(op, m, T, ldt, t_t, F, ldf, f_t);
+    BKO_CHECK(valid_dtype(t_t) && valid_dtype(f_t) && valid_dtype(compute), "bad dtype");
+    *tile_rows = stencil_tile_rows(op, m, T, ldt, t_t, F, ldf, f_t, compute);
     return BKO_OK;
     BKO_GUARD_END
 }

@@ -28,7 +28,7 @@ bko_status launch_stencil_group(const Operator *const *ops, int nchips, const in
                                 std::vector<unsigned char> &host_jobs, hipStream_t stream);
 // Rows per tile the operator action takes for these fields (0: per-cell kernel).
 int stencil_tile_rows(const Operator &op, int m, const void *X, int64_t ldx, bko_dtype t_in, const void *Y,
-                      int64_t ldy, bko_dtype t_out);
+                      int64_t ldy, bko_dtype t_out, bko_dtype compute);
 
 // `sweeps` damped Jacobi sweeps X <- X + omega (B - A X) / diag(A) in FP64
 // over m columns; work is an n x m FP64 block (ldw >= n).

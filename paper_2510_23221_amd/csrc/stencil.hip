@@ -125,7 +125,15 @@ __device__ __forceinline__ void vstore(T *p, const Vec<T, N> &r)
     }
 }
 
-constexpr int kTileVecs = 4;  // 16-byte vectors per thread and plane
+// 16-byte vectors per thread and plane: as many as keep each of the plane
+// arrays carried in registers (previous, current, next plane and the
+// coupling below) at 64 bytes of accumulator values per thread, between one
+// and four (FP64 or FP32 fields: four; BF16 fields with FP32 accumulation:
+// two; more would hold the kernel to one wave per SIMD)
+__host__ __device__ constexpr int tile_vecs(int vx, int acc_bytes)
+{
+    return 64 / (vx * acc_bytes) < 1 ? 1 : (64 / (vx * acc_bytes) > 4 ? 4 : 64 / (vx * acc_bytes));
+}
 
 // A workgroup owns full-width rows [j0, j0 + TY) of one field and marches
 // through the nz planes.  The current plane of the tile plus one halo row on
@@ -147,7 +155,7 @@ __device__ __forceinline__ void stencil_tile_body(
     int64_t ldx, Tout *__restrict__ Y, int64_t ldy, const double *__restrict__ Bres, int64_t ldb, int TY, int ntiles)
 {
     constexpr int VX = 16 / sizeof(Tin);
-    constexpr int R = kTileVecs;
+    constexpr int R = tile_vecs(VX, sizeof(Acc));
     // fields fastest: the workgroups an XCD runs together share one tile's
     // coefficients (reused from L2); the halo rows of neighbouring tiles are
     // the only re-reads
@@ -341,11 +349,11 @@ __global__ __launch_bounds__(kThreads) void stencil_tile_group_kernel(const Sten
         j.ldy, nullptr, 0, j.ty, j.ntiles);
 }
 
-// Tile height: about kThreads * VX * kTileVecs cells per plane, lowered until
+// Tile height: about kThreads * VX * tile_vecs(VX) cells per plane, lowered until
 // the launch has enough workgroups to fill the chip.
-inline int tile_rows(int nx, int ny, int m, int vx)
+inline int tile_rows(int nx, int ny, int m, int vx, int acc_bytes)
 {
-    int ty = std::max(1, std::min(ny, kThreads * vx * kTileVecs / nx));
+    int ty = std::max(1, std::min(ny, kThreads * vx * tile_vecs(vx, acc_bytes) / nx));
     while (ty > 2 && static_cast<int64_t>((ny + ty - 1) / ty) * m < 2048) ty = (ty + 1) / 2;
     return ty;
 }
@@ -353,7 +361,8 @@ inline int tile_rows(int nx, int ny, int m, int vx)
 // Rows per tile of stencil_tile_kernel for these fields, or 0 when the
 // per-cell kernel takes them: rows not a whole number of 16-byte vectors,
 // views not 16-byte aligned, or tiles too short to pay for their halo.
-int tile_plan(const Operator &op, int m, size_t win, size_t wout, uintptr_t X, int64_t ldx, uintptr_t Y, int64_t ldy)
+int tile_plan(const Operator &op, int m, size_t win, size_t wout, size_t wacc, uintptr_t X, int64_t ldx, uintptr_t Y,
+              int64_t ldy)
 {
     const int vx = static_cast<int>(16 / win);
     const size_t ya = std::min<size_t>(16, vx * wout);
@@ -361,11 +370,12 @@ int tile_plan(const Operator &op, int m, size_t win, size_t wout, uintptr_t X, i
     const bool aligned = op.nx % vx == 0 && 2 * (op.nx / vx) <= kThreads && X % 16 == 0 &&
                          (ldx * win) % 16 == 0 && Y % ya == 0 && (ldy * wout) % ya == 0;
     if (!aligned || m <= 0) return 0;
-    const int ty = tile_rows(op.nx, op.ny, m, vx);
+    const int ty = tile_rows(op.nx, op.ny, m, vx, static_cast<int>(wacc));
     // short tiles waste the halo and most threads: the per-cell kernel is
     // better there (e.g. the few-column products inside the block solve)
     if (!(ty >= 8 || ty == op.ny)) return 0;
-    if (static_cast<int64_t>(ty) * op.nx > static_cast<int64_t>(kThreads) * vx * kTileVecs) return 0;
+    if (static_cast<int64_t>(ty) * op.nx > static_cast<int64_t>(kThreads) * vx * tile_vecs(vx, static_cast<int>(wacc)))
+        return 0;
     const int ntiles = (op.ny + ty - 1) / ty;
     if (static_cast<uint64_t>(ntiles) * m > 0x7fffffffu) return 0;
     return ty;
@@ -376,7 +386,7 @@ bko_status run(const Operator &op, const Tc *diag, const Tc *wx, const Tc *wy, c
                const void *X, int64_t ldx, void *Y, int64_t ldy, const double *Bres, int64_t ldb,
                hipStream_t stream, const int *skip, int *stop)
 {
-    const int ty = tile_plan(op, m, sizeof(Tin), sizeof(Tout), reinterpret_cast<uintptr_t>(X), ldx,
+    const int ty = tile_plan(op, m, sizeof(Tin), sizeof(Tout), sizeof(Acc), reinterpret_cast<uintptr_t>(X), ldx,
                              reinterpret_cast<uintptr_t>(Y), ldy);
     if (ty > 0) {
         const int ntiles = (op.ny + ty - 1) / ty;
@@ -518,6 +528,7 @@ bko_status launch_stencil_group(const Operator *const *ops, int nchips, const in
                                 std::vector<unsigned char> &host_jobs, hipStream_t stream)
 {
     const size_t win = dtype_size(t_in), wout = dtype_size(t_out);
+    const size_t wacc = compute == BKO_F64 ? sizeof(double) : sizeof(float);
     const int vx = static_cast<int>(16 / win);
     const size_t ya = std::min<size_t>(16, vx * wout);
     const size_t ls = std::min(win, compute == BKO_F64 ? sizeof(double) : sizeof(float));
@@ -536,8 +547,8 @@ bko_status launch_stencil_group(const Operator *const *ops, int nchips, const in
             continue;
         }
         // the batch fills the chip: full-height tiles of about kThreads * vx
-        // * kTileVecs cells per plane (or at most ty_cap rows)
-        int ty = std::max(1, std::min(op.ny, kThreads * vx * kTileVecs / op.nx));
+        // * tile_vecs(vx) cells per plane (or at most ty_cap rows)
+        int ty = std::max(1, std::min(op.ny, kThreads * vx * tile_vecs(vx, static_cast<int>(wacc)) / op.nx));
         if (ty_cap > 0) ty = std::min(ty, ty_cap);
         StencilJob j{};
         const bool f64 = compute == BKO_F64;
@@ -587,10 +598,10 @@ bko_status launch_stencil_group(const Operator *const *ops, int nchips, const in
 }
 
 int stencil_tile_rows(const Operator &op, int m, const void *X, int64_t ldx, bko_dtype t_in, const void *Y,
-                      int64_t ldy, bko_dtype t_out)
+                      int64_t ldy, bko_dtype t_out, bko_dtype compute)
 {
-    return tile_plan(op, m, dtype_size(t_in), dtype_size(t_out), reinterpret_cast<uintptr_t>(X), ldx,
-                     reinterpret_cast<uintptr_t>(Y), ldy);
+    return tile_plan(op, m, dtype_size(t_in), dtype_size(t_out), compute == BKO_F64 ? sizeof(double) : sizeof(float),
+                     reinterpret_cast<uintptr_t>(X), ldx, reinterpret_cast<uintptr_t>(Y), ldy);
 }
 
 bko_status launch_jacobi(const Operator &op, int m, const double *B, int64_t ldb, double *X, int64_t ldx,
