@@ -427,9 +427,10 @@ bko_status bko_apply_operator(bko_op A, int m, const void *T, int ldt, bko_dtype
                               int ldf, bko_dtype f_t, bko_dtype compute, void *stream);
 
 /*
- * dst = src, `bytes` bytes of device memory, with 16-byte vector loads and
- * stores (the library's reference for achievable HBM bandwidth: every
- * HBM-bound kernel of the path reads and writes whole fields the same way).
+ * dst = src, `bytes` bytes of device memory, one 16-byte vector load and
+ * store per thread (the library's reference for achievable HBM bandwidth:
+ * every HBM-bound kernel of the path reads and writes whole fields with
+ * 16-byte vector accesses).
  * Both pointers 16-byte aligned, bytes a multiple of 16, no overlap;
  * otherwise BKO_EINVAL.  Asynchronous.
  */

@@ -287,36 +287,24 @@ __global__ void zero_kernel(uint32_t *p, size_t words)
     for (size_t w = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words; w += stride) p[w] = 0u;
 }
 
-// Device copy with 16-byte vector accesses: each workgroup moves 16 KB per
-// round (four vectors per thread, all four loads issued before the stores),
-// rounds spread over the grid; the last partial round vector by vector.
-// The achievable-bandwidth reference of the HBM-bound kernels.
-constexpr int kCopyVecs = 4;
+// Device copy with 16-byte vector accesses: one vector per thread over a
+// grid that covers the buffer (measured on MI355X, a grid of short-lived
+// workgroups sustains more bandwidth than fewer workgroups looping over
+// several vectors each); a grid-stride loop covers buffers beyond the
+// largest grid.  The achievable-bandwidth reference of the HBM-bound kernels.
 __global__ __launch_bounds__(256) void copy16_kernel(uint4 *__restrict__ dst, const uint4 *__restrict__ src,
                                                      size_t nvec)
 {
-    constexpr size_t per_round = 256 * kCopyVecs;
-    const size_t rounds = nvec / per_round;
-    for (size_t r = blockIdx.x; r < rounds; r += gridDim.x) {
-        const size_t base = r * per_round + threadIdx.x;
-        uint4 v[kCopyVecs];
-#pragma unroll
-        for (int i = 0; i < kCopyVecs; ++i) v[i] = src[base + i * 256];
-#pragma unroll
-        for (int i = 0; i < kCopyVecs; ++i) dst[base + i * 256] = v[i];
-    }
-    for (size_t e = rounds * per_round + static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; e < nvec;
-         e += static_cast<size_t>(gridDim.x) * 256)
-        dst[e] = src[e];
+    const size_t stride = static_cast<size_t>(gridDim.x) * 256;
+    for (size_t e = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; e < nvec; e += stride) dst[e] = src[e];
 }
 
 bko_status launch_copy16(void *dst, const void *src, size_t bytes, hipStream_t stream)
 {
     if (bytes == 0) return BKO_OK;
     const size_t nvec = bytes / 16;
-    const size_t rounds = nvec / (256 * kCopyVecs);
-    // a few workgroups per CU resident at once, each looping over rounds
-    const size_t blocks = std::max<size_t>(1, std::min<size_t>(rounds, 256 * 8));
+    // grid x workgroup size stays below 2^32 threads
+    const size_t blocks = std::min<size_t>((nvec + 255) / 256, (size_t(1) << 23));
     hipLaunchKernelGGL(copy16_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
                        static_cast<uint4 *>(dst), static_cast<const uint4 *>(src), nvec);
     BKO_HIP(hipGetLastError());

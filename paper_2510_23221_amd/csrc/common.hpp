@@ -26,14 +26,16 @@ __device__ inline float bf16_to_f32(uint16_t b)
     return __uint_as_float(static_cast<uint32_t>(b) << 16);
 }
 
-// Round to nearest, ties to even; NaN stays a quiet NaN (a select, not a
-// branch, so that vectorised conversions stay branch-free).
+// Round to nearest, ties to even, by gfx950's conversion instruction (one
+// instruction for two values where the compiler pairs neighbouring
+// conversions); NaN stays a NaN.  The empty register constraint keeps the
+// FP32 value itself as the input: without it the compiler may merge a
+// preceding FP64 -> FP32 conversion into one FP64 -> BF16 rounding, while
+// every FP64 value the library stores as BF16 is rounded to FP32 first.
 __device__ inline uint16_t f32_to_bf16(float f)
 {
-    const uint32_t u = __float_as_uint(f);
-    const uint32_t rounded = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-    const uint32_t quiet = (u >> 16) | 0x40u;
-    return static_cast<uint16_t>((u & 0x7fffffffu) > 0x7f800000u ? quiet : rounded);
+    asm("" : "+v"(f));
+    return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f));
 }
 
 template <class T> struct Conv;
