@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--nchips", type=int, default=None)
     ap.add_argument("--train-epochs", type=float, default=2.0)
     ap.add_argument("--test-chips", type=int, default=256)
+    ap.add_argument("--infer-chips", type=int, default=16,
+                    help="unseen chips whose learned starts come from one network pass")
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cg-columns", type=int, default=512, help="columns of the per-sample CG baseline (0: skip)")
@@ -499,7 +501,12 @@ def bench_learned(args):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     chips, Bs = synth.learned_start_test_chips(args.test_chips, w.chips[0].dims, w.s)
-    recs = lstart.evaluate(net, norm, chips, Bs, w.tol, compute=capi.F32, smooth=20, precond=pc)
+    # the trained parameters in a network sized for the maps of several
+    # chips, so that their learned starts come from one inference pass
+    group = max(1, args.infer_chips)
+    inet = lstart.make_net(w.chips[0], base=32, max_batch=group * w.s, seed=0)
+    inet.set_params(net.params)
+    recs = lstart.evaluate(inet, norm, chips, Bs, w.tol, compute=capi.F32, smooth=20, precond=pc, group=group)
     z = np.array([r["zero_iters"] for r in recs])
     zs = np.array([r["zero_smooth_iters"] for r in recs])
     ln = np.array([r["learned_iters"] for r in recs])
@@ -511,7 +518,7 @@ def bench_learned(args):
            "n_gpus": 1, "data": "synthetic", "dtype": "bf16 weights, f32 activations; f32+f64 solve",
            "config": {"workload": "learned-start-128x128x8", "train_chips": len(w.chips), "pairs": len(w.chips) * w.m,
                       "s": w.s, "test_chips": len(recs), "tol": w.tol, "params": net.nparams, "epochs": args.train_epochs,
-                      "smoothing_sweeps": 20, "precond": args.precond},
+                      "smoothing_sweeps": 20, "precond": args.precond, "chips_per_inference": group},
            "seconds": {"generate_pairs": round(t_gen, 2), "train": round(t_train, 2)},
            "train_loss": [(a, round(b, 6)) for a, b in log],
            "iters": {"zero": float(z.mean()), "zero_smoothed": float(zs.mean()), "learned": float(ln.mean())},

@@ -629,16 +629,25 @@ class UNet:
             pass
 
 
-def lstart_pack(chip_dims, F: torch.Tensor, k_cell: torch.Tensor, kmu: float, ksig: float, hval: float):
+def lstart_pack(chip_dims, F: torch.Tensor, k_cell: torch.Tensor, kmu: float, ksig: float, hval: float,
+                x: Optional[torch.Tensor] = None, scale: Optional[torch.Tensor] = None):
     """Network input of the fields F ((m, N) FP64, one field per row) of one
-    chip.  Returns (x (m, 2 nz + 1, ny, nx) float32, scale (m,) float64)."""
+    chip.  Returns (x (m, 2 nz + 1, ny, nx) float32, scale (m,) float64);
+    x and scale may be given (contiguous, e.g. slices of the input of a
+    batch that spans several chips)."""
     nx, ny, nz = chip_dims
     m = F.shape[0]
     fp, ldf, ft = _block(F, "F")
     if ft != F64:
         raise ValueError("F must be float64")
-    x = torch.empty((m, 2 * nz + 1, ny, nx), dtype=torch.float32, device=F.device)
-    scale = torch.empty(m, dtype=torch.float64, device=F.device)
+    if x is None:
+        x = torch.empty((m, 2 * nz + 1, ny, nx), dtype=torch.float32, device=F.device)
+    elif x.shape != (m, 2 * nz + 1, ny, nx) or x.dtype != torch.float32 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous float32 (m, 2 nz + 1, ny, nx) tensor")
+    if scale is None:
+        scale = torch.empty(m, dtype=torch.float64, device=F.device)
+    elif scale.shape != (m,) or scale.dtype != torch.float64 or not scale.is_contiguous():
+        raise ValueError("scale must be a contiguous float64 (m,) tensor")
     k = k_cell.to(dtype=torch.float64).contiguous()
     _check(load_library().bko_lstart_pack(nx, ny, nz, fp, ldf, m, _ptr(k), kmu, ksig, hval, _ptr(scale), _ptr(x),
                                           _stream()))

@@ -152,36 +152,79 @@ def predict_x0(net: capi.UNet, norm: Normalizer, chip: synth.Chip, k: torch.Tens
     return X0
 
 
+def predict_x0_group(net: capi.UNet, norm: Normalizer, chips: List[synth.Chip], ks: List[torch.Tensor],
+                     Bs: List[torch.Tensor], Gs: List[capi.HeatOperator], smooth: int = 0,
+                     omega: float = 0.6) -> List[torch.Tensor]:
+    """predict_x0 for several chips of one grid with one network pass over
+    all their power maps (net.max_batch >= the total number of maps): the
+    small layers then have enough images to fill the GPU."""
+    nx, ny, nz = chips[0].dims
+    counts = [B.shape[0] for B in Bs]
+    total = sum(counts)
+    if total > net.max_batch or any(c.dims != chips[0].dims for c in chips):
+        raise ValueError("the chips must share a grid and their maps fit one network batch")
+    dev = Bs[0].device
+    x = torch.empty((total, 2 * nz + 1, ny, nx), dtype=torch.float32, device=dev)
+    scale = torch.empty(total, dtype=torch.float64, device=dev)
+    o = 0
+    for chip, k, B, c in zip(chips, ks, Bs, counts):
+        capi.lstart_pack(chip.dims, B, k, norm.kmu, norm.ksig, norm.hval(chip), x=x[o:o + c], scale=scale[o:o + c])
+        o += c
+    y = net.infer(x)
+    out, o = [], 0
+    for G, B, c in zip(Gs, Bs, counts):
+        X0 = torch.empty_like(B)
+        capi.lstart_unpack(y[o:o + c], scale[o:o + c], norm.gain, X0)
+        if smooth > 0:
+            capi.jacobi_smooth(G, B, X0, smooth, omega)
+        out.append(X0)
+        o += c
+    return out
+
+
 def evaluate(net: Optional[capi.UNet], norm: Optional[Normalizer], chips: List[synth.Chip], Bs: List[np.ndarray],
-             tol: float, device="cuda", compute=capi.F32, smooth: int = 0, precond: int = capi.PRECOND_NONE):
+             tol: float, device="cuda", compute=capi.F32, smooth: int = 0, precond: int = capi.PRECOND_NONE,
+             group: int = 1):
     """Block solves of every chip from the zero start, from the zero start
     after the same smoothing sweeps, and (if net is given) from the learned
-    start, all with the given preconditioner.  Returns per-chip records
-    (iterations, final residuals, seconds)."""
+    start, all with the given preconditioner.  With group > 1 the learned
+    starts of `group` consecutive chips come from one network pass
+    (predict_x0_group) and each chip is charged an equal share of its time.
+    Returns per-chip records (iterations, final residuals, seconds)."""
     recs = []
-    for chip, B in zip(chips, Bs):
-        G = capi.HeatOperator.from_chip(chip, device, precond=precond)
-        k = torch.as_tensor(chip.k, device=device)
-        Bd = torch.as_tensor(B, device=device)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, info0 = capi.block_krylov_solve(G, Bd, tol, compute=compute)
-        t1 = time.perf_counter()
-        rec = {"zero_iters": info0["iters"], "zero_res": info0["max_rel_res"], "zero_s": t1 - t0}
-        if smooth > 0:
-            Z = torch.zeros_like(Bd)
-            capi.jacobi_smooth(G, Bd, Z, smooth)
-            _, infoz = capi.block_krylov_solve(G, Bd, tol, compute=compute, X0=Z)
-            rec.update({"zero_smooth_iters": infoz["iters"], "zero_smooth_res": infoz["max_rel_res"]})
+    for g0 in range(0, len(chips), group):
+        gchips, gB = chips[g0:g0 + group], Bs[g0:g0 + group]
+        Gs = [capi.HeatOperator.from_chip(chip, device, precond=precond) for chip in gchips]
+        ks = [torch.as_tensor(chip.k, device=device) for chip in gchips]
+        Bds = [torch.as_tensor(B, device=device) for B in gB]
+        grecs = []
+        for G, Bd in zip(Gs, Bds):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info0 = capi.block_krylov_solve(G, Bd, tol, compute=compute)
+            t1 = time.perf_counter()
+            rec = {"zero_iters": info0["iters"], "zero_res": info0["max_rel_res"], "zero_s": t1 - t0}
+            if smooth > 0:
+                Z = torch.zeros_like(Bd)
+                capi.jacobi_smooth(G, Bd, Z, smooth)
+                _, infoz = capi.block_krylov_solve(G, Bd, tol, compute=compute, X0=Z)
+                rec.update({"zero_smooth_iters": infoz["iters"], "zero_smooth_res": infoz["max_rel_res"]})
+            grecs.append(rec)
         if net is not None:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            X0 = predict_x0(net, norm, chip, k, Bd, G, smooth)
+            if group > 1:
+                X0s = predict_x0_group(net, norm, gchips, ks, Bds, Gs, smooth)
+            else:
+                X0s = [predict_x0(net, norm, gchips[0], ks[0], Bds[0], Gs[0], smooth)]
             torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            _, info1 = capi.block_krylov_solve(G, Bd, tol, compute=compute, X0=X0)
-            t2 = time.perf_counter()
-            rec.update({"learned_iters": info1["iters"], "learned_res": info1["max_rel_res"],
-                        "infer_s": t1 - t0, "learned_s": t2 - t1, "rejected": info1["x0_rejected"]})
-        recs.append(rec)
+            share = (time.perf_counter() - t0) / len(gchips)
+            for rec, G, Bd, X0 in zip(grecs, Gs, Bds, X0s):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _, info1 = capi.block_krylov_solve(G, Bd, tol, compute=compute, X0=X0)
+                t2 = time.perf_counter()
+                rec.update({"learned_iters": info1["iters"], "learned_res": info1["max_rel_res"],
+                            "infer_s": share, "learned_s": t2 - t1, "rejected": info1["x0_rejected"]})
+        recs.extend(grecs)
     return recs

@@ -261,3 +261,25 @@ def test_learned_start_cuts_block_iterations(dev, compute):
     assert all(r["learned_res"] <= 1e-8 and r["zero_smooth_res"] <= 1e-8 for r in recs)
     assert all(r["rejected"] == 0 for r in recs)
     assert learned < zero, [(r["zero_iters"], r["zero_smooth_iters"], r["learned_iters"]) for r in recs]
+
+
+def test_grouped_prediction_matches_per_chip(dev):
+    """Learned starts of several chips from one network pass equal the
+    per-chip predictions (the network treats every image on its own)."""
+    from paper_2510_23221_amd import lstart
+    w = synth.workload(4, grid=(32, 32, 4), nchips=2, m=16, s=8)
+    data = lstart.generate_pairs(w.chips, w.B, w.C, 1e-10, compute=capi.F64)
+    norm = lstart.fit_normalizer(data)
+    net = lstart.make_net(w.chips[0], base=8, max_batch=8, seed=0)
+    big = lstart.make_net(w.chips[0], base=8, max_batch=24, seed=5)
+    big.set_params(net.params)
+    chips, Bs = synth.learned_start_test_chips(3, (32, 32, 4), 8)
+    Gs = [capi.HeatOperator.from_chip(c, dev) for c in chips]
+    ks = [torch.as_tensor(c.k, device=dev) for c in chips]
+    Bds = [torch.as_tensor(B, device=dev) for B in Bs]
+    grouped = lstart.predict_x0_group(big, norm, chips, ks, Bds, Gs, smooth=5)
+    for chip, k, B, G, X0 in zip(chips, ks, Bds, Gs, grouped):
+        ref = lstart.predict_x0(net, norm, chip, k, B, G, smooth=5)
+        scale = float(ref.abs().max())
+        assert scale > 0
+        assert float((X0 - ref).abs().max()) <= 1e-6 * scale
