@@ -153,6 +153,37 @@ __device__ inline const ChipDev &chip_of(const ChipDev *cds, const uint16_t *tab
     return cd;
 }
 
+// The 256-cell tiles a workgroup of the stencil + Gram product takes, in
+// order.  When the chip's planes are whole tiles, the tiles are numbered
+// z-major (in-plane tile q, plane l -> q nz + l) and each workgroup takes a
+// run of consecutive numbers in the XCD-contiguous workgroup order, so it
+// walks consecutive planes of one in-plane tile: the neighbours one plane
+// away are the tiles it has just read or reads next, and the workgroups
+// beside it on the same XCD hold the neighbouring rows, all served from that
+// XCD's L2.  Otherwise the tiles are dealt round-robin.
+struct TileWalk {
+    int64_t i0, i1, step, tp;
+    int nz;
+    bool zmajor;
+    __device__ TileWalk(int local, int wgs, int64_t ntiles, int64_t plane, int nz_)
+    {
+        nz = nz_;
+        tp = plane / kTileRows;
+        zmajor = plane % kTileRows == 0 && tp * nz == ntiles;
+        if (zmajor) {
+            const int64_t per = (ntiles + wgs - 1) / wgs;
+            i0 = static_cast<int64_t>(remap_block(static_cast<uint32_t>(local), static_cast<uint32_t>(wgs))) * per;
+            i1 = i0 + per < ntiles ? i0 + per : ntiles;
+            step = 1;
+        } else {
+            i0 = local;
+            i1 = ntiles;
+            step = wgs;
+        }
+    }
+    __device__ int64_t tile(int64_t i) const { return zmajor ? i / nz + tp * (i % nz) : i; }
+};
+
 // ------------------------------------------------------------------ Gram partials
 
 // Row and column block of Gram block q: the upper blocks (a <= b) in order
@@ -292,7 +323,9 @@ __global__ __launch_bounds__(kSpThreads, (NB > 2 ? 2 : 1)) void spmm_gram_kernel
 #pragma unroll
     for (int q = 0; q < NB * (NB + 1) / 2; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
     const int64_t ntiles = ldw / kTileRows;
-    for (int64_t tile = local; tile < ntiles; tile += wgs) {
+    const TileWalk walk(local, wgs, ntiles, plane, nz);
+    for (int64_t it = walk.i0; it < walk.i1; it += walk.step) {
+        const int64_t tile = walk.tile(it);
         for (int half = 0; half < kTileRows / TR; ++half) {
             const int64_t a = tile * kTileRows + half * TR + cell;
             if (a < n) {
@@ -427,7 +460,9 @@ __global__ __launch_bounds__(kSpThreads, (NB > 2 ? 2 : 1)) void spmm_gram_vec_ke
 #pragma unroll
     for (int q = 0; q < NB * (NB + 1) / 2; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
     const int64_t ntiles = ldw / kTileRows;
-    for (int64_t tile = local; tile < ntiles; tile += wgs) {
+    const TileWalk walk(local, wgs, ntiles, plane, nz);
+    for (int64_t it = walk.i0; it < walk.i1; it += walk.step) {
+        const int64_t tile = walk.tile(it);
         for (int half = 0; half < kTileRows / TR; ++half) {
             const int64_t a = tile * kTileRows + half * TR + cell;
             if (a < n) {
