@@ -1058,10 +1058,14 @@ __global__ __launch_bounds__(kThreads) void update_w_kernel(const ChipDev *__res
 // holds rows 2 i + q), so that one 8-byte load gives a lane its operand in
 // both blocks and 16 lanes read a whole 128-byte line of a column; result
 // register r of the two blocks holds 2 consecutive rows (8 g + 2 r, + 1 for
-// lane group g), one 8-byte store.  The W^T W partial takes every row of
-// both blocks as a k slot of the FP64 matrix cores, as in update_w_kernel.
-// (Held to two waves per SIMD it spills; one wave with no spills measured
-// faster.)
+// lane group g), one 8-byte store.  The W^T W partial is shared out over the
+// waves: the 128 new rows of the four waves are staged in LDS (row stride of
+// 80 floats, so the four lane groups of a matrix-core read fall on disjoint
+// banks) and each wave accumulates whole upper 16 x 16 blocks of the Gram
+// over all of them on the FP64 matrix cores (NB (NB + 1) / 2 blocks: two per
+// wave for s <= 64, one for s <= 48, and the last two blocks split by rows
+// between pairs of waves).  Each wave then holds 3 or 2 accumulator blocks
+// instead of all of them, which keeps the kernel at two waves per SIMD.
 template <int NB>
 __global__ __launch_bounds__(kThreads) void update_w_rows2_kernel(const ChipDev *__restrict__ cds,
                                                                      const uint16_t *__restrict__ tab, int s, int init)
@@ -1073,9 +1077,15 @@ __global__ __launch_bounds__(kThreads) void update_w_rows2_kernel(const ChipDev 
     constexpr int KS = 4 * NB;
     constexpr int SP = 16 * NB;
     constexpr int MST = SP + 1;
+    constexpr int NBLK = NB * (NB + 1) / 2;
+    static_assert(NBLK % 4 == 2, "the Gram blocks split as whole blocks per wave plus two shared ones");
+    constexpr int FB = NBLK / 4;  // whole Gram blocks per wave
+    constexpr int SR = 4 * 32;    // rows staged per half tile (four waves x 32)
+    constexpr int WST = 80;       // row stride of the staged rows, floats
+    static_assert(SP <= WST, "staged row width");
     __shared__ float M3s[SP * MST];
     __shared__ float M2s[SP * MST];  // -M2
-    __shared__ double lds[kMaxS * kMaxS];
+    __shared__ __align__(16) float Wst[SR * WST];
     if (!init) {
         float *const dst[2] = {M3s, M2s};
         const gptr<const float> src[2] = {glb(static_cast<const float *>(cd.sm.M3f)),
@@ -1091,9 +1101,16 @@ __global__ __launch_bounds__(kThreads) void update_w_rows2_kernel(const ChipDev 
     const int li = lane & 15, lg = lane >> 4;
     const f2 zero = {0.f, 0.f};
     auto ld8 = [](gptr<const float> p) { return *reinterpret_cast<gptr<const f2>>(p); };
-    d4 g[NB * (NB + 1) / 2];
+    // this wave's Gram blocks: whole blocks wave + 4 f (f < FB), then half
+    // of block 4 FB + wave / 2 (rows 64 (wave % 2) .. + 64 of the stage)
+    int ga[FB + 1], gb[FB + 1];
 #pragma unroll
-    for (int q = 0; q < NB * (NB + 1) / 2; ++q) g[q] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int f = 0; f < FB; ++f) gram_block<NB, true>(wave + 4 * f, ga[f], gb[f]);
+    gram_block<NB, true>(4 * FB + (wave >> 1), ga[FB], gb[FB]);
+    const int hk0 = (wave & 1) * (SR / 2);
+    d4 g[FB + 1];
+#pragma unroll
+    for (int q = 0; q <= FB; ++q) g[q] = d4{0.0, 0.0, 0.0, 0.0};
     const int64_t ntiles = ldw / kTileRows;
     for (int64_t tile = local; tile < ntiles; tile += wgs) {
         for (int h = 0; h < 2; ++h) {
@@ -1111,33 +1128,40 @@ __global__ __launch_bounds__(kThreads) void update_w_rows2_kernel(const ChipDev 
                     }
                 }
             } else {
-                f2 wa[KS], aa[KS];
+                // W M3, then AP (-M2) with the AP rows in the same registers
+                // (one operand block live at a time)
+                f2 xa[KS];
 #pragma unroll
                 for (int t = 0; t < KS; ++t) {
                     const int col = 4 * t + lg;
-                    wa[t] = col < s ? ld8(gptr<const float>(W) + col * ldw + r0 + 2 * li) : zero;
-                    aa[t] = col < s ? ld8(AP + col * ldw + r0 + 2 * li) : zero;
+                    xa[t] = col < s ? ld8(gptr<const float>(W) + col * ldw + r0 + 2 * li) : zero;
                 }
 #pragma unroll
                 for (int jb = 0; jb < NB; ++jb) {
                     const int colj = jb * 16 + li;
-                    f4 acc[2];
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+                    for (int q = 0; q < 2; ++q) wv[jb][q] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                     for (int t = 0; t < KS; ++t) {
                         const float m3 = M3s[(4 * t + lg) * MST + colj];
 #pragma unroll
-                        for (int q = 0; q < 2; ++q) acc[q] = MF<float>::mma(wa[t][q], m3, acc[q]);
+                        for (int q = 0; q < 2; ++q) wv[jb][q] = MF<float>::mma(xa[t][q], m3, wv[jb][q]);
                     }
+                }
+#pragma unroll
+                for (int t = 0; t < KS; ++t) {
+                    const int col = 4 * t + lg;
+                    xa[t] = col < s ? ld8(AP + col * ldw + r0 + 2 * li) : zero;
+                }
+#pragma unroll
+                for (int jb = 0; jb < NB; ++jb) {
+                    const int colj = jb * 16 + li;
 #pragma unroll
                     for (int t = 0; t < KS; ++t) {
                         const float m2 = M2s[(4 * t + lg) * MST + colj];
 #pragma unroll
-                        for (int q = 0; q < 2; ++q) acc[q] = MF<float>::mma(aa[t][q], m2, acc[q]);
+                        for (int q = 0; q < 2; ++q) wv[jb][q] = MF<float>::mma(xa[t][q], m2, wv[jb][q]);
                     }
-                    wv[jb][0] = acc[0];
-                    wv[jb][1] = acc[1];
                 }
                 // every lane has read its rows of W: write the new rows
 #pragma unroll
@@ -1152,20 +1176,60 @@ __global__ __launch_bounds__(kThreads) void update_w_rows2_kernel(const ChipDev 
                     }
                 }
             }
+            // stage the new rows (columns s .. SP are zero: their operands were)
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
+            for (int jb = 0; jb < NB; ++jb)
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
+                for (int q = 0; q < 2; ++q)
 #pragma unroll
-                    for (int ab = 0; ab < NB; ++ab)
+                    for (int r = 0; r < 4; ++r)
+                        Wst[(wave * 32 + 8 * lg + 2 * r + q) * WST + jb * 16 + li] = wv[jb][q][r];
+            __syncthreads();
+            // W^T W over the staged rows: row k0 + lg is the k slot of lane group lg
 #pragma unroll
-                        for (int bb = ab; bb < NB; ++bb)
-                            g[ublock<NB>(ab, bb)] = mma64(static_cast<double>(wv[ab][q][r]),
-                                                          static_cast<double>(wv[bb][q][r]), g[ublock<NB>(ab, bb)]);
+            for (int f = 0; f < FB; ++f) {
+                const float *pa = Wst + lg * WST + ga[f] * 16 + li, *pb = Wst + lg * WST + gb[f] * 16 + li;
+#pragma unroll 8
+                for (int k0 = 0; k0 < SR; k0 += 4)
+                    g[f] = mma64(static_cast<double>(pa[k0 * WST]), static_cast<double>(pb[k0 * WST]), g[f]);
+            }
+            {
+                const float *pa = Wst + (hk0 + lg) * WST + ga[FB] * 16 + li;
+                const float *pb = Wst + (hk0 + lg) * WST + gb[FB] * 16 + li;
+#pragma unroll 8
+                for (int k0 = 0; k0 < SR / 2; k0 += 4)
+                    g[FB] = mma64(static_cast<double>(pa[k0 * WST]), static_cast<double>(pb[k0 * WST]), g[FB]);
+            }
+            __syncthreads();  // the next half overwrites the stage
         }
     }
-    static_assert(kMaxS * kMaxS >= publish_lds<kThreads>(4), "publish_partial LDS");
-    publish_partial<NB, true>(g, s, lds, glb(cd.parts) + static_cast<size_t>(local) * s * s);
+    // publish: whole blocks by their wave; the shared blocks summed through LDS
+    const gptr<double> out = glb(cd.parts) + static_cast<size_t>(local) * s * s;
+    auto put = [&](int a, int b, const d4 &v) {
+        const int j = b * 16 + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = a * 16 + mfma_row<true>(lg, r);
+            if (i < s && j < s) {
+                out[i * s + j] = v[r];
+                if (a != b) out[j * s + i] = v[r];
+            }
+        }
+    };
+#pragma unroll
+    for (int f = 0; f < FB; ++f) put(ga[f], gb[f], g[f]);
+    double *xs = reinterpret_cast<double *>(Wst);
+    if (wave & 1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xs[((wave >> 1) * 4 + r) * 64 + lane] = g[FB][r];
+    }
+    __syncthreads();
+    if (!(wave & 1)) {
+        d4 v = g[FB];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] += xs[((wave >> 1) * 4 + r) * 64 + lane];
+        put(ga[FB], gb[FB], v);
+    }
 }
 
 // D += P M1 ;  P = W M3 + P M4   (matrix cores, storage precision; Q = W M3)
