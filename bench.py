@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--workload", choices=["single", "batched", "learned"], default="single",
                     help="single chip (default), batch of uneven chips, or learned start")
     ap.add_argument("--nchips", type=int, default=None)
-    ap.add_argument("--train-epochs", type=float, default=2.0)
+    ap.add_argument("--train-epochs", type=float, default=4.0)
     ap.add_argument("--test-chips", type=int, default=256)
     ap.add_argument("--infer-chips", type=int, default=16,
                     help="unseen chips whose learned starts come from one network pass")
