@@ -153,8 +153,9 @@ __device__ inline const ChipDev &chip_of(const ChipDev *cds, const uint16_t *tab
     return cd;
 }
 
-// The 256-cell tiles a workgroup of the stencil + Gram product takes, in
-// order.  When the chip's planes are whole tiles, the tiles are numbered
+// The tiles (of `unit` consecutive cells: 256, or one LDS stage) a
+// workgroup of the stencil + Gram product takes, in order.  When the chip's
+// planes are whole tiles, the tiles are numbered
 // z-major (in-plane tile q, plane l -> q nz + l) and each workgroup takes a
 // run of consecutive numbers in the XCD-contiguous workgroup order, so it
 // walks consecutive planes of one in-plane tile: the neighbours one plane
@@ -165,11 +166,11 @@ struct TileWalk {
     int64_t i0, i1, step, tp;
     int nz;
     bool zmajor;
-    __device__ TileWalk(int local, int wgs, int64_t ntiles, int64_t plane, int nz_)
+    __device__ TileWalk(int local, int wgs, int64_t ntiles, int64_t plane, int nz_, int unit = kTileRows)
     {
         nz = nz_;
-        tp = plane / kTileRows;
-        zmajor = plane % kTileRows == 0 && tp * nz == ntiles;
+        tp = plane / unit;
+        zmajor = plane % unit == 0 && tp * nz == ntiles;
         if (zmajor) {
             const int64_t per = (ntiles + wgs - 1) / wgs;
             i0 = static_cast<int64_t>(remap_block(static_cast<uint32_t>(local), static_cast<uint32_t>(wgs))) * per;
@@ -411,7 +412,17 @@ template <class T> __device__ __forceinline__ typename Vec16<T>::type ld16(gptr<
 // that every access to P, AP, the coefficients and the LDS stage is one
 // 16-byte operation (chips whose nx is a multiple of V: a group of V cells
 // then lies in one x-row).  The x neighbours inside the group come from its
-// own vector, the two outside it from scalar loads.
+// own vector, the two outside it from scalar loads.  The unit of work is one
+// LDS stage of TR rows, walked as TileWalk orders it; in a z-major walk of
+// FP32 blocks with s > 32 (streamed from HBM) each thread keeps its vectors
+// of the current plane and the plane above from one stage to the next
+// (kCarry), so a run of planes reads each vector of P once for its own plane
+// and as the z neighbours of the planes beside it.  For s > 32 the Gram
+// blocks are shared out over the waves (kOwn): each wave accumulates whole
+// upper 16 x 16 blocks over all staged rows, and the NBLK % 4 remaining
+// blocks over a quarter of the rows each (summed through LDS at the end), so
+// a wave holds at most four accumulator blocks; for s <= 32 each wave takes
+// every block over a quarter of the rows.
 template <class T, int NB>
 __global__ __launch_bounds__(kSpThreads, (NB > 2 ? 2 : 1)) void spmm_gram_vec_kernel(const ChipDev *__restrict__ cds,
                                                                                       const uint16_t *__restrict__ tab,
@@ -424,8 +435,15 @@ __global__ __launch_bounds__(kSpThreads, (NB > 2 ? 2 : 1)) void spmm_gram_vec_ke
     constexpr int LD = stage_ld<T, NB>();
     constexpr int TPC = TR / V;              // threads per column class
     constexpr int CSTEP = kSpThreads / TPC;  // column classes
+    constexpr int NCOL = (SP + CSTEP - 1) / CSTEP;  // columns per thread at most
     constexpr int NW = kSpThreads / 64;
+    constexpr int NBLK = NB * (NB + 1) / 2;
+    constexpr int FB = NBLK / NW;  // whole Gram blocks per wave
+    constexpr int RB = NBLK % NW;  // blocks shared by every wave (a quarter of the rows each)
+    constexpr bool kCarry = sizeof(T) == 4 && NB > 2;
+    constexpr bool kOwn = NB > 2;  // Gram blocks owned by waves
     static_assert(kSpThreads % TPC == 0 && (LD * sizeof(T)) % 16 == 0, "vector staging");
+    static_assert(TR % (16 * NW) == 0, "row quarters of the Gram");
     int local;
     const ChipDev &cd = chip_of(cds, tab, local);
     const int wgs = cd.wgs;
@@ -456,58 +474,107 @@ __global__ __launch_bounds__(kSpThreads, (NB > 2 ? 2 : 1)) void spmm_gram_vec_ke
     const int cell = (tid % TPC) * V, cls = tid / TPC;
     const VT zero = VT(T(0));
 
-    d4 acc[NB * (NB + 1) / 2];  // upper blocks of P^T AP (symmetric)
+    // s > 32: this wave's Gram blocks are whole blocks wave + NW f and a
+    // quarter of the rows of each shared block NW FB + r; s <= 32: every
+    // block over a quarter of the rows
+    constexpr int NACC = kOwn ? FB + RB : NBLK;
+    int ga[NACC], gb[NACC];
+    if constexpr (kOwn) {
 #pragma unroll
-    for (int q = 0; q < NB * (NB + 1) / 2; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-    const int64_t ntiles = ldw / kTileRows;
-    const TileWalk walk(local, wgs, ntiles, plane, nz);
+        for (int f = 0; f < FB; ++f) gram_block<NB, true>(wave + NW * f, ga[f], gb[f]);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) gram_block<NB, true>(NW * FB + r, ga[FB + r], gb[FB + r]);
+    }
+    d4 acc[NACC];
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+
+    VT c0[kCarry ? NCOL : 1], c1[kCarry ? NCOL : 1];  // plane below and this plane, carried
+    const TileWalk walk(local, wgs, ldw / TR, plane, nz, TR);
     for (int64_t it = walk.i0; it < walk.i1; it += walk.step) {
-        const int64_t tile = walk.tile(it);
-        for (int half = 0; half < kTileRows / TR; ++half) {
-            const int64_t a = tile * kTileRows + half * TR + cell;
-            if (a < n) {
-                const int i0 = static_cast<int>(a % nx);
-                const int64_t q = a / nx;
-                const int j = static_cast<int>(q % ny);
-                const int l = static_cast<int>(q / ny);
-                // a missing neighbour reads the group itself with a zero coupling
-                const int64_t oxl = i0 > 0 ? -1 : 0, oxr = i0 + V < nx ? V : V - 1;
-                const int64_t oym = j > 0 ? -static_cast<int64_t>(nx) : 0, oyp = j < ny - 1 ? nx : 0;
-                const int64_t ozm = l > 0 ? -plane : 0, ozp = l < nz - 1 ? plane : 0;
-                const VT d = ld16(cdiag + a), cxp = ld16(cwx + a), cyp = ld16(cwy + a), czp = ld16(cwz + a);
-                const VT cym = j > 0 ? ld16(cwy + a - nx) : zero;
-                const VT czm = l > 0 ? ld16(cwz + a - plane) : zero;
-                VT cxm;
-                cxm[0] = i0 > 0 ? cwx[a - 1] : T(0);
+        const int64_t a = walk.tile(it) * TR + cell;
+        // the previous stage of this workgroup was the same rows one plane down
+        const bool cont = kCarry && walk.zmajor && it != walk.i0 && it % nz != 0;
+        if (a < n) {
+            const int i0 = static_cast<int>(a % nx);
+            const int64_t q = a / nx;
+            const int j = static_cast<int>(q % ny);
+            const int l = static_cast<int>(q / ny);
+            // a missing neighbour reads the group itself with a zero coupling
+            const int64_t oxl = i0 > 0 ? -1 : 0, oxr = i0 + V < nx ? V : V - 1;
+            const int64_t oym = j > 0 ? -static_cast<int64_t>(nx) : 0, oyp = j < ny - 1 ? nx : 0;
+            const int64_t ozm = l > 0 ? -plane : 0, ozp = l < nz - 1 ? plane : 0;
+            const VT d = ld16(cdiag + a), cxp = ld16(cwx + a), cyp = ld16(cwy + a), czp = ld16(cwz + a);
+            const VT cym = j > 0 ? ld16(cwy + a - nx) : zero;
+            const VT czm = l > 0 ? ld16(cwz + a - plane) : zero;
+            VT cxm;
+            cxm[0] = i0 > 0 ? cwx[a - 1] : T(0);
 #pragma unroll
-                for (int e = 1; e < V; ++e) cxm[e] = cxp[e - 1];
-#pragma unroll 2
-                for (int c = cls; c < s; c += CSTEP) {
-                    const gptr<const T> x = P + c * ldw + a;
-                    const VT xc = ld16(x), xym = ld16(x + oym), xyp = ld16(x + oyp), xzm = ld16(x + ozm),
-                             xzp = ld16(x + ozp);
-                    const T xl = x[oxl], xr = x[oxr];
-                    VT y;
-#pragma unroll
-                    for (int e = 0; e < V; ++e) {
-                        const T left = e == 0 ? xl : xc[e > 0 ? e - 1 : 0];
-                        const T right = e == V - 1 ? xr : xc[e < V - 1 ? e + 1 : 0];
-                        const T nb = cxm[e] * left + cxp[e] * right + cym[e] * xym[e] + cyp[e] * xyp[e] +
-                                     czm[e] * xzm[e] + czp[e] * xzp[e];
-                        y[e] = d[e] * xc[e] - nb;
-                    }
-                    *reinterpret_cast<gptr<VT>>(AP + c * ldw + a) = y;
-                    *reinterpret_cast<VT *>(Ps + c * LD + cell) = xc;
-                    *reinterpret_cast<VT *>(APs + c * LD + cell) = y;
+            for (int e = 1; e < V; ++e) cxm[e] = cxp[e - 1];
+            auto column = [&](int c, VT &k0, VT &k1) __attribute__((always_inline)) {
+                const gptr<const T> x = P + c * ldw + a;
+                VT xc, xzm;
+                if (cont) {
+                    xzm = k0;
+                    xc = k1;
+                } else {
+                    xc = ld16(x);
+                    xzm = ld16(x + ozm);
                 }
+                const VT xym = ld16(x + oym), xyp = ld16(x + oyp), xzp = ld16(x + ozp);
+                const T xl = x[oxl], xr = x[oxr];
+                VT y;
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const T left = e == 0 ? xl : xc[e > 0 ? e - 1 : 0];
+                    const T right = e == V - 1 ? xr : xc[e < V - 1 ? e + 1 : 0];
+                    const T nb = cxm[e] * left + cxp[e] * right + cym[e] * xym[e] + cyp[e] * xyp[e] +
+                                 czm[e] * xzm[e] + czp[e] * xzp[e];
+                    y[e] = d[e] * xc[e] - nb;
+                }
+                *reinterpret_cast<gptr<VT>>(AP + c * ldw + a) = y;
+                *reinterpret_cast<VT *>(Ps + c * LD + cell) = xc;
+                *reinterpret_cast<VT *>(APs + c * LD + cell) = y;
+                k0 = xc;
+                k1 = xzp;
+            };
+            if constexpr (kCarry) {
+#pragma unroll
+                for (int k = 0; k < NCOL; ++k)
+                    if (cls + k * CSTEP < s) column(cls + k * CSTEP, c0[k], c1[k]);
             } else {
-                // padding rows of the tile: zero in the Gram (AP keeps its zero padding)
-                for (int c = cls; c < s; c += CSTEP) {
-                    *reinterpret_cast<VT *>(Ps + c * LD + cell) = zero;
-                    *reinterpret_cast<VT *>(APs + c * LD + cell) = zero;
-                }
+#pragma unroll 2
+                for (int c = cls; c < s; c += CSTEP) column(c, c0[0], c1[0]);
             }
-            __syncthreads();
+        } else {
+            // padding rows of the stage: zero in the Gram (AP keeps its zero padding)
+            for (int c = cls; c < s; c += CSTEP) {
+                *reinterpret_cast<VT *>(Ps + c * LD + cell) = zero;
+                *reinterpret_cast<VT *>(APs + c * LD + cell) = zero;
+            }
+        }
+        __syncthreads();
+        if constexpr (kOwn) {
+            // P^T AP over the staged rows: row k0 + lg is the k slot of lane group lg
+#pragma unroll
+            for (int f = 0; f < FB; ++f) {
+                const T *pa = Ps + (ga[f] * 16 + li) * LD + lg, *pb = APs + (gb[f] * 16 + li) * LD + lg;
+#pragma unroll 8
+                for (int k0 = 0; k0 < TR; k0 += 4)
+                    acc[f] = mma64(static_cast<double>(pa[k0]), static_cast<double>(pb[k0]), acc[f]);
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int rows0 = wave * (TR / NW);
+                const T *pa = Ps + (ga[FB + r] * 16 + li) * LD + rows0 + lg;
+                const T *pb = APs + (gb[FB + r] * 16 + li) * LD + rows0 + lg;
+#pragma unroll 8
+                for (int k0 = 0; k0 < TR / NW; k0 += 4)
+                    acc[FB + r] = mma64(static_cast<double>(pa[k0]), static_cast<double>(pb[k0]), acc[FB + r]);
+            }
+        } else {
+            // every block over this wave's quarter of the staged rows: rows
+            // r + t feed matrix-core step t for lane group lg
 #pragma unroll
             for (int rb = 0; rb < TR / (16 * NW); ++rb) {
                 const int r = wave * (TR / NW) + rb * 16 + lg * 4;
@@ -529,11 +596,50 @@ __global__ __launch_bounds__(kSpThreads, (NB > 2 ? 2 : 1)) void spmm_gram_vec_ke
                         for (int y = x; y < NB; ++y)
                             acc[ublock<NB>(x, y)] = mma64(u[x][t], v[y][t], acc[ublock<NB>(x, y)]);
             }
+        }
+        __syncthreads();
+    }
+    if constexpr (!kOwn) {
+        static_assert(spmm_gram_lds<T, NB>() >= sizeof(double) * publish_lds<kSpThreads>(NB * NB < 4 ? NB * NB : 4),
+                      "publish_partial needs more LDS than the staged tiles");
+        publish_partial<NB, true, NBLK, kSpThreads>(acc, s, reinterpret_cast<double *>(smem),
+                                                    glb(cd.parts) + static_cast<size_t>(local) * s * s);
+        return;
+    } else {
+        // publish: whole blocks by their wave; the shared blocks summed through LDS
+        const gptr<double> out = glb(cd.parts) + static_cast<size_t>(local) * s * s;
+        auto put = [&](int ab, int bb, const d4 &v) {
+            const int jj = bb * 16 + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ii = ab * 16 + mfma_row<true>(lg, r);
+                if (ii < s && jj < s) {
+                    out[ii * s + jj] = v[r];
+                    if (ab != bb) out[jj * s + ii] = v[r];
+                }
+            }
+        };
+#pragma unroll
+        for (int f = 0; f < FB; ++f) put(ga[f], gb[f], acc[f]);
+        if constexpr (RB > 0) {
+            static_assert(spmm_gram_lds<T, NB>() >= sizeof(double) * RB * NW * 4 * 64, "LDS for the shared blocks");
+            double *xs = reinterpret_cast<double *>(smem);
+            __syncthreads();  // the stage is dead (also when this workgroup had no rows)
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) xs[((r * NW + wave) * 4 + e) * 64 + lane] = acc[FB + r][e];
             __syncthreads();
+            for (int r = wave; r < RB; r += NW) {
+                d4 v = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int w = 0; w < NW; ++w)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] += xs[((r * NW + w) * 4 + e) * 64 + lane];
+                put(ga[FB + r], gb[FB + r], v);
+            }
         }
     }
-    publish_partial<NB, true, NB * (NB + 1) / 2, kSpThreads>(acc, s, reinterpret_cast<double *>(smem),
-                                                    glb(cd.parts) + static_cast<size_t>(local) * s * s);
 }
 
 // gram = sum over the chip's partials, entry by entry in index order
