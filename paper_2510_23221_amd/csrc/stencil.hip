@@ -125,6 +125,12 @@ __device__ __forceinline__ void vstore(T *p, const Vec<T, N> &r)
     }
 }
 
+// Planes of the tile kept in LDS: a ring of three (this plane, the next,
+// the one after) when the plane's LDS type is narrower than 8 bytes, else two
+// (double-buffered; three FP64 planes would hold the kernel to two
+// workgroups per CU, measured slower); ls = bytes of the LDS type.
+__host__ __device__ constexpr int lds_planes(int ls) { return ls < 8 ? 3 : 2; }
+
 // 16-byte vectors per thread and plane: as many as keep each of the plane
 // arrays carried in registers (previous, current, next plane and the
 // coupling below) at 64 bytes of accumulator values per thread, between one
@@ -188,6 +194,126 @@ __device__ __forceinline__ void stencil_tile_body(
         vrow[r] = vok[r] ? q / nvx : 0;
         vx0[r] = vok[r] ? (q % nvx) * VX : 0;
     }
+    // halo work: rows j0 - 1 and j0 + rows of the current plane
+    const int hq = tid;  // < 2 * nvx handled by this thread
+    const bool hok = hq < 2 * nvx;
+    const int hside = hok ? hq / nvx : 0;
+    const int hx0 = hok ? (hq % nvx) * VX : 0;
+    const int hy = hside == 0 ? j0 - 1 : j0 + rows;
+    const bool hin = hok && hy >= 0 && hy < ny;
+    const int hlrow = hside == 0 ? 0 : rows + 1;
+
+    if constexpr (lds_planes(sizeof(Ls)) == 3) {
+        // Ring of three planes in LDS: the raw vectors of plane l + 2 (tile
+        // and halo rows) are requested at the start of plane l and stored
+        // into the ring at its end, so their HBM latency overlaps the work of
+        // plane l; plane l and its upper neighbours are read from the ring,
+        // the plane below from registers.  Slot (l + 2) % 3 held plane l - 1,
+        // whose last readers finished before this plane's barrier.
+        Vec<Tin, VX> raw[R], hraw;
+        auto slot = [&](int l) { return buf0 + (l % 3) * bufsz; };
+        auto fetch = [&](int l) __attribute__((always_inline)) {
+            const int64_t pl = static_cast<int64_t>(l) * plane;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (vok[r] && l < nz) {
+                    raw[r] = vload<Tin, VX>(xf + pl + static_cast<int64_t>(j0 + vrow[r]) * nx + vx0[r]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) raw[r].v[e] = Tin{};
+                }
+            }
+            if (hin && l < nz) {
+                hraw = vload<Tin, VX>(xf + pl + static_cast<int64_t>(hy) * nx + hx0);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VX; ++e) hraw.v[e] = Tin{};
+            }
+        };
+        auto to_lds = [](const Vec<Tin, VX> &v) __attribute__((always_inline)) {
+            if constexpr (std::is_same_v<Ls, Tin>) {
+                return v;
+            } else {
+                Vec<Ls, VX> o;
+#pragma unroll
+                for (int e = 0; e < VX; ++e) o.v[e] = store_from<Ls, Acc>(load_as<Acc>(&v.v[e]));
+                return o;
+            }
+        };
+        auto stash = [&](int l) __attribute__((always_inline)) {
+            Ls *b = slot(l);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (vok[r]) vstore<Ls, VX>(b + (vrow[r] + 1) * nx + vx0[r], to_lds(raw[r]));
+            if (hok) vstore<Ls, VX>(b + hlrow * nx + hx0, to_lds(hraw));
+        };
+        fetch(0);
+        stash(0);
+        fetch(1);
+        stash(1);
+        Acc prev[R][VX], wzm[R][VX];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                prev[r][e] = Acc(0);
+                wzm[r][e] = Acc(0);
+            }
+        for (int l = 0; l < nz; ++l) {
+            const int64_t pl = static_cast<int64_t>(l) * plane;
+            fetch(l + 2);
+            __syncthreads();
+            const Ls *bc = slot(l), *bn = slot(l + 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!vok[r]) continue;
+                const int j = j0 + vrow[r];
+                const int64_t a = pl + static_cast<int64_t>(j) * nx + vx0[r];
+                const Vec<Tc, VX> d = vload<Tc, VX>(diag + a);
+                const Vec<Tc, VX> cx = vload<Tc, VX>(wx + a);
+                const Vec<Tc, VX> cy = vload<Tc, VX>(wy + a);
+                const Vec<Tc, VX> cz = vload<Tc, VX>(wz + a);
+                Acc cym[VX];
+                if (j > 0) {
+                    const Vec<Tc, VX> t = vload<Tc, VX>(wy + a - nx);
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) cym[e] = static_cast<Acc>(t.v[e]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) cym[e] = Acc(0);
+                }
+                const Acc cxm0 = vx0[r] > 0 ? static_cast<Acc>(wx[a - 1]) : Acc(0);
+                const int off = (vrow[r] + 1) * nx + vx0[r];
+                const Ls *brow = bc + off;
+                const Vec<Ls, VX> cv = vload<Ls, VX>(brow), nv = vload<Ls, VX>(bn + off);
+                const Vec<Ls, VX> upv = vload<Ls, VX>(brow - nx), dnv = vload<Ls, VX>(brow + nx);
+                const Acc left = vx0[r] > 0 ? load_as<Acc>(brow - 1) : Acc(0);
+                const Acc right = vx0[r] + VX < nx ? load_as<Acc>(brow + VX) : Acc(0);
+                Acc cur[VX];
+#pragma unroll
+                for (int e = 0; e < VX; ++e) cur[e] = load_as<Acc>(&cv.v[e]);
+                Vec<Tout, VX> out;
+#pragma unroll
+                for (int e = 0; e < VX; ++e) {
+                    const Acc xm = e > 0 ? cur[e - 1] : left;
+                    const Acc xp = e < VX - 1 ? cur[e + 1] : right;
+                    const Acc cxm = e > 0 ? static_cast<Acc>(cx.v[e - 1]) : cxm0;
+                    const Acc nb = cxm * xm + static_cast<Acc>(cx.v[e]) * xp + cym[e] * load_as<Acc>(&upv.v[e]) +
+                                   static_cast<Acc>(cy.v[e]) * load_as<Acc>(&dnv.v[e]) + wzm[r][e] * prev[r][e] +
+                                   static_cast<Acc>(cz.v[e]) * load_as<Acc>(&nv.v[e]);
+                    Acc y = static_cast<Acc>(d.v[e]) * cur[e] - nb;
+                    if constexpr (kResidual) y = static_cast<Acc>(bf[a + e]) - y;
+                    out.v[e] = store_from<Tout, Acc>(y);
+                    wzm[r][e] = static_cast<Acc>(cz.v[e]);
+                    prev[r][e] = cur[e];
+                }
+                vstore<Tout, VX>(yf + a, out);
+            }
+            stash(l + 2);
+        }
+        return;
+    }
+
     Acc prev[R][VX], cur[R][VX], nxt[R][VX], wzm[R][VX];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -203,14 +329,6 @@ __device__ __forceinline__ void stencil_tile_body(
             for (int e = 0; e < VX; ++e) cur[r][e] = load_as<Acc>(&v.v[e]);
         }
     }
-    // halo work: rows j0 - 1 and j0 + rows of the current plane
-    const int hq = tid;  // < 2 * nvx handled by this thread
-    const bool hok = hq < 2 * nvx;
-    const int hside = hok ? hq / nvx : 0;
-    const int hx0 = hok ? (hq % nvx) * VX : 0;
-    const int hy = hside == 0 ? j0 - 1 : j0 + rows;
-    const bool hin = hok && hy >= 0 && hy < ny;
-    const int hlrow = hside == 0 ? 0 : rows + 1;
 
     for (int l = 0; l < nz; ++l) {
         const int64_t pl = static_cast<int64_t>(l) * plane;
@@ -391,7 +509,8 @@ bko_status run(const Operator &op, const Tc *diag, const Tc *wx, const Tc *wy, c
     if (ty > 0) {
         const int ntiles = (op.ny + ty - 1) / ty;
         const uint64_t nb = static_cast<uint64_t>(ntiles) * m;
-        const size_t lds = 2 * std::min(sizeof(Acc), sizeof(Tin)) * static_cast<size_t>(ty + 2) * op.nx;
+        const size_t ls = std::min(sizeof(Acc), sizeof(Tin));
+        const size_t lds = lds_planes(static_cast<int>(ls)) * ls * static_cast<size_t>(ty + 2) * op.nx;
         hipLaunchKernelGGL((stencil_tile_kernel<Tin, Tout, Tc, Acc, kResidual>), dim3(static_cast<uint32_t>(nb)),
                            dim3(kThreads), lds, stream, diag, wx, wy, wz, op.nx, op.ny, op.nz,
                            static_cast<const Tin *>(X), ldx, static_cast<Tout *>(Y), ldy, Bres, ldb, ty, ntiles,
@@ -568,7 +687,7 @@ bko_status launch_stencil_group(const Operator *const *ops, int nchips, const in
         j.m = m[c];
         j.block0 = static_cast<uint32_t>(total);
         total += static_cast<uint64_t>(j.ntiles) * m[c];
-        lds = std::max(lds, 2 * ls * static_cast<size_t>(ty + 2) * op.nx);
+        lds = std::max(lds, lds_planes(static_cast<int>(ls)) * ls * static_cast<size_t>(ty + 2) * op.nx);
         jobs.push_back(j);
     }
     if (total > 0x7fffffffu) {
