@@ -10,8 +10,8 @@
 //                        - wz_a x_{a+p} - wz_{a-p} x_{a-p},     p = nx*ny.
 //
 // Two kernels.  stencil_tile_kernel (the operator action over many fields):
-// full-width row tiles marched through z with the current plane in LDS and
-// 16-byte vector access; stencil_kernel (short tiles, unaligned views, the
+// full-width row tiles marched through z with the planes in LDS (a ring of
+// three for BF16/FP32 planes) and 16-byte vector access; stencil_kernel (short tiles, unaligned views, the
 // FP64 residual): a workgroup owns 256 consecutive cells and a group of
 // columns, each thread loading its cell's seven coefficients once for every
 // column of the group.  Both remap the workgroup order so that each XCD walks
@@ -142,9 +142,11 @@ __host__ __device__ constexpr int tile_vecs(int vx, int acc_bytes)
 }
 
 // A workgroup owns full-width rows [j0, j0 + TY) of one field and marches
-// through the nz planes.  The current plane of the tile plus one halo row on
-// each side sits in LDS (double-buffered, so one barrier per plane); the
-// planes below and above are carried in registers.  Every global access of
+// through the nz planes with one barrier per plane.  FP64 planes: the
+// current plane of the tile plus one halo row on each side sits in LDS
+// (double-buffered), the planes below and above in registers.  Narrower
+// planes: a ring of three planes with their halo rows in LDS (below).  Every
+// global access of
 // the field is a 16-byte vector access of consecutive cells.  Workgroups are
 // ordered field-fastest within a tile and each XCD walks a contiguous range,
 // so the coefficients of a tile (as many bytes per cell as the field itself,
