@@ -1247,8 +1247,10 @@ __global__ __launch_bounds__(kThreads) void update_w_rows2_kernel(const ChipDev 
                     const int colj = jb * 16 + li;
 #pragma unroll
                     for (int q = 0; q < 2; ++q) wv[jb][q] = f4{0.f, 0.f, 0.f, 0.f};
+                    // M3 = S^+ is upper triangular: the k steps of 16-row
+                    // blocks below the column block are zero
 #pragma unroll
-                    for (int t = 0; t < KS; ++t) {
+                    for (int t = 0; t < 4 * (jb + 1); ++t) {
                         const float m3 = M3s[(4 * t + lg) * MST + colj];
 #pragma unroll
                         for (int q = 0; q < 2; ++q) wv[jb][q] = MF<float>::mma(xa[t][q], m3, wv[jb][q]);
@@ -1480,21 +1482,28 @@ __global__ __launch_bounds__(kThreads) void update_dqp_rows4_kernel(const ChipDe
                     ap[q][r] = 0.f;
                 }
             }
+            // M3 = S^+ is upper and M4 = S^T lower triangular: k steps in
+            // 16-row blocks below (M3) or above (M4) the column block are
+            // zero and skipped
 #pragma unroll
             for (int t = 0; t < KS; ++t) {
                 const int k = 4 * t + lg;
-                const float m1 = M1[k * MST + colj], m3 = M3[k * MST + colj];
+                const float m1 = M1[k * MST + colj];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    ad[q] = MF<float>::mma(pa[t][q], m1, ad[q]);
-                    ap[q] = MF<float>::mma(wa[t][q], m3, ap[q]);
+                for (int q = 0; q < 4; ++q) ad[q] = MF<float>::mma(pa[t][q], m1, ad[q]);
+                if (t < 4 * (jb + 1)) {
+                    const float m3 = M3[k * MST + colj];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) ap[q] = MF<float>::mma(wa[t][q], m3, ap[q]);
                 }
             }
 #pragma unroll
             for (int t = 0; t < KS; ++t) {
-                const float m4 = M4[(4 * t + lg) * MST + colj];
+                if (t >= 4 * jb) {
+                    const float m4 = M4[(4 * t + lg) * MST + colj];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) ap[q] = MF<float>::mma(pa[t][q], m4, ap[q]);
+                    for (int q = 0; q < 4; ++q) ap[q] = MF<float>::mma(pa[t][q], m4, ap[q]);
+                }
             }
             if (colj < s) {
 #pragma unroll
