@@ -1127,8 +1127,9 @@ __global__ __launch_bounds__(kThreads) void update_w_kernel(const ChipDev *__res
                     V acc;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) acc[r] = T(0);
+                    // S^+ is upper triangular: no k steps below the column block
 #pragma unroll
-                    for (int t = 0; t < KS; ++t) acc = MF<T>::mma(wa[t], M3s[(4 * t + lg) * MST + colj], acc);
+                    for (int t = 0; t < 4 * (jb + 1); ++t) acc = MF<T>::mma(wa[t], M3s[(4 * t + lg) * MST + colj], acc);
 #pragma unroll
                     for (int t = 0; t < KS; ++t) acc = MF<T>::mma(aa[t], M2s[(4 * t + lg) * MST + colj], acc);
                     wv[jb] = acc;
@@ -1398,14 +1399,17 @@ __global__ __launch_bounds__(kThreads) void update_dqp_kernel(const ChipDev *__r
                     ad[r] = colj < s ? D[colj * ldw + r0 + mfma_row<kF64>(lg, r)] : T(0);
                     ap[r] = T(0);
                 }
+                // S^+ upper, S^T lower triangular: only their nonzero 16-row
+                // blocks (jb is uniform: the guards are scalar branches)
 #pragma unroll
                 for (int t = 0; t < KS; ++t) {
                     const int k = 4 * t + lg;
                     ad = MF<T>::mma(pa[t], M1[k * MST + colj], ad);
-                    ap = MF<T>::mma(wa[t], M3[k * MST + colj], ap);
+                    if (t < 4 * (jb + 1)) ap = MF<T>::mma(wa[t], M3[k * MST + colj], ap);
                 }
 #pragma unroll
-                for (int t = 0; t < KS; ++t) ap = MF<T>::mma(pa[t], M4[(4 * t + lg) * MST + colj], ap);
+                for (int t = 0; t < KS; ++t)
+                    if (t >= 4 * jb) ap = MF<T>::mma(pa[t], M4[(4 * t + lg) * MST + colj], ap);
                 if (colj < s) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
@@ -1591,8 +1595,9 @@ __global__ __launch_bounds__(kThreads) void update_w_fused_kernel(const ChipDev 
                 V acc;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) acc[r] = T(0);
+                // S^+ is upper triangular: no k steps below the column block
 #pragma unroll
-                for (int t = 0; t < KS; ++t) acc = MF<T>::mma(wa[p][t], M3s[(4 * t + lg) * MST + colj], acc);
+                for (int t = 0; t < 4 * (jb + 1); ++t) acc = MF<T>::mma(wa[p][t], M3s[(4 * t + lg) * MST + colj], acc);
                 wm[p][jb] = acc;
             }
     };
@@ -1843,10 +1848,11 @@ __global__ __launch_bounds__(kThreads) void update_dqp_fused_kernel(const ChipDe
                     V ap;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) ap[r] = T(0);
+                    // S^+ upper, S^T lower triangular: only their nonzero 16-row blocks
 #pragma unroll
-                    for (int t = 0; t < KS; ++t) ap = MF<T>::mma(wa[p][t], M3[(4 * t + lg) * MST + colj], ap);
+                    for (int t = 0; t < 4 * (jb + 1); ++t) ap = MF<T>::mma(wa[p][t], M3[(4 * t + lg) * MST + colj], ap);
 #pragma unroll
-                    for (int t = 0; t < KS; ++t) ap = MF<T>::mma(pa[p][t], M4[(4 * t + lg) * MST + colj], ap);
+                    for (int t = 4 * jb; t < KS; ++t) ap = MF<T>::mma(pa[p][t], M4[(4 * t + lg) * MST + colj], ap);
                     if (colj < s) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) P[colj * ldw + r0 + mfma_row<kF64>(lg, r)] = ap[r];
