@@ -1424,13 +1424,26 @@ __global__ __launch_bounds__(kThreads) void update_dqp_kernel(const ChipDev *__r
 }
 
 // The same update in FP32 for s > 32, where the N x s blocks no longer fit
-// the Infinity Cache and come from HBM: a wave takes its 64 rows at once as
-// four interleaved 16-row matrix-core blocks (block q holds rows 4 i + q,
-// i = 0..15), so that one 16-byte load gives a lane its operand in all four
-// blocks and 16 lanes read 256 contiguous bytes of a column; result register
-// r of the four blocks then holds 4 consecutive rows (rows 16 g + 4 r ..
-// + 3 of lane group g), written with one 16-byte store.
-template <int NB>
+// the Infinity Cache and come from HBM.  A wave takes 64 rows as four
+// interleaved 16-row blocks (block q holds rows 4 i + q, i = 0..15), so that
+// one 16-byte load gives a lane its operand in all four blocks and 16 lanes
+// read 256 contiguous bytes of a column.  The products are formed
+// transposed, (P M)^T = M^T P^T: the small matrix is the matrix-core A
+// operand and the rows of P the B operand, so that result register r of
+// lane (i, g) is column 16 jb + 4 g + r at row 4 i + q; the four blocks then
+// give a lane 4 consecutive rows of one column, and 16 lanes write (and
+// read, for D) 256 contiguous bytes of it with one 16-byte access each.  In
+// the untransposed form each such access touched 16 columns in 16-byte
+// pieces, and the kernel ran 30 % slower.
+//
+// The wave keeps all 2 s new columns of its rows in accumulators and streams
+// the k steps of P and W through a ring of kDepth register slots, each
+// refilled kDepth steps ahead (the last steps of a tile fetch the first ones
+// of the next), so that the loads overlap the matrix-core work instead of
+// preceding it.  D is not the accumulators' start value: column block jb of
+// D is loaded at step 3 jb and added in at step 3 jb + 3, which keeps its
+// load latency off the chain too.
+template <int NB, int kDepth = 4>
 __global__ __launch_bounds__(kThreads) void update_dqp_rows4_kernel(const ChipDev *__restrict__ cds,
                                                                     const uint16_t *__restrict__ tab, int s)
 {
@@ -1441,6 +1454,7 @@ __global__ __launch_bounds__(kThreads) void update_dqp_rows4_kernel(const ChipDe
     constexpr int KS = 4 * NB;
     constexpr int SP = 16 * NB;
     constexpr int MST = SP + 1;
+    static_assert(KS % kDepth == 0 && 3 * NB < KS, "a tile holds whole ring turns and the D schedule");
     extern __shared__ __align__(16) double dlds[];
     float *M1 = reinterpret_cast<float *>(dlds);
     float *M3 = M1 + SP * MST;
@@ -1462,59 +1476,91 @@ __global__ __launch_bounds__(kThreads) void update_dqp_rows4_kernel(const ChipDe
     const int li = lane & 15, lg = lane >> 4;
     const int64_t ntiles = ldw / kTileRows;
     const f4 zero = {0.f, 0.f, 0.f, 0.f};
+    if (local >= ntiles) return;
+    f4 pr[kDepth], wr[kDepth];
+    auto fetch = [&](int64_t tile, int t, f4 &pv, f4 &wv) {
+        const int col = 4 * t + lg;
+        const int64_t a = col * ldw + tile * kTileRows + wave * 64 + 4 * li;
+        pv = col < s ? ld16(gptr<const float>(P) + a) : zero;
+        wv = col < s ? ld16(W + a) : zero;
+    };
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) fetch(local, d, pr[d], wr[d]);
     for (int64_t tile = local; tile < ntiles; tile += wgs) {
         const int64_t r0 = tile * kTileRows + wave * 64;
-        f4 pa[KS], wa[KS];
+        const int64_t nxt = tile + wgs;
+        f4 ad[NB][4], ap[NB][4], dv[4];
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ad[jb][q] = ap[jb][q] = zero;
+        // the small-matrix entries of step t + 1 are read during step t; the
+        // empty asm re-defines their LDS index every step, which keeps the
+        // compiler from hoisting all of them (they do not change from tile
+        // to tile) into registers for the whole loop
+        int mb = lg * MST + li;
+        float m1[2][NB], m3[2][NB], m4[2][NB];
+        auto read_m = [&](int t, int slot) {
+            const int tb = t / 4;
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+                const int o = mb + 4 * t * MST + jb * 16;
+                m1[slot][jb] = M1[o];
+                m3[slot][jb] = jb >= tb ? M3[o] : 0.f;
+                m4[slot][jb] = jb <= tb ? M4[o] : 0.f;
+            }
+        };
+        asm volatile("" : "+v"(mb));
+        read_m(0, 0);
 #pragma unroll
         for (int t = 0; t < KS; ++t) {
-            const int col = 4 * t + lg;
-            pa[t] = col < s ? ld16(gptr<const float>(P) + col * ldw + r0 + 4 * li) : zero;
-            wa[t] = col < s ? ld16(W + col * ldw + r0 + 4 * li) : zero;
-        }
-        // every lane has read its rows of P: the new rows are written column
-        // block by column block
-#pragma unroll 1
-        for (int jb = 0; jb < NB; ++jb) {
-            const int colj = jb * 16 + li;
-            f4 ad[4], ap[4];
+            const int tb = t / 4;
+            const int cs = t & 1;
+            asm volatile("" : "+v"(mb));
+            if (t + 1 < KS) read_m(t + 1, cs ^ 1);
+            const f4 pa = pr[t % kDepth], wa = wr[t % kDepth];
+            // M3 = S^+ is upper and M4 = S^T lower triangular: column block
+            // jb takes M3's k steps only for tb <= jb and M4's only for tb >= jb
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const f4 d = colj < s ? ld16(gptr<const float>(D) + colj * ldw + r0 + 16 * lg + 4 * r) : zero;
+            for (int jb = 0; jb < NB; ++jb) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    ad[q][r] = d[q];
-                    ap[q][r] = 0.f;
+                for (int q = 0; q < 4; ++q) ad[jb][q] = MF<float>::mma(m1[cs][jb], pa[q], ad[jb][q]);
+                if (jb >= tb) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) ap[jb][q] = MF<float>::mma(m3[cs][jb], wa[q], ap[jb][q]);
+                }
+                if (jb <= tb) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) ap[jb][q] = MF<float>::mma(m4[cs][jb], pa[q], ap[jb][q]);
                 }
             }
-            // M3 = S^+ is upper and M4 = S^T lower triangular: k steps in
-            // 16-row blocks below (M3) or above (M4) the column block are
-            // zero and skipped
+            if (t % 3 == 0 && t / 3 >= 1 && t / 3 <= NB) {
+                const int jb = t / 3 - 1;
 #pragma unroll
-            for (int t = 0; t < KS; ++t) {
-                const int k = 4 * t + lg;
-                const float m1 = M1[k * MST + colj];
+                for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) ad[q] = MF<float>::mma(pa[t][q], m1, ad[q]);
-                if (t < 4 * (jb + 1)) {
-                    const float m3 = M3[k * MST + colj];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) ap[q] = MF<float>::mma(wa[t][q], m3, ap[q]);
-                }
+                    for (int r = 0; r < 4; ++r) ad[jb][q][r] += dv[r][q];
             }
-#pragma unroll
-            for (int t = 0; t < KS; ++t) {
-                if (t >= 4 * jb) {
-                    const float m4 = M4[(4 * t + lg) * MST + colj];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) ap[q] = MF<float>::mma(pa[t][q], m4, ap[q]);
-                }
-            }
-            if (colj < s) {
+            if (t % 3 == 0 && t / 3 < NB) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int64_t idx = colj * ldw + r0 + 16 * lg + 4 * r;
-                    const f4 dn = {ad[0][r], ad[1][r], ad[2][r], ad[3][r]};
-                    const f4 pn = {ap[0][r], ap[1][r], ap[2][r], ap[3][r]};
+                    const int c = (t / 3) * 16 + 4 * lg + r;
+                    dv[r] = c < s ? ld16(gptr<const float>(D) + c * ldw + r0 + 4 * li) : zero;
+                }
+            }
+            const int tn = t + kDepth;
+            if (tn < KS) fetch(tile, tn, pr[t % kDepth], wr[t % kDepth]);
+            else if (nxt < ntiles) fetch(nxt, tn - KS, pr[t % kDepth], wr[t % kDepth]);
+        }
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = jb * 16 + 4 * lg + r;
+                if (c < s) {
+                    const int64_t idx = c * ldw + r0 + 4 * li;
+                    const f4 dn = {ad[jb][0][r], ad[jb][1][r], ad[jb][2][r], ad[jb][3][r]};
+                    const f4 pn = {ap[jb][0][r], ap[jb][1][r], ap[jb][2][r], ap[jb][3][r]};
                     *reinterpret_cast<gptr<f4>>(D + idx) = dn;
                     *reinterpret_cast<gptr<f4>>(P + idx) = pn;
                 }
