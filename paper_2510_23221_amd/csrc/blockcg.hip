@@ -709,7 +709,10 @@ __device__ __forceinline__ double recip(double p)
 // g precedes the first write).  gmax_ext >= 0 replaces the block's own largest
 // diagonal in the deactivation threshold; ldA > 0 and roff place the output
 // rows (stride ldA) and the right half (from column roff) in a larger array.
-template <int SP>
+// kSym: g is exactly symmetric already, so its transposed reads (bank
+// conflicts at a row stride of 64 doubles) are skipped; the result is the
+// same bit for bit, since (x + x) / 2 = x.
+template <int SP, bool kSym = false>
 __device__ __forceinline__ void wave_eliminate(const double *g, int ld, int s, double rel_thr, double *A, int *active,
                                                double gmax_ext = -1.0, int ldA = 0, int roff = 0)
 {
@@ -724,7 +727,7 @@ __device__ __forceinline__ void wave_eliminate(const double *g, int ld, int s, d
     for (int i = 0; i < SP; ++i) {
         const int ic = i < s ? i : 0;
         x[i] = g[ic * ld + lc];
-        y[i] = g[lc * ld + ic];
+        if constexpr (!kSym) y[i] = g[lc * ld + ic];
     }
     double gmax = g[lc * ld + lc];
     gmax = lane < s ? gmax : 0.0;
@@ -735,7 +738,7 @@ __device__ __forceinline__ void wave_eliminate(const double *g, int ld, int s, d
     double a[SP];
 #pragma unroll
     for (int i = 0; i < SP; ++i) {
-        const double gi = 0.5 * (x[i] + y[i]);
+        const double gi = kSym ? x[i] : 0.5 * (x[i] + y[i]);
         const double left = (i < s && lane < s) ? gi : (i == lane ? gmax : 0.0);
         const double right = (i == lane - SP) ? 1.0 : 0.0;
         a[i] = lane < SP ? left : right;
@@ -783,6 +786,76 @@ __device__ __forceinline__ void small_gemm(int s, FA fa, FB fb, FO out)
             if (io < s && j < s) out(io, j, acc[r]);
         }
     }
+}
+
+// small_gemm for the one-workgroup factorisation, for products of at most
+// 4 KT rows and columns: the wave index is made scalar, so block indices and
+// k ranges are uniform; each wave gathers the operands of all KT k steps of
+// two output blocks (reads at clamped indices, out-of-range and skipped terms
+// selected to zero afterwards, so that the reads issue back to back with no
+// branch between them) before the first matrix-core step, then runs the two
+// accumulation chains interleaved and unconditionally (a conditional step
+// would make the compiler copy the accumulator around it).  fa and fb must
+// read valid memory for every index below s.  kfirst(bi, bj) is the first k
+// step (of 4) that can be nonzero for output block (bi, bj), for triangular
+// operands; the terms before it are zero either way.
+template <int KT, class FA, class FB, class FO, class FK>
+__device__ __forceinline__ void small_gemm_wide(int s, FA fa, FB fb, FO out, FK kfirst)
+{
+    constexpr int NW = kFacThreads / 64;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int li = lane & 15, lg = lane >> 4;
+    const int nb = (s + 15) / 16, nbb = nb * nb;
+    for (int blk = wave; blk < nbb; blk += 2 * NW) {
+        const bool two = blk + NW < nbb;
+        int bi[2], bj[2];
+        double av[2][KT], bv[2][KT];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int b = h == 0 || two ? blk + h * NW : blk;
+            bi[h] = b / nb;
+            bj[h] = b % nb;
+            const int k0 = kfirst(bi[h], bj[h]);
+            const int i = bi[h] * 16 + li, j = bj[h] * 16 + li;
+            const int ic = i < s ? i : s - 1, jc = j < s ? j : s - 1;
+#pragma unroll
+            for (int t = 0; t < KT; ++t) {
+                const int k = 4 * t + lg;
+                const int kc = k < s ? k : s - 1;
+                const double va = fa(ic, kc), vb = fb(kc, jc);
+                const bool kin = k < s && t >= k0;
+                av[h][t] = (i < s && kin) ? va : 0.0;
+                bv[h][t] = (j < s && kin) ? vb : 0.0;
+            }
+        }
+        d4 acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+        if (two) {
+#pragma unroll
+            for (int t = 0; t < KT; ++t) {
+                acc[0] = mma64(av[0][t], bv[0][t], acc[0]);
+                acc[1] = mma64(av[1][t], bv[1][t], acc[1]);
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < KT; ++t) acc[0] = mma64(av[0][t], bv[0][t], acc[0]);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h == 1 && !two) continue;
+            const int j = bj[h] * 16 + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int io = bi[h] * 16 + mfma_row<true>(lg, r);
+                if (io < s && j < s) out(io, j, acc[h][r]);
+            }
+        }
+    }
+}
+template <int KT, class FA, class FB, class FO>
+__device__ __forceinline__ void small_gemm_wide(int s, FA fa, FB fb, FO out)
+{
+    small_gemm_wide<KT>(s, fa, fb, out, [](int, int) { return 0; });
 }
 
 // LDS of a workgroup that factors its chip's s x s Gram itself (s <= 32).
@@ -851,7 +924,7 @@ __device__ __forceinline__ void factor_small(int s, double rel_thr, int mode, Fa
 // complement); every pivot is tested against the same threshold on the
 // largest diagonal of G.  The s x s products afterwards run on the FP64
 // matrix cores too.
-__global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__restrict__ cds, int s, double rel_thr,
+__global__ __launch_bounds__(kFacThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void factor_kernel(const ChipDev *__restrict__ cds, int s, double rel_thr,
                                                              int mode)
 {
     const ChipDev &cd = cds[blockIdx.x];  // one workgroup per chip
@@ -870,78 +943,102 @@ __global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__re
     __shared__ double gmax;
     __shared__ int notconv;
     const int tid = threadIdx.x;
+    const int s1 = s < 32 ? s : 32, s2 = s - s1;
     {
-        // all loads of C and of the Gram in flight before the LDS stores
+        // all loads of C and of the Gram (and its transpose, which makes the
+        // symmetrised entry 0.5 (G[i][j] + G[j][i]) in registers) in flight
+        // before the LDS stores
         constexpr int IT = kMaxS * kMaxS / kFacThreads;
-        double cv[IT], gv[IT];
+        double cv[IT], gv[IT], gt[IT];
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
             const int e = tid + i * kFacThreads;
             cv[i] = e < ss ? sm.C[e] : 0.0;
             gv[i] = e < ss ? gram[e] : 0.0;
+            gt[i] = e < ss ? gram[(e % s) * s + e / s] : 0.0;
         }
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
             const int e = tid + i * kFacThreads;
             if (e < ss) {
                 Cl[e] = cv[i];
-                G[e] = gv[i];
+                G[e] = 0.5 * (gv[i] + gt[i]);
             }
         }
     }
-    for (int e = tid; e < s * w; e += kFacThreads) A[e] = 0.0;  // structural zeros of U21 and E12
+    // structural zeros of U21 and E12 (every other entry of [U | E] is written
+    // by the eliminations and products below)
+    for (int e = tid; e < s2 * s1; e += kFacThreads) {
+        const int i = e / s1, j = e % s1;
+        A[(s1 + i) * w + j] = 0.0;
+        A[j * w + s + s1 + i] = 0.0;
+    }
     if (tid == 0) notconv = 0;
     __syncthreads();
-    // symmetrise in place (each pair by one thread) and take the largest diagonal
-    for (int e = tid; e < ss; e += kFacThreads) {
-        const int i = e / s, j = e % s;
-        if (i < j) {
-            const double v = 0.5 * (G[i * s + j] + G[j * s + i]);
-            G[i * s + j] = v;
-            G[j * s + i] = v;
-        }
-    }
+    // the largest diagonal
     if (tid < 64) {
         double v = tid < s ? G[tid * s + tid] : 0.0;
         for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
         if (tid == 0) gmax = v;
     }
     __syncthreads();
-    const int s1 = s < 32 ? s : 32, s2 = s - s1;
     const double gm = gmax;
-    if (tid < 64) wave_eliminate<32>(G, s, s1, rel_thr, A, active, gm, w, s);
+    if (tid < 64) wave_eliminate<32, true>(G, s, s1, rel_thr, A, active, gm, w, s);
     __syncthreads();
     if (s2 > 0) {
         for (int k = tid; k < s1; k += kFacThreads) dp1[k] = active[k] ? 1.0 / A[k * w + k] : 0.0;
         // U12 = E11 G12 (E11[i][k] = A[i][s + k])
-        small_gemm(
+        small_gemm_wide<8>(
             32, [&](int i, int k) { return A[i * w + s + k]; },
-            [&](int k, int j) { return j < s2 ? G[k * s + s1 + j] : 0.0; },
+            [&](int k, int j) {
+                const double v = G[k * s + s1 + j];
+                return j < s2 ? v : 0.0;
+            },
             [&](int i, int j, double v) {
                 if (j < s2) A[i * w + s1 + j] = v;
             });
         __syncthreads();
         // Schur complement G22 -= U12^T D1^+ U12, in place
-        small_gemm(
-            32, [&](int i, int k) { return i < s2 ? A[k * w + s1 + i] * dp1[k] : 0.0; },
-            [&](int k, int j) { return j < s2 ? A[k * w + s1 + j] : 0.0; },
+        small_gemm_wide<8>(
+            32,
+            [&](int i, int k) {
+                const double v = A[k * w + s1 + i] * dp1[k];
+                return i < s2 ? v : 0.0;
+            },
+            [&](int k, int j) {
+                const double v = A[k * w + s1 + j];
+                return j < s2 ? v : 0.0;
+            },
             [&](int i, int j, double v) {
                 if (i < s2 && j < s2) G[(s1 + i) * s + s1 + j] -= v;
             });
         __syncthreads();
         if (tid < 64) wave_eliminate<32>(G + s1 * s + s1, s, s2, rel_thr, A + s1 * w + s1, active + s1, gm, w, s);
         // T1 = U12^T D1^+ E11 (s2 x s1) into the G11 block, no longer read
-        small_gemm(
-            32, [&](int i, int k) { return i < s2 ? A[k * w + s1 + i] * dp1[k] : 0.0; },
+        // (E11 is lower triangular: k >= j)
+        small_gemm_wide<8>(
+            32,
+            [&](int i, int k) {
+                const double v = A[k * w + s1 + i] * dp1[k];
+                return i < s2 ? v : 0.0;
+            },
             [&](int k, int j) { return A[k * w + s + j]; },
             [&](int i, int j, double v) {
                 if (i < s2) G[i * s + j] = v;
-            });
+            },
+            [](int, int bj) { return 4 * bj; });
         __syncthreads();
         // E21 = -E22 T1 (E22[i][k] = A[s1 + i][s + s1 + k])
-        small_gemm(
-            32, [&](int i, int k) { return (i < s2 && k < s2) ? A[(s1 + i) * w + s + s1 + k] : 0.0; },
-            [&](int k, int j) { return k < s2 ? G[k * s + j] : 0.0; },
+        small_gemm_wide<8>(
+            32,
+            [&](int i, int k) {
+                const double v = A[(s1 + i) * w + s + s1 + k];
+                return (i < s2 && k < s2) ? v : 0.0;
+            },
+            [&](int k, int j) {
+                const double v = G[k * s + j];
+                return k < s2 ? v : 0.0;
+            },
             [&](int i, int j, double v) {
                 if (i < s2) A[(s1 + i) * w + s + j] = -v;
             });
@@ -953,16 +1050,18 @@ __global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__re
     int inactive = 0;
     for (int k = 0; k < s; ++k) inactive += active[k] ? 0 : 1;
     if (mode == 0) {
-        // delta^+ = E^T diag(dv) E (E = right half); M2 = delta^+, M1 = delta^+ C
-        small_gemm(
+        // delta^+ = E^T diag(dv) E (E = right half, lower triangular: only
+        // k >= max(i, j) contributes); M2 = delta^+, M1 = delta^+ C
+        small_gemm_wide<kMaxS / 4>(
             s, [&](int i, int k) { return A[k * w + s + i]; }, [&](int k, int j) { return dv[k] * A[k * w + s + j]; },
             [&](int i, int j, double v) {
                 G[i * s + j] = v;
                 sm.M2[i * s + j] = v;
                 sm.M2f[i * s + j] = static_cast<float>(v);
-            });
+            },
+            [](int bi, int bj) { return 4 * (bi > bj ? bi : bj); });
         __syncthreads();
-        small_gemm(
+        small_gemm_wide<kMaxS / 4>(
             s, [&](int i, int k) { return G[i * s + k]; }, [&](int k, int j) { return Cl[k * s + j]; },
             [&](int i, int j, double v) {
                 sm.M1[i * s + j] = v;
@@ -971,9 +1070,14 @@ __global__ __launch_bounds__(kFacThreads) void factor_kernel(const ChipDev *__re
         return;
     }
     // Cn = S C into G, S[i][k] = U[i][k] dv[i] (k >= i)
-    small_gemm(
-        s, [&](int i, int k) { return k >= i ? A[i * w + k] * dv[i] : 0.0; },
-        [&](int k, int j) { return Cl[k * s + j]; }, [&](int i, int j, double v) { G[i * s + j] = v; });
+    small_gemm_wide<kMaxS / 4>(
+        s,
+        [&](int i, int k) {
+            const double v = A[i * w + k] * dv[i];
+            return k >= i ? v : 0.0;
+        },
+        [&](int k, int j) { return Cl[k * s + j]; }, [&](int i, int j, double v) { G[i * s + j] = v; },
+        [](int bi, int) { return 4 * bi; });
     // M3[k][j] = Linv[j][k] = E[j][k] dv[j] (k <= j);  M4[k][j] = S[j][k] = U[j][k] dv[j] (k >= j)
     for (int e = tid; e < ss; e += kFacThreads) {
         const int k = e / s, j = e % s;
