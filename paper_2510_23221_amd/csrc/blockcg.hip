@@ -761,46 +761,21 @@ __device__ __forceinline__ void wave_eliminate(const double *g, int ld, int s, d
     }
 }
 
-// out(i, j, sum_k fa(i, k) fb(k, j)) for an s x s product (s <= 64) on the
-// FP64 matrix cores: the factorisation kernel's waves take the 16 x 16 output
-// blocks in turn; operands outside s x s read as zero.
-template <class FA, class FB, class FO>
-__device__ __forceinline__ void small_gemm(int s, FA fa, FB fb, FO out)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int li = lane & 15, lg = lane >> 4;
-    const int nb = (s + 15) / 16;
-    for (int blk = wave; blk < nb * nb; blk += kFacThreads / 64) {
-        const int bi = blk / nb, bj = blk % nb;
-        const int i = bi * 16 + li, j = bj * 16 + li;
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < s; k0 += 4) {
-            const int k = k0 + lg;
-            const double a = (i < s && k < s) ? fa(i, k) : 0.0;
-            const double b = (k < s && j < s) ? fb(k, j) : 0.0;
-            acc = mma64(a, b, acc);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int io = bi * 16 + mfma_row<true>(lg, r);
-            if (io < s && j < s) out(io, j, acc[r]);
-        }
-    }
-}
-
-// small_gemm for the one-workgroup factorisation, for products of at most
-// 4 KT rows and columns: the wave index is made scalar, so block indices and
-// k ranges are uniform; each wave gathers the operands of all KT k steps of
-// two output blocks (reads at clamped indices, out-of-range and skipped terms
-// selected to zero afterwards, so that the reads issue back to back with no
-// branch between them) before the first matrix-core step, then runs the two
-// accumulation chains interleaved and unconditionally (a conditional step
-// would make the compiler copy the accumulator around it).  fa and fb must
-// read valid memory for every index below s.  kfirst(bi, bj) is the first k
-// step (of 4) that can be nonzero for output block (bi, bj), for triangular
-// operands; the terms before it are zero either way.
+// out(i, j, sum_k fa(i, k) fb(k, j)) for an s x s product (s <= 4 KT) on the
+// FP64 matrix cores, by a workgroup that factors a Gram (the factorisation
+// kernel, or every workgroup of a fused update).  The wave index is made
+// scalar, so block indices and k ranges are uniform; each wave gathers the
+// operands of all KT k steps of two output blocks (reads at clamped indices,
+// out-of-range and skipped terms selected to zero afterwards, so that the
+// reads issue back to back with no branch between them) before the first
+// matrix-core step, then runs the two accumulation chains interleaved and
+// unconditionally (a conditional step makes the compiler copy the
+// accumulator around it).  fa and fb must read valid memory for every index
+// below s.  kfirst(bi, bj) is the first k step (of 4) that can be nonzero
+// for output block (bi, bj), for triangular operands; the terms before it
+// are zero either way.
 template <int KT, class FA, class FB, class FO, class FK>
-__device__ __forceinline__ void small_gemm_wide(int s, FA fa, FB fb, FO out, FK kfirst)
+__device__ __forceinline__ void small_gemm(int s, FA fa, FB fb, FO out, FK kfirst)
 {
     constexpr int NW = kFacThreads / 64;
     const int lane = threadIdx.x & 63;
@@ -853,9 +828,9 @@ __device__ __forceinline__ void small_gemm_wide(int s, FA fa, FB fb, FO out, FK 
     }
 }
 template <int KT, class FA, class FB, class FO>
-__device__ __forceinline__ void small_gemm_wide(int s, FA fa, FB fb, FO out)
+__device__ __forceinline__ void small_gemm(int s, FA fa, FB fb, FO out)
 {
-    small_gemm_wide<KT>(s, fa, fb, out, [](int, int) { return 0; });
+    small_gemm<KT>(s, fa, fb, out, [](int, int) { return 0; });
 }
 
 // LDS of a workgroup that factors its chip's s x s Gram itself (s <= 32).
@@ -988,7 +963,7 @@ __global__ __launch_bounds__(kFacThreads) __attribute__((amdgpu_waves_per_eu(1, 
     if (s2 > 0) {
         for (int k = tid; k < s1; k += kFacThreads) dp1[k] = active[k] ? 1.0 / A[k * w + k] : 0.0;
         // U12 = E11 G12 (E11[i][k] = A[i][s + k])
-        small_gemm_wide<8>(
+        small_gemm<8>(
             32, [&](int i, int k) { return A[i * w + s + k]; },
             [&](int k, int j) {
                 const double v = G[k * s + s1 + j];
@@ -999,7 +974,7 @@ __global__ __launch_bounds__(kFacThreads) __attribute__((amdgpu_waves_per_eu(1, 
             });
         __syncthreads();
         // Schur complement G22 -= U12^T D1^+ U12, in place
-        small_gemm_wide<8>(
+        small_gemm<8>(
             32,
             [&](int i, int k) {
                 const double v = A[k * w + s1 + i] * dp1[k];
@@ -1016,7 +991,7 @@ __global__ __launch_bounds__(kFacThreads) __attribute__((amdgpu_waves_per_eu(1, 
         if (tid < 64) wave_eliminate<32>(G + s1 * s + s1, s, s2, rel_thr, A + s1 * w + s1, active + s1, gm, w, s);
         // T1 = U12^T D1^+ E11 (s2 x s1) into the G11 block, no longer read
         // (E11 is lower triangular: k >= j)
-        small_gemm_wide<8>(
+        small_gemm<8>(
             32,
             [&](int i, int k) {
                 const double v = A[k * w + s1 + i] * dp1[k];
@@ -1029,7 +1004,7 @@ __global__ __launch_bounds__(kFacThreads) __attribute__((amdgpu_waves_per_eu(1, 
             [](int, int bj) { return 4 * bj; });
         __syncthreads();
         // E21 = -E22 T1 (E22[i][k] = A[s1 + i][s + s1 + k])
-        small_gemm_wide<8>(
+        small_gemm<8>(
             32,
             [&](int i, int k) {
                 const double v = A[(s1 + i) * w + s + s1 + k];
@@ -1052,7 +1027,7 @@ __global__ __launch_bounds__(kFacThreads) __attribute__((amdgpu_waves_per_eu(1, 
     if (mode == 0) {
         // delta^+ = E^T diag(dv) E (E = right half, lower triangular: only
         // k >= max(i, j) contributes); M2 = delta^+, M1 = delta^+ C
-        small_gemm_wide<kMaxS / 4>(
+        small_gemm<kMaxS / 4>(
             s, [&](int i, int k) { return A[k * w + s + i]; }, [&](int k, int j) { return dv[k] * A[k * w + s + j]; },
             [&](int i, int j, double v) {
                 G[i * s + j] = v;
@@ -1061,7 +1036,7 @@ __global__ __launch_bounds__(kFacThreads) __attribute__((amdgpu_waves_per_eu(1, 
             },
             [](int bi, int bj) { return 4 * (bi > bj ? bi : bj); });
         __syncthreads();
-        small_gemm_wide<kMaxS / 4>(
+        small_gemm<kMaxS / 4>(
             s, [&](int i, int k) { return G[i * s + k]; }, [&](int k, int j) { return Cl[k * s + j]; },
             [&](int i, int j, double v) {
                 sm.M1[i * s + j] = v;
@@ -1070,7 +1045,7 @@ __global__ __launch_bounds__(kFacThreads) __attribute__((amdgpu_waves_per_eu(1, 
         return;
     }
     // Cn = S C into G, S[i][k] = U[i][k] dv[i] (k >= i)
-    small_gemm_wide<kMaxS / 4>(
+    small_gemm<kMaxS / 4>(
         s,
         [&](int i, int k) {
             const double v = A[i * w + k] * dv[i];
@@ -1769,13 +1744,15 @@ __global__ __launch_bounds__(kThreads) void update_w_fused_kernel(const ChipDev 
         }
     });
     const int w = 2 * s;
-    // delta^+ = E^T diag(dv) E (E = right half of the eliminated [G | I])
-    small_gemm(
+    // delta^+ = E^T diag(dv) E (E = right half of the eliminated [G | I],
+    // lower triangular: only k >= max(i, j) contributes)
+    small_gemm<4 * NB>(
         s, [&](int i, int k) { return fs.A[k * w + s + i]; }, [&](int k, int j) { return fs.dv[k] * fs.A[k * w + s + j]; },
         [&](int i, int j, double v) {
             M2s[i * MST + j] = static_cast<T>(-v);
             fs.G[i * s + j] = v;
-        });
+        },
+        [](int bi, int bj) { return 4 * (bi > bj ? bi : bj); });
     __syncthreads();
     if (local == 0) {
         // M1 = delta^+ C for this step's update of D
@@ -1783,7 +1760,7 @@ __global__ __launch_bounds__(kThreads) void update_w_fused_kernel(const ChipDev 
         for (int q = 0; q < kGramRegs; ++q)
             if (threadIdx.x + q * kThreads < s * s) fs.Cl[threadIdx.x + q * kThreads] = cv[q];
         __syncthreads();
-        small_gemm(
+        small_gemm<4 * NB>(
             s, [&](int i, int k) { return fs.G[i * s + k]; }, [&](int k, int j) { return fs.Cl[k * s + j]; },
             [&](int i, int j, double v) {
                 sm.M1[i * s + j] = v;
@@ -1956,29 +1933,42 @@ __global__ __launch_bounds__(kThreads) void update_dqp_fused_kernel(const ChipDe
             if (threadIdx.x + q * kThreads < s * s) fs.Cl[threadIdx.x + q * kThreads] = cv[q];
         if (threadIdx.x == 0) fs.notconv = 0;
         __syncthreads();
-        small_gemm(
-            s, [&](int i, int k) { return k >= i ? fs.A[i * w + k] * fs.dv[i] : 0.0; },
-            [&](int k, int j) { return fs.Cl[k * s + j]; }, [&](int i, int j, double v) { fs.G[i * s + j] = v; });
+        small_gemm<4 * NB>(
+            s,
+            [&](int i, int k) {
+                const double v = fs.A[i * w + k] * fs.dv[i];
+                return k >= i ? v : 0.0;
+            },
+            [&](int k, int j) { return fs.Cl[k * s + j]; }, [&](int i, int j, double v) { fs.G[i * s + j] = v; },
+            [](int bi, int) { return 4 * bi; });
         __syncthreads();
-        for (int j = threadIdx.x; j < s; j += kThreads) {
-            double n0 = 0.0, n1 = 0.0;
-            int r = 0;
-            for (; r + 1 <= j; r += 2) {
-                n0 += fs.G[r * s + j] * fs.G[r * s + j];
-                n1 += fs.G[(r + 1) * s + j] * fs.G[(r + 1) * s + j];
+        // ||C e_j|| (C upper triangular) by 8 lanes per column: rows p, p + 8,
+        // p + 16, p + 24, then a fixed butterfly over the 8 lanes
+        {
+            static_assert(kThreads >= 8 * 32, "8 lanes per column for s <= 32");
+            const int j = threadIdx.x >> 3, p = threadIdx.x & 7;
+            double n = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = p + 8 * q;
+                const double v = (j < s && r <= j) ? fs.G[r * s + j] : 0.0;
+                n = fma(v, v, n);
             }
-            if (r <= j) n0 += fs.G[r * s + j] * fs.G[r * s + j];
-            if (!(sqrt(n0 + n1) <= sm.th[j])) atomicAdd(&fs.notconv, 1);
+            n += __shfl_xor(n, 4);
+            n += __shfl_xor(n, 2);
+            n += __shfl_xor(n, 1);
+            if (j < s && p == 0 && !(sqrt(n) <= sm.th[j])) atomicAdd(&fs.notconv, 1);
         }
         for (int e = threadIdx.x; e < s * s; e += kThreads) sm.C[e] = fs.G[e];
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int inactive = 0;
-            for (int k = 0; k < s; ++k) inactive += fs.active[k] ? 0 : 1;
-            ctrl[kIters] = iters + (mode == 1 ? 1 : 0);
-            ctrl[kDeflated] = inactive;
-            if (inactive == s) ctrl[kAllDeflated] = 1;
-            if (fs.notconv == 0 || inactive == s) ctrl[kConverged] = 1;
+        if (threadIdx.x < 64) {
+            const int inactive = __popcll(__ballot(threadIdx.x < s && !fs.active[threadIdx.x]));
+            if (threadIdx.x == 0) {
+                ctrl[kIters] = iters + (mode == 1 ? 1 : 0);
+                ctrl[kDeflated] = inactive;
+                if (inactive == s) ctrl[kAllDeflated] = 1;
+                if (fs.notconv == 0 || inactive == s) ctrl[kConverged] = 1;
+            }
         }
     }
     __syncthreads();
