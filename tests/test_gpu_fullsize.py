@@ -267,6 +267,27 @@ def test_config4_bf16_stages_sampled(dev):
     del T, F
 
 
+# ------------------------------------------------------------------ s > 32 row kernels over several tiles per workgroup
+
+@pytest.mark.parametrize("s,nz", [(48, 8), (40, 12)])
+def test_wide_solve_several_tiles_per_workgroup(dev, s, nz):
+    """FP32 block solves whose chips have more 256-row tiles than the chip's
+    workgroup cap (1820 at s = 48, 2621 at s = 40), so that workgroups walk
+    more than one tile and the D/Q/P update's register ring prefetches across
+    tiles; s = 40 also leaves the last column block ragged.  Residuals by the
+    oracle's SpMV."""
+    rng = np.random.default_rng(300 + s)
+    chip = synth.chip_stack(rng, 256, 256, nz)
+    A = oracle.assemble_chip(chip)
+    assert A.n // 256 > (1 << 22) // (s * s)
+    G = capi.HeatOperator.from_chip(chip, dev, precond=capi.PRECOND_JACOBI)
+    B = synth.power_blocky(rng, chip, s)
+    X, info = capi.block_krylov_solve(G, torch.as_tensor(B, device=dev), 1e-8, compute=capi.F32)
+    assert info["status"] == capi.OK
+    rel, floor, _ = _rel_res(A, B, to_np(X))
+    assert (rel <= 1e-8 * 1.0001 + floor).all(), (rel.max(), info)
+
+
 # ------------------------------------------------------------------ batch extremes
 
 def test_batch_extreme_chips(dev):
