@@ -350,6 +350,26 @@ def test_block_solve_degenerate_columns_blocked(ops, dev, compute):
     assert np.abs(X[17]).max() == 0.0
 
 
+@pytest.mark.parametrize("compute", [capi.F64, capi.F32])
+def test_block_solve_degenerate_columns_wide(ops, dev, compute):
+    """s = 48 (the separate factorisation: a 32-pivot and a 16-pivot half,
+    the Schur complement and the products on the matrix cores): duplicates,
+    a combination and zero columns in both halves are deflated; the solve
+    converges and the zero columns stay zero."""
+    chip, A, G = ops["2d"]
+    rng = np.random.default_rng(6)
+    B = rng.standard_normal((48, A.n))
+    B[40] = B[3]
+    B[45] = 2.0 * B[0] - B[33]
+    B[9] = B[1]
+    B[20] = 0.0
+    B[37] = 0.0
+    tol = 1e-10 if compute == capi.F64 else 1e-8
+    X, info, _ = _solve_check(A, G, B, tol, compute, dev, xerr=1e-6)
+    assert info["deflated"] >= 1
+    assert np.abs(X[20]).max() == 0.0 and np.abs(X[37]).max() == 0.0
+
+
 def test_block_solve_initial_guess(ops, dev):
     chip, A, G = ops["2d"]
     rng = np.random.default_rng(5)
