@@ -1298,11 +1298,39 @@ __global__ __launch_bounds__(kThreads) void update_w_rows2_kernel(const ChipDev 
 #pragma unroll
     for (int q = 0; q <= FB; ++q) g[q] = d4{0.0, 0.0, 0.0, 0.0};
     const int64_t ntiles = ldw / kTileRows;
-    for (int64_t tile = local; tile < ntiles; tile += wgs) {
-        for (int h = 0; h < 2; ++h) {
-            const int64_t r0 = tile * kTileRows + wave * 64 + 32 * h;
-            f4 wv[NB][2];
-            if (init) {
+    // stage one unit's new rows (columns s .. SP are zero: their operands
+    // were), then W^T W over the staged rows (row k0 + lg is the k slot of
+    // lane group lg)
+    auto stage_gram = [&](const f4 (&wv)[NB][2]) {
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    Wst[(wave * 32 + 8 * lg + 2 * r + q) * WST + jb * 16 + li] = wv[jb][q][r];
+        __syncthreads();
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+            const float *pa = Wst + lg * WST + ga[f] * 16 + li, *pb = Wst + lg * WST + gb[f] * 16 + li;
+#pragma unroll 8
+            for (int k0 = 0; k0 < SR; k0 += 4)
+                g[f] = mma64(static_cast<double>(pa[k0 * WST]), static_cast<double>(pb[k0 * WST]), g[f]);
+        }
+        {
+            const float *pa = Wst + (hk0 + lg) * WST + ga[FB] * 16 + li;
+            const float *pb = Wst + (hk0 + lg) * WST + gb[FB] * 16 + li;
+#pragma unroll 8
+            for (int k0 = 0; k0 < SR / 2; k0 += 4)
+                g[FB] = mma64(static_cast<double>(pa[k0 * WST]), static_cast<double>(pb[k0 * WST]), g[FB]);
+        }
+        __syncthreads();  // the next unit overwrites the stage
+    };
+    if (init) {
+        for (int64_t tile = local; tile < ntiles; tile += wgs)
+            for (int h = 0; h < 2; ++h) {
+                const int64_t r0 = tile * kTileRows + wave * 64 + 32 * h;
+                f4 wv[NB][2];
 #pragma unroll
                 for (int jb = 0; jb < NB; ++jb) {
                     const int colj = jb * 16 + li;
@@ -1313,43 +1341,72 @@ __global__ __launch_bounds__(kThreads) void update_w_rows2_kernel(const ChipDev 
                         wv[jb][1][r] = v[1];
                     }
                 }
-            } else {
-                // W M3, then AP (-M2) with the AP rows in the same registers
-                // (one operand block live at a time)
-                f2 xa[KS];
+                stage_gram(wv);
+            }
+    } else if (local < ntiles) {
+        // W M3 + AP (-M2) in one pass over the k steps: the W and AP rows
+        // of each step stream through a ring of kDepth register slots,
+        // refilled kDepth steps ahead; the last steps of a 32-row unit fetch
+        // the first ones of the next, so those loads fly during this unit's
+        // stores, stage and Gram products
+        constexpr int kDepth = 4;
+        static_assert(KS % kDepth == 0, "a unit holds whole ring turns");
+        f2 rw[kDepth], rp[kDepth];
+        auto fetch = [&](int64_t r0, int t, f2 &xw, f2 &xp) {
+            const int col = 4 * t + lg;
+            const int64_t a = col * ldw + r0 + 2 * li;
+            xw = col < s ? ld8(gptr<const float>(W) + a) : zero;
+            xp = col < s ? ld8(AP + a) : zero;
+        };
+        const int64_t u_first = local * kTileRows + wave * 64;
 #pragma unroll
-                for (int t = 0; t < KS; ++t) {
-                    const int col = 4 * t + lg;
-                    xa[t] = col < s ? ld8(gptr<const float>(W) + col * ldw + r0 + 2 * li) : zero;
-                }
+        for (int d = 0; d < kDepth; ++d) fetch(u_first, d, rw[d], rp[d]);
+        for (int64_t tile = local; tile < ntiles; tile += wgs)
+            for (int h = 0; h < 2; ++h) {
+                const int64_t r0 = tile * kTileRows + wave * 64 + 32 * h;
+                const bool has_next = h == 0 || tile + wgs < ntiles;
+                const int64_t r0n = h == 0 ? r0 + 32 : (tile + wgs) * kTileRows + wave * 64;
+                f4 wv[NB][2];
 #pragma unroll
-                for (int jb = 0; jb < NB; ++jb) {
-                    const int colj = jb * 16 + li;
+                for (int jb = 0; jb < NB; ++jb)
 #pragma unroll
                     for (int q = 0; q < 2; ++q) wv[jb][q] = f4{0.f, 0.f, 0.f, 0.f};
-                    // M3 = S^+ is upper triangular: the k steps of 16-row
-                    // blocks below the column block are zero
+                // the small-matrix entries of step t + 1 are read during
+                // step t; the empty asm keeps the compiler from hoisting all
+                // of them (unit-invariant) into registers for the whole loop
+                int mb = lg * MST + li;
+                float m3[2][NB], m2[2][NB];
+                auto read_m = [&](int t, int slot) {
+                    const int tb = t / 4;
 #pragma unroll
-                    for (int t = 0; t < 4 * (jb + 1); ++t) {
-                        const float m3 = M3s[(4 * t + lg) * MST + colj];
-#pragma unroll
-                        for (int q = 0; q < 2; ++q) wv[jb][q] = MF<float>::mma(xa[t][q], m3, wv[jb][q]);
+                    for (int jb = 0; jb < NB; ++jb) {
+                        const int o = mb + 4 * t * MST + jb * 16;
+                        m3[slot][jb] = jb >= tb ? M3s[o] : 0.f;
+                        m2[slot][jb] = M2s[o];
                     }
-                }
+                };
+                asm volatile("" : "+v"(mb));
+                read_m(0, 0);
 #pragma unroll
                 for (int t = 0; t < KS; ++t) {
-                    const int col = 4 * t + lg;
-                    xa[t] = col < s ? ld8(AP + col * ldw + r0 + 2 * li) : zero;
-                }
+                    const int tb = t / 4, cs = t & 1;
+                    asm volatile("" : "+v"(mb));
+                    if (t + 1 < KS) read_m(t + 1, cs ^ 1);
+                    const f2 xw = rw[t % kDepth], xp = rp[t % kDepth];
+                    // M3 = S^+ is upper triangular: column block jb takes
+                    // its k steps only for tb <= jb
 #pragma unroll
-                for (int jb = 0; jb < NB; ++jb) {
-                    const int colj = jb * 16 + li;
+                    for (int jb = 0; jb < NB; ++jb) {
+                        if (jb >= tb) {
 #pragma unroll
-                    for (int t = 0; t < KS; ++t) {
-                        const float m2 = M2s[(4 * t + lg) * MST + colj];
+                            for (int q = 0; q < 2; ++q) wv[jb][q] = MF<float>::mma(xw[q], m3[cs][jb], wv[jb][q]);
+                        }
 #pragma unroll
-                        for (int q = 0; q < 2; ++q) wv[jb][q] = MF<float>::mma(xa[t][q], m2, wv[jb][q]);
+                        for (int q = 0; q < 2; ++q) wv[jb][q] = MF<float>::mma(xp[q], m2[cs][jb], wv[jb][q]);
                     }
+                    const int tn = t + kDepth;
+                    if (tn < KS) fetch(r0, tn, rw[t % kDepth], rp[t % kDepth]);
+                    else if (has_next) fetch(r0n, tn - KS, rw[t % kDepth], rp[t % kDepth]);
                 }
                 // every lane has read its rows of W: write the new rows
 #pragma unroll
@@ -1363,33 +1420,8 @@ __global__ __launch_bounds__(kThreads) void update_w_rows2_kernel(const ChipDev 
                         }
                     }
                 }
+                stage_gram(wv);
             }
-            // stage the new rows (columns s .. SP are zero: their operands were)
-#pragma unroll
-            for (int jb = 0; jb < NB; ++jb)
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        Wst[(wave * 32 + 8 * lg + 2 * r + q) * WST + jb * 16 + li] = wv[jb][q][r];
-            __syncthreads();
-            // W^T W over the staged rows: row k0 + lg is the k slot of lane group lg
-#pragma unroll
-            for (int f = 0; f < FB; ++f) {
-                const float *pa = Wst + lg * WST + ga[f] * 16 + li, *pb = Wst + lg * WST + gb[f] * 16 + li;
-#pragma unroll 8
-                for (int k0 = 0; k0 < SR; k0 += 4)
-                    g[f] = mma64(static_cast<double>(pa[k0 * WST]), static_cast<double>(pb[k0 * WST]), g[f]);
-            }
-            {
-                const float *pa = Wst + (hk0 + lg) * WST + ga[FB] * 16 + li;
-                const float *pb = Wst + (hk0 + lg) * WST + gb[FB] * 16 + li;
-#pragma unroll 8
-                for (int k0 = 0; k0 < SR / 2; k0 += 4)
-                    g[FB] = mma64(static_cast<double>(pa[k0 * WST]), static_cast<double>(pb[k0 * WST]), g[FB]);
-            }
-            __syncthreads();  // the next half overwrites the stage
-        }
     }
     // publish: whole blocks by their wave; the shared blocks summed through LDS
     const gptr<double> out = glb(cd.parts) + static_cast<size_t>(local) * s * s;
