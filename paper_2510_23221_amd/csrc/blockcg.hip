@@ -898,9 +898,10 @@ __device__ __forceinline__ void factor_small(int s, double rel_thr, int mode, Fa
 // sequential elimination (inactive pivots contribute nothing to the Schur
 // complement); every pivot is tested against the same threshold on the
 // largest diagonal of G.  The s x s products afterwards run on the FP64
-// matrix cores too.
-__global__ __launch_bounds__(kFacThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void factor_kernel(const ChipDev *__restrict__ cds, int s, double rel_thr,
-                                                             int mode)
+// matrix cores too.  One workgroup per chip runs alone on its compute unit,
+// so the kernel may use the whole register file (one wave per SIMD).
+__global__ __launch_bounds__(kFacThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void factor_kernel(
+    const ChipDev *__restrict__ cds, int s, double rel_thr, int mode)
 {
     const ChipDev &cd = cds[blockIdx.x];  // one workgroup per chip
     const gptr<int> ctrl = glb(cd.ctrl);
