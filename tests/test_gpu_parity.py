@@ -590,11 +590,12 @@ def test_initial_guess_single_column(ops, dev):
 
 
 @pytest.mark.parametrize("s,compute", [(48, capi.F64), (64, capi.F32), (64, capi.F64), (17, capi.F32),
-                                       (48, capi.F32), (40, capi.F32)])
+                                       (48, capi.F32), (40, capi.F32), (33, capi.F32), (33, capi.F64)])
 def test_block_solve_wide_blocks(ops, dev, s, compute):
     """Widths that take the three- and four-block register tiles, the FP32
     interleaved-row updates (s > 32, also with a ragged last column block)
-    and the blocked factorisation, and a width one past a tile edge."""
+    and the blocked factorisation (s = 33: a second pivot block of one), and
+    widths one past a tile edge."""
     chip, A, G = ops["stack"]
     rng = np.random.default_rng(40 + s)
     B = rng.standard_normal((s, A.n))
