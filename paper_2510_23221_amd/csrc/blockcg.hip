@@ -2946,13 +2946,25 @@ size_t solve_workspace_bytes(int64_t n, int s, bko_dtype compute)
     return make_layout(ops, 1, s, compute, 1).bytes;
 }
 
+// Row tiles per workgroup of a single-chip solve: about two workgroups per
+// compute unit, the granularity the batch autotuner picks on the stacks
+// measured (512 tiles: one per workgroup; 4096 tiles at s = 64: eight, a
+// 587 ms solve against 616 ms at one per workgroup).  The workspace is sized
+// for one tile per workgroup, so any granularity fits it.
+int solve_tiles_per_wg(const Operator &op)
+{
+    const int64_t tiles = static_cast<int64_t>(align_up(static_cast<size_t>(op.n), kTileRows)) / kTileRows;
+    const int64_t target = 2 * static_cast<int64_t>(device_cu_count());
+    return static_cast<int>(std::max<int64_t>(1, (tiles + target - 1) / target));
+}
+
 bko_status block_solve(const Operator &op, int s, const double *B, int64_t ldb, double *X, int64_t ldx,
                        const double *X0, int64_t ldx0, bko_dtype compute, double tol, int max_iter, void *work,
                        size_t work_bytes, bko_solve_info *info, hipStream_t st)
 {
     (void)work_bytes;
     const Operator *ops[1] = {&op};
-    const Layout L = make_layout(ops, 1, s, compute, 1);
+    const Layout L = make_layout(ops, 1, s, compute, solve_tiles_per_wg(op));
     const double *Bs[1] = {B};
     double *Xs[1] = {X};
     const double *X0s[1] = {X0};

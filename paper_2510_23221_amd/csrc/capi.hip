@@ -36,6 +36,14 @@ size_t device_max_lds()
     return static_cast<size_t>(v);
 }
 
+int device_cu_count()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) return 256;
+    return v;
+}
+
 CoeffLayout coeff_layout(int64_t n)
 {
     CoeffLayout L{};

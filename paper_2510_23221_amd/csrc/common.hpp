@@ -119,6 +119,9 @@ bko_status hip_fail(hipError_t e, const char *what);
 // LDS bytes one workgroup may allocate on the current device.
 size_t device_max_lds();
 
+// Compute units of the current device.
+int device_cu_count();
+
 #define BKO_HIP(call)                                                   \
     do {                                                                \
         hipError_t e_ = (call);                                         \

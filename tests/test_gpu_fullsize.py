@@ -271,11 +271,12 @@ def test_config4_bf16_stages_sampled(dev):
 
 @pytest.mark.parametrize("s,nz", [(48, 8), (40, 12)])
 def test_wide_solve_several_tiles_per_workgroup(dev, s, nz):
-    """FP32 block solves whose chips have more 256-row tiles than the chip's
-    workgroup cap (1820 at s = 48, 2621 at s = 40), so that workgroups walk
-    more than one tile and the D/Q/P update's register ring prefetches across
-    tiles; s = 40 also leaves the last column block ragged.  Residuals by the
-    oracle's SpMV."""
+    """FP32 block solves whose chips have more 256-row tiles than any
+    single-chip grid takes (two workgroups per compute unit, and never more
+    than the partial cap of 1820 at s = 48 or 2621 at s = 40), so that
+    workgroups walk several tiles and the register rings of the s > 32
+    updates prefetch across tiles; s = 40 also leaves the last column block
+    ragged.  Residuals by the oracle's SpMV."""
     rng = np.random.default_rng(300 + s)
     chip = synth.chip_stack(rng, 256, 256, nz)
     A = oracle.assemble_chip(chip)
