@@ -51,11 +51,11 @@ TRAFFIC_BYTES = {
     ("stack-128x128x8-s32-m5000", "spmm", "", "f32"): 41.8e6,
     ("stack-128x128x8-s32-m5000", "apply", "", "f32"): 11181.7e6,
     ("stack-128x128x8-s32-m5000", "combine", "", "f32"): 5409.0e6,
-    ("stack-256x256x16-s64-m20000", "update_dqp", "", "f32"): 1344.1e6,
-    ("stack-256x256x16-s64-m20000", "update_w", "", "f32"): 837.6e6,
-    ("stack-256x256x16-s64-m20000", "spmm", "", "f32"): 887.1e6,
-    ("stack-256x256x16-s64-m20000", "apply", "", "f32"): 95428.8e6,
-    ("stack-256x256x16-s64-m20000", "combine", "", "f32"): 43403.8e6,
+    ("stack-256x256x16-s64-m20000", "update_dqp", "", "f32"): 1343.3e6,
+    ("stack-256x256x16-s64-m20000", "update_w", "", "f32"): 820.3e6,
+    ("stack-256x256x16-s64-m20000", "spmm", "", "f32"): 841.2e6,
+    ("stack-256x256x16-s64-m20000", "apply", "", "f32"): 95631.6e6,
+    ("stack-256x256x16-s64-m20000", "combine", "", "f32"): 43402.9e6,
 }
 
 # one launch in this many of the dominant block-solve kernel carries events
