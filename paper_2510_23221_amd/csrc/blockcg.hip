@@ -145,9 +145,16 @@ struct SmallG {
     }
 };
 
-// Chip of this workgroup and the workgroup's index within the chip.
+// Chip of this workgroup and the workgroup's index within the chip.  A
+// layout of one chip passes no table (one dependent load fewer at the start
+// of every row kernel).
+__device__ inline int chip_index(const uint16_t *tab) { return tab ? tab[blockIdx.x] : 0; }
 __device__ inline const ChipDev &chip_of(const ChipDev *cds, const uint16_t *tab, int &local)
 {
+    if (!tab) {
+        local = static_cast<int>(blockIdx.x);
+        return cds[0];
+    }
     const ChipDev &cd = cds[tab[blockIdx.x]];
     local = static_cast<int>(blockIdx.x) - cd.wg_base;
     return cd;
@@ -1712,7 +1719,9 @@ __global__ __launch_bounds__(kThreads) void update_w_fused_kernel(const ChipDev 
     int local;
     const ChipDev &cd = chip_of(cds, tab, local);
     const int wgs = cd.wgs;
-    if (glb(cd.ctrl)[kConverged]) return;
+    // the control word is tested after the Gram and the small matrices are
+    // requested, so that their loads overlap its latency
+    const int stop = glb(cd.ctrl)[kConverged];
     using V = typename MF<T>::V;
     constexpr bool kF64 = MF<T>::kF64;
     constexpr int KS = 4 * NB;
@@ -1766,6 +1775,7 @@ __global__ __launch_bounds__(kThreads) void update_w_fused_kernel(const ChipDev 
     small_fetch<T, SP, MST>(glb(f64 ? reinterpret_cast<const T *>(cd.sm.M3) : reinterpret_cast<const T *>(cd.sm.M3f)),
                             s, mv);
     if (local == 0) gram_fetch(sm.C, s, cv);
+    if (stop) return;
     const bool first = local < ntiles;
     small_stash<T, SP, MST>(M3s, mv, false);
     for (int e = threadIdx.x; e < SP * MST; e += kThreads) M2s[e] = T(0);
@@ -1863,7 +1873,9 @@ __global__ __launch_bounds__(kThreads) void update_dqp_fused_kernel(const ChipDe
     const ChipDev &cd = chip_of(cds, tab, local);
     const int wgs = cd.wgs;
     const gptr<int> ctrl = glb(cd.ctrl);
-    if (ctrl[kStop]) return;
+    // the control word is tested after the Gram and the small matrices are
+    // requested, so that their loads overlap its latency
+    const int stop = ctrl[kStop];
     using V = typename MF<T>::V;
     constexpr bool kF64 = MF<T>::kF64;
     constexpr int KS = 4 * NB;
@@ -1934,6 +1946,7 @@ __global__ __launch_bounds__(kThreads) void update_dqp_fused_kernel(const ChipDe
         gram_fetch(sm.C, s, cv);
         iters = ctrl[kIters];
     }
+    if (stop) return;
     const bool first = local < ntiles;
     small_stash<T, SP, MST>(M1, mv, false);
     gram_stash(gv, s, fs);
@@ -2260,7 +2273,7 @@ __global__ __launch_bounds__(kThreads) void scale_cols_kernel(const ChipDev *__r
     const ChipDev &cd = chip_of(cds, tab, local);
     const int wgs = cd.wgs;
     if (!cd.X0) return;
-    const double *al = alpha + static_cast<size_t>(tab[blockIdx.x]) * kMaxS;
+    const double *al = alpha + static_cast<size_t>(chip_index(tab)) * kMaxS;
     const int64_t ntiles = cd.ldw / kTileRows;
     for (int64_t tile = local; tile < ntiles; tile += wgs) {
         const int64_t a = tile * kTileRows + threadIdx.x;
@@ -2703,7 +2716,8 @@ bko_status batch_solve_t(const Layout &L, void *work, const double *const *B, co
     std::vector<int> ctrlh(static_cast<size_t>(kCtrlInts) * nc, 0);
     std::vector<double> thh(static_cast<size_t>(kMaxS) * nc, 0.0), nh(static_cast<size_t>(kMaxS) * nc, 0.0),
         sh(static_cast<size_t>(kMaxS) * nc, 0.0);
-    Ctx x{&L, reinterpret_cast<const ChipDev *>(base + L.off_cds), reinterpret_cast<const uint16_t *>(base + L.off_tab), st};
+    Ctx x{&L, reinterpret_cast<const ChipDev *>(base + L.off_cds),
+          L.nchips == 1 ? nullptr : reinterpret_cast<const uint16_t *>(base + L.off_tab), st};
     int *ctrl_d = reinterpret_cast<int *>(base + L.off_ctrl);
     double *th_d = reinterpret_cast<double *>(base + L.off_th);
     double *norms_d = reinterpret_cast<double *>(base + L.off_norms);
@@ -3006,7 +3020,8 @@ bko_status time_granularity(const BatchPlan &p, int tpw, void *work, hipStream_t
     const std::vector<uint16_t> tabh = wg_table(L);
     BKO_HIP(hipMemcpyAsync(base + L.off_cds, recs.data(), sizeof(ChipDev) * nc, hipMemcpyHostToDevice, st));
     BKO_HIP(hipMemcpyAsync(base + L.off_tab, tabh.data(), sizeof(uint16_t) * tabh.size(), hipMemcpyHostToDevice, st));
-    Ctx x{&L, reinterpret_cast<const ChipDev *>(base + L.off_cds), reinterpret_cast<const uint16_t *>(base + L.off_tab), st};
+    Ctx x{&L, reinterpret_cast<const ChipDev *>(base + L.off_cds),
+          L.nchips == 1 ? nullptr : reinterpret_cast<const uint16_t *>(base + L.off_tab), st};
     int biggest = 0;
     for (int c = 1; c < nc; ++c)
         if (L.chips[c].tiles > L.chips[biggest].tiles) biggest = c;
