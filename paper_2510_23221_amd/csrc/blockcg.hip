@@ -654,9 +654,9 @@ __global__ __launch_bounds__(kSpThreads, (NB > 2 ? 2 : 1)) void spmm_gram_vec_ke
 __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(const ChipDev *__restrict__ cds, int ss)
 {
     const ChipDev &cd = cds[blockIdx.y];
-    if (glb(cd.ctrl)[kConverged]) return;
     const gptr<const double> __restrict__ parts = glb(static_cast<const double *>(cd.parts));
     const int nparts = cd.wgs;
+    const gptr<const int> ctrl = glb(cd.ctrl);
     __shared__ double sh[kThreads];
     const int per = (ss + gridDim.x - 1) / gridDim.x;  // entries of this workgroup (<= 64)
     const int slices = kThreads / per;
@@ -664,6 +664,14 @@ __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(const ChipDev *__
     const int le = tid % per, sl = tid / per;
     const int e = blockIdx.x * per + le;
     double a = 0.0;
+    // the control word is tested after the partials are summed, so that its
+    // latency overlaps their loads (a converged chip's reduction reads them
+    // for nothing and writes nothing); read with a vector load (the empty asm
+    // hides that the offset is uniform), so that waiting for the chip's
+    // pointers does not wait for it too
+    int zo = 0;
+    asm volatile("" : "+v"(zo));
+    const int stop = ctrl[kConverged + zo];
     if (sl < slices && e < ss) {
         // slice sl sums partials sl, sl + slices, ... ; 8 loads in flight
         for (int p0 = sl; p0 < nparts; p0 += 8 * slices) {
@@ -677,6 +685,7 @@ __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(const ChipDev *__
             for (int q = 0; q < 8; ++q) a += v[q];
         }
     }
+    if (stop) return;
     sh[tid] = a;
     __syncthreads();
     if (sl == 0 && e < ss) {
